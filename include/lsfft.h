@@ -1,0 +1,163 @@
+/*
+ * lsfft — Green-function-preconditioned (Lippmann-Schwinger) fixed-point solver
+ * for periodic linear-elastic unit cells on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only; no C++ or framework types cross it.
+ *
+ * The method (Khorrami, Mianroodi, Shanthraj, Svendsen, "Development and
+ * comparison of spectral algorithms for numerical modeling of the
+ * quasi-static mechanical behavior of inhomogeneous materials"):
+ *   given the grid n1 x n2 x n3, per-voxel isotropic moduli lambda(x), mu(x),
+ *   a reference medium C_H = (lambda0, mu0) and a macroscopic strain Ebar,
+ *   iterate (strain form of the 3D TD algorithm of Sec. 5.2, identical iterates
+ *   to its displacement form):
+ *       sigma^k   = C(x) : eps^k                           (Hooke, Sec. 5.1)
+ *       r_k       = |sigma_hat q^b| / |sigma_hat(0)|       (stopping test)
+ *       eps^{k+1} = eps^k + IDFT( Gamma_H(q) DFT(sigma^k) ) (Green step, eq. (34), (48))
+ *   with eps^0 = Ebar.  The scheme selects the wavevector q:
+ *       BASIC  plain Fourier wavevector (the "F" choice),
+ *       FB     forward-difference gradient with the conjugate divergence,
+ *       AFB    averaged forward / half-central pair (AFD, AhC) of Sec. 5.3,
+ *              equal to Willot's rotated scheme,
+ *       DGO    the discrete Green operator of Sec. 5.4 (PCD only), iterated in
+ *              polarisation form eps^{k+1} = Ebar + IDFT(Gamma^c DFT((C - C_H) eps^k)).
+ *
+ * Field layout (every real field, host or device): components major, then
+ * x3, x2, x1 with x1 fastest:  index = c*N + (i3*n2 + i2)*n1 + i1,
+ * N = n1*n2*n3.  Tensor fields have 6 components in Voigt order
+ * (11, 22, 33, 23, 13, 12) holding TENSOR components (E_12, not 2 E_12).
+ *
+ * Half-spectrum layout used by the operator entry points: components major,
+ * then k3, k2, k1 with k1 fastest, k1 in [0, n1/2], k2 in [0, n2), k3 in
+ * [0, n3) (standard FFT order; index j is the wavenumber j for j < n/2 and
+ * j - n otherwise, so the Nyquist index n/2 is the paper's kappa = -n/2):
+ *   index = c*(n3*n2*(n1/2+1)) + (k3*n2 + k2)*(n1/2+1) + k1,
+ * complex values as interleaved (re, im) pairs of the solver's precision.
+ * Transforms are unnormalised forward DFTs, exp(-i k.x).
+ *
+ * Error behaviour: every entry point returns an lsfft_status.  Negative
+ * values mean nothing was computed and no output was written; positive
+ * values mean outputs were written but the iteration did not converge
+ * (LSFFT_ENOTCONV) or diverged (LSFFT_EDIVERGED).  A solver handle is not
+ * thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef LSFFT_H
+#define LSFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsfft_solver_s *lsfft_solver;
+
+/* Discretisation: trapezoidal (nodes) or piecewise-constant (cell centres),
+ * Sec. 3.1 / 3.2.  For BASIC, FB and AFB both give identical iterates on
+ * per-voxel data (the PCD algorithm differs only in where C is sampled); the
+ * flag is recorded and gates DGO, which is defined for PCD only. */
+typedef enum { LSFFT_TD = 0, LSFFT_PCD = 1 } lsfft_disc;
+
+typedef enum { LSFFT_BASIC = 0, LSFFT_FB = 1, LSFFT_AFB = 2, LSFFT_DGO = 3 } lsfft_scheme;
+
+/* F64: all arithmetic in FP64.  F32: fields, FFTs and the Green step in FP32;
+ * the residual, mean stress and convergence reductions in FP64. */
+typedef enum { LSFFT_F64 = 0, LSFFT_F32 = 1 } lsfft_prec;
+
+typedef enum {
+  LSFFT_OK = 0,          /* converged: r <= tol                              */
+  LSFFT_ENOTCONV = 1,    /* maxit reached; outputs hold the last iterate      */
+  LSFFT_EDIVERGED = 2,   /* residual non-finite or > 1e6 x the first residual */
+  LSFFT_EINVAL = -1,     /* invalid argument; nothing computed                */
+  LSFFT_ENOMEM = -2,     /* device allocation failed                          */
+  LSFFT_EDEVICE = -3     /* HIP runtime error                                 */
+} lsfft_status;
+
+typedef struct {
+  int32_t n[3];            /* n1 (fastest), n2, n3: each even, 2^a 3^b, 4..512  */
+  double h[3];             /* grid spacing per axis; 0 means 1.0               */
+  const double *lambda;    /* N Lame lambda values, HOST memory, field layout  */
+  const double *mu;        /* N shear moduli mu, HOST memory, field layout     */
+  double lambda0, mu0;     /* reference medium C_H (isotropic)                 */
+  int32_t disc;            /* lsfft_disc                                       */
+  int32_t scheme;          /* lsfft_scheme                                     */
+  int32_t prec;            /* lsfft_prec                                       */
+  int32_t dgo_images;      /* DGO only: image window M >= 0 (nu in [-M, M], and
+                              [-M, M+1] at a Nyquist index)                     */
+  int32_t dgo_weight_power;/* DGO only: 1 = the single sinc weight as printed,
+                              2 = squared sinc weight                          */
+  void *stream;            /* hipStream_t for all work; NULL = default stream   */
+} lsfft_config;
+
+/* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda
+ * and mu to the device (the caller may free them on return), builds the
+ * per-axis wavevector tables and, for DGO, the discrete Green operator
+ * table (Sec. 5.4).  EINVAL: NULL pointers, unsupported n, h < 0, any
+ * mu <= 0 or 3 lambda + 2 mu <= 0 (not positive definite), the same for
+ * C_H, non-finite moduli, DGO with TD, dgo_images < 0 or > 64, a weight
+ * power other than 1 or 2, unknown enum values.  On success *out owns
+ * device memory until lsfft_destroy. */
+lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out);
+
+/* Solve for macroscopic strain Ebar[6] (Voigt tensor components).  Stops at
+ * the first k with r_k <= tol (returns LSFFT_OK) or at k = maxit
+ * (LSFFT_ENOTCONV).  r_k is the relative equilibrium norm
+ * sqrt(sum_xi |sigma_hat(xi) q^b(xi)|^2) / |sigma_hat(0)|_F evaluated before
+ * the k-th update (BASIC, FB, AFB), or |eps^k - eps^{k-1}| / (sqrt(N)|Ebar|_F)
+ * (DGO).  Outputs: eps and sig (6N doubles, HOST memory, field layout; either
+ * may be NULL), sig_mean[6] = <sigma> (may be NULL), *iters = k (number of
+ * updates applied), *residual = r_k (either may be NULL).  tol >= 0,
+ * maxit >= 0.  tol = 0 runs exactly maxit iterations. */
+lsfft_status lsfft_solve(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit,
+                         double *eps, double *sig, double sig_mean[6], int32_t *iters,
+                         double *residual);
+
+/* Same as lsfft_solve with DEVICE output pointers of the solver's precision
+ * (float for F32, double for F64), 6N elements each, field layout; either may
+ * be NULL.  No host copies of fields are made. */
+lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit,
+                                void *eps_dev, void *sig_dev, double sig_mean[6],
+                                int32_t *iters, double *residual);
+
+/* Residual history r_0..r_iters of the last solve, copied to HOST out[0..cap);
+ * *count receives iters + 1.  EINVAL if no solve has run. */
+lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count);
+
+/* Operator: sig_hat = DFT(C : eps) for a DEVICE strain field eps_dev (6N,
+ * solver precision, field layout) into DEVICE sig_hat_dev (half-spectrum
+ * layout, 6*n3*n2*(n1/2+1) complex).  For DGO the polarisation
+ * (C - C_H) : eps is transformed instead.  Sec. 5.2, the steps
+ * "T = C E; T_check = F^- T". */
+lsfft_status lsfft_stress_spectrum(lsfft_solver s, const void *eps_dev, void *sig_hat_dev);
+
+/* Operator: the Green step on a DEVICE half spectrum (layout above):
+ * out = -Gamma_0(q) in (BASIC, FB, AFB: the strain increment of eq. (34),
+ * zero at xi = 0 and at singular frequencies) or out = Gamma^c in (DGO, the
+ * paper's sign), unnormalised.  in must be the transform of a real field.
+ * *res_sq (may be NULL) receives sum over the FULL spectrum of
+ * |in(xi) q^b(xi)|^2 (BASIC, FB, AFB; 0 for DGO).  in and out may alias. */
+lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev, double *res_sq);
+
+/* Per-kernel event timing for benchmarking.  lsfft_set_timing(s, id) makes
+ * every later solve record HIP events around each launch of kernel `id`
+ * (0 = x-pass, 1 = forward y-pass, 2 = z-pass + Green, 3 = inverse y-pass,
+ * 4 = packed kx = 0 / Nyquist planes, 5 = reduction; -1 = off).
+ * lsfft_get_timing returns the mean duration in ms and the launch count
+ * of the last timed solve. */
+lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id);
+lsfft_status lsfft_get_timing(lsfft_solver s, double *mean_ms, int32_t *launches);
+const char *lsfft_kernel_name(int32_t kernel_id);
+
+/* Release all device memory of the solver.  lsfft_destroy(NULL) is a no-op. */
+lsfft_status lsfft_destroy(lsfft_solver s);
+
+/* Static string for a status code. */
+const char *lsfft_status_string(lsfft_status st);
+
+/* Library version string. */
+const char *lsfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSFFT_H */

@@ -1,0 +1,188 @@
+// Device-side building blocks: complex arithmetic and an in-workgroup
+// Stockham FFT of one pencil whose L points are spread over L/E threads,
+// E points per thread, exchanged through LDS between radix passes.
+//
+// Data distribution (input AND output, both directions): the thread with
+// pencil-local index t holds points  m = t + (L/E) * e,  e = 0..E-1,  in v[e].
+// So a pencil can be loaded, transformed, processed point-wise and stored
+// back without any reordering.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lsfft {
+
+template <typename T> struct cplx {
+  T x, y;
+};
+
+template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { return cplx<T>{a, b}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> conjg(cplx<T> a) { return {a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool FWD> __device__ __forceinline__ cplx<T> rot(cplx<T> a) {
+  return FWD ? cplx<T>{a.y, -a.x} : cplx<T>{-a.y, a.x};
+}
+template <typename T> __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { return {-a.y, a.x}; }
+template <typename T> __device__ __forceinline__ T norm2(cplx<T> a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------- radix plans
+// Passes use radices from {8, 4, 3, 2}, greedily the largest that divides both
+// the remaining length and E (each thread then runs E/R butterflies per pass).
+template <int L, int E> struct Plan {
+  static constexpr int pick(int rem) {
+    return (rem % 8 == 0 && E % 8 == 0) ? 8
+         : (rem % 4 == 0 && E % 4 == 0) ? 4
+         : (rem % 3 == 0 && E % 3 == 0) ? 3
+         : (rem % 2 == 0 && E % 2 == 0) ? 2 : 0;
+  }
+  static constexpr int npass() {
+    int rem = L, n = 0;
+    while (rem > 1) {
+      int r = pick(rem);
+      if (r == 0) return -1;
+      rem /= r;
+      ++n;
+    }
+    return n;
+  }
+  static constexpr int radix(int p) {
+    int rem = L, r = 1;
+    for (int i = 0; i <= p; ++i) { r = pick(rem); rem /= r; }
+    return r;
+  }
+  static constexpr int stride(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= radix(i);
+    return s;
+  }
+  static_assert(L % E == 0, "E must divide L");
+  static_assert(npass() > 0 || L == 1, "length not factorable with radices dividing E");
+};
+
+// ---------------------------------------------------------------- butterflies
+// In-place DFT of R points, sign exp(-2 pi i / R) when FWD.
+template <typename T, bool FWD> __device__ __forceinline__ void bfly2(cplx<T> *a) {
+  cplx<T> t = a[0];
+  a[0] = t + a[1];
+  a[1] = t - a[1];
+}
+
+template <typename T, bool FWD> __device__ __forceinline__ void bfly3(cplx<T> *a) {
+  const T c = T(-0.5);
+  const T s = T(0.86602540378443864676372317075293618);  // sin(2 pi / 3)
+  cplx<T> sum = a[1] + a[2], dif = a[1] - a[2];
+  cplx<T> m = a[0] + c * sum;
+  a[0] = a[0] + sum;
+  cplx<T> r = s * rot<T, FWD>(dif);  // -i s (a1 - a2) forward
+  a[1] = m + r;
+  a[2] = m - r;
+}
+
+template <typename T, bool FWD> __device__ __forceinline__ void bfly4(cplx<T> *a) {
+  cplx<T> t0 = a[0] + a[2], t1 = a[0] - a[2];
+  cplx<T> t2 = a[1] + a[3], t3 = rot<T, FWD>(a[1] - a[3]);
+  a[0] = t0 + t2;
+  a[2] = t0 - t2;
+  a[1] = t1 + t3;
+  a[3] = t1 - t3;
+}
+
+template <typename T, bool FWD> __device__ __forceinline__ void bfly8(cplx<T> *a) {
+  const T h = T(0.70710678118654752440084436210484904);  // sqrt(1/2)
+  cplx<T> e[4] = {a[0], a[2], a[4], a[6]};
+  cplx<T> o[4] = {a[1], a[3], a[5], a[7]};
+  bfly4<T, FWD>(e);
+  bfly4<T, FWD>(o);
+  // twiddles W8^k, k = 1, 2, 3 (conjugated for the inverse)
+  cplx<T> o1 = FWD ? cplx<T>{h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)}
+                   : cplx<T>{h * (o[1].x - o[1].y), h * (o[1].y + o[1].x)};
+  cplx<T> o2 = rot<T, FWD>(o[2]);
+  cplx<T> o3 = FWD ? cplx<T>{h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)}
+                   : cplx<T>{-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y)};
+  a[0] = e[0] + o[0];
+  a[4] = e[0] - o[0];
+  a[1] = e[1] + o1;
+  a[5] = e[1] - o1;
+  a[2] = e[2] + o2;
+  a[6] = e[2] - o2;
+  a[3] = e[3] + o3;
+  a[7] = e[3] - o3;
+}
+
+template <typename T, bool FWD, int R> __device__ __forceinline__ void bfly(cplx<T> *a) {
+  if constexpr (R == 2) bfly2<T, FWD>(a);
+  else if constexpr (R == 3) bfly3<T, FWD>(a);
+  else if constexpr (R == 4) bfly4<T, FWD>(a);
+  else if constexpr (R == 8) bfly8<T, FWD>(a);
+}
+
+// ---------------------------------------------------------------- Stockham pass
+// tw: table of exp(-2 pi i m / L) at tw[m * ts], m = 0..L-1.
+// lds: this pencil's scratch, point m at lds[m * ms].
+// Barrier protocol: every exchange is  barrier; write; barrier; read,  so the
+// scratch may be reused by consecutive transforms without extra barriers.
+template <typename T, int L, int E, bool FWD, int P>
+struct StockhamPass {
+  __device__ __forceinline__ static void run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
+                                             const cplx<T> *__restrict__ tw, int ts) {
+    using PL = Plan<L, E>;
+    constexpr int NP = PL::npass();
+    constexpr int R = PL::radix(P);
+    constexpr int Ns = PL::stride(P);
+    constexpr int NB = E / R;
+    constexpr int TPC = L / E;
+    constexpr bool LAST = (P + 1 == NP);
+    cplx<T> out[E];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + TPC * b;
+      cplx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[b + r * NB];
+      const int k = (Ns > 1) ? (j % Ns) : 0;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cplx<T> w = tw[(k * r * (L / (Ns * R))) * ts];
+          if (!FWD) w.y = -w.y;
+          a[r] = a[r] * w;
+        }
+      }
+      bfly<T, FWD, R>(a);
+      if (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[b + r * NB] = a[r];
+      } else {
+        if (b == 0) __syncthreads();
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ms] = a[r];
+      }
+    }
+    if constexpr (LAST) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = out[e];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = lds[(t + TPC * e) * ms];
+      StockhamPass<T, L, E, FWD, P + 1>::run(v, t, lds, ms, tw, ts);
+    }
+  }
+};
+
+template <typename T, int L, int E, bool FWD>
+__device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
+                                           const cplx<T> *__restrict__ tw, int ts) {
+  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0>::run(v, t, lds, ms, tw, ts);
+}
+
+// Number of LDS exchanges the transform performs (passes - 1).
+template <int L, int E> constexpr int fft_exchanges() { return Plan<L, E>::npass() - 1; }
+
+}  // namespace lsfft

@@ -1,0 +1,728 @@
+// Kernels of one fixed-point iteration (strain form of the 3D TD / PCD
+// algorithms of Sec. 5.2 / 5.4 and of the DGO algorithm of Sec. 5.4):
+//
+//   k_xpass  x-lines: inverse real transform of the strain increment,
+//            strain update, Hooke (Sec. 5.1), forward real transform of the
+//            stress; FP64 block sums of <sigma> (and of |eps_new - eps_old|^2).
+//   k_ypass  y-pencils: batched complex transform (forward or inverse).
+//   k_zpass  z-pencils of all six components: forward transform, Green step
+//            (green.hpp), FP64 block sums of the equilibrium residual,
+//            inverse transform.
+//   k_reduce single workgroup: fixed-order FP64 reduction of the block sums,
+//            convergence / divergence decision, device-side stop flag.
+//
+// Spectrum storage: for component c, kx in [0, n1/2) in
+//   main[c][k3][k2][kx]   (rows of n1/2 complex, aligned)
+// and the x-Nyquist plane kx = n1/2 in
+//   nyq[c][k3][k2].
+// Every kernel returns at once when the stop flag is set, so iterations may
+// be enqueued ahead of the host's convergence check.
+#pragma once
+#include "fft.hpp"
+#include "green.hpp"
+
+namespace lsfft {
+
+struct Dims {
+  int n1, n2, n3, L;
+  long long N, rows, comp_main, comp_nyq;
+};
+
+struct State {
+  int done;
+  int status;
+  int iters;
+  int pad;
+  double r0;
+  double r;
+  double sig_mean[6];
+};
+
+enum { XMODE_INIT = 0, XMODE_UPDATE = 1, XMODE_DGO = 2, XMODE_EXTERNAL = 3 };
+
+template <typename T> struct XArgs {
+  Dims d;
+  T *eps;
+  const T *eps_in;   // XMODE_EXTERNAL: strain to transform (not updated)
+  const T *lam;
+  const T *mu;
+  cplx<T> *spec;
+  cplx<T> *nyq;
+  const cplx<T> *tw;  // exp(-2 pi i m / n1), m = 0..n1-1
+  T Eb[6];
+  T lam0, mu0;
+  double *partial;    // [gridDim.x][8]
+  const State *st;
+  int mode;
+  int polarisation;   // transform (C - C0) : eps instead of C : eps
+};
+
+template <typename T> __device__ __forceinline__ void ld2(const T *p, T &a, T &b);
+template <> __device__ __forceinline__ void ld2<float>(const float *p, float &a, float &b) {
+  float2 v = *reinterpret_cast<const float2 *>(p);
+  a = v.x;
+  b = v.y;
+}
+template <> __device__ __forceinline__ void ld2<double>(const double *p, double &a, double &b) {
+  double2 v = *reinterpret_cast<const double2 *>(p);
+  a = v.x;
+  b = v.y;
+}
+template <typename T> __device__ __forceinline__ void st2(T *p, T a, T b);
+template <> __device__ __forceinline__ void st2<float>(float *p, float a, float b) {
+  *reinterpret_cast<float2 *>(p) = make_float2(a, b);
+}
+template <> __device__ __forceinline__ void st2<double>(double *p, double a, double b) {
+  *reinterpret_cast<double2 *>(p) = make_double2(a, b);
+}
+
+template <typename T> __device__ __forceinline__ T shfl(T v, int lane) { return __shfl(v, lane, 64); }
+
+// Partner value X[(L - k) mod L] for every point k = t + TPC e held by this
+// thread.  The partner of thread t is thread (TPC - t) mod TPC of the same
+// pencil (same wavefront); it holds the partner point in slot E-1-e, or in
+// slot (E-e) mod E when t = 0 (the pencil's own thread).
+template <typename T, int E, int TPC>
+__device__ __forceinline__ void partner(const cplx<T> (&v)[E], cplx<T> (&pv)[E], int t, int lane) {
+  const int plane = lane - t + ((TPC - t) % TPC);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cplx<T> send = v[E - 1 - e];
+    cplx<T> got;
+    if constexpr (TPC > 1) {
+      got.x = shfl(send.x, plane);
+      got.y = shfl(send.y, plane);
+    } else {
+      got = send;
+    }
+    pv[e] = (t == 0) ? v[(E - e) % E] : got;
+  }
+}
+
+// Inverse real transform of one x-line.  In: v[e] = X[k], k = t + TPC e,
+// k in [0, L), and xn = X[L] (meaningful in thread t = 0).  Out: v[e] =
+// (x[2m], x[2m+1]) for m = t + TPC e: the unnormalised inverse real DFT of
+// length 2L, via one complex inverse transform of length L.
+template <typename T, int L, int E>
+__device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int lane, cplx<T> *lds,
+                                         const cplx<T> *__restrict__ tw) {
+  constexpr int TPC = L / E;
+  cplx<T> pv[E];
+  partner<T, E, TPC>(v, pv, t, lane);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TPC * e;
+    if (k == 0) {
+      const T a = v[e].x, b = xn.x;  // X[0] and X[L] are real for a real line
+      v[e] = cplx<T>{a + b, a - b};
+    } else {
+      const cplx<T> xp = conjg(pv[e]);
+      const cplx<T> w = conjg(tw[k]);  // exp(+2 pi i k / (2L))
+      v[e] = (v[e] + xp) + mul_i(w * (v[e] - xp));
+    }
+  }
+  fft_pencil<T, L, E, false>(v, t, lds, 1, tw, 2);
+}
+
+// Forward real transform of one x-line.  In: v[e] = (x[2m], x[2m+1]).
+// Out: v[e] = X[k] for k = t + TPC e in [0, L), and the return value X[L]
+// (in thread t = 0).
+template <typename T, int L, int E>
+__device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cplx<T> *lds,
+                                            const cplx<T> *__restrict__ tw) {
+  constexpr int TPC = L / E;
+  fft_pencil<T, L, E, true>(v, t, lds, 1, tw, 2);
+  cplx<T> pv[E];
+  partner<T, E, TPC>(v, pv, t, lane);
+  cplx<T> xn{T(0), T(0)};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TPC * e;
+    const cplx<T> z = v[e];
+    if (k == 0) {
+      v[e] = cplx<T>{z.x + z.y, T(0)};
+      xn = cplx<T>{z.x - z.y, T(0)};
+    } else {
+      const cplx<T> zp = conjg(pv[e]);
+      const cplx<T> fe = T(0.5) * (z + zp);
+      const cplx<T> d = T(0.5) * (z - zp);
+      const cplx<T> fo = cplx<T>{d.y, -d.x};  // (z - zp) / (2i)
+      v[e] = fe + tw[k] * fo;
+    }
+  }
+  return xn;
+}
+
+template <int WG> __device__ __forceinline__ void block_sum(double *vals, int nv, double *red) {
+  // fixed-order reduction: per-wavefront butterfly, then wavefronts in order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = (WG + 63) / 64;
+  for (int i = 0; i < nv; ++i) {
+    double x = vals[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[wave * 8 + i] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < nv; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w * 8 + i];
+      vals[i] = s;
+    }
+  }
+}
+
+// One workgroup = P x-lines of L complex points (TPC = L/E threads each).
+template <typename T, int L, int E, int WG>
+__global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int TPC = L / E;
+  constexpr int P = WG / TPC;
+  static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
+  __shared__ cplx<T> lds[P * L];
+  __shared__ double red[(WG + 63) / 64 * 8];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int p = tid / TPC, t = tid % TPC;
+  const long long row = (long long)blockIdx.x * P + p;
+  const bool valid = row < a.d.rows;
+  const int n1 = 2 * L;
+  const long long N = a.d.N;
+  cplx<T> *sl = lds + p * L;
+  const bool need_delta = (a.mode == XMODE_UPDATE || a.mode == XMODE_DGO);
+  const bool need_old = (a.mode == XMODE_UPDATE || a.mode == XMODE_DGO);
+  const bool write_eps = (a.mode != XMODE_EXTERNAL);
+
+  T lam[E][2], mu[E][2];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const long long idx = row * n1 + 2 * (t + TPC * e);
+    if (valid) {
+      ld2(a.lam + idx, lam[e][0], lam[e][1]);
+      ld2(a.mu + idx, mu[e][0], mu[e][1]);
+    } else {
+      lam[e][0] = lam[e][1] = mu[e][0] = mu[e][1] = T(0);
+    }
+  }
+  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // ------------------------------------------------ normal components 11, 22, 33
+  {
+    cplx<T> w[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (need_delta) {
+        const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
+        cplx<T> xn{T(0), T(0)};
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[c][e] = valid ? src[t + TPC * e] : cplx<T>{T(0), T(0)};
+        if (valid && t == 0) xn = a.nyq[(long long)c * a.d.rows + row];
+        c2r_line<T, L, E>(w[c], xn, t, lane, sl, a.tw);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[c][e] = cplx<T>{T(0), T(0)};
+      }
+    }
+    // strain update and Hooke, two voxels (2m, 2m+1) per point
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = row * n1 + 2 * (t + TPC * e);
+      T ev[3][2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T o0 = T(0), o1 = T(0);
+        if (valid && (need_old || a.mode == XMODE_EXTERNAL)) {
+          ld2((a.mode == XMODE_EXTERNAL ? a.eps_in : a.eps) + c * N + idx, o0, o1);
+        }
+        T n0, n1v;
+        if (a.mode == XMODE_UPDATE) {
+          n0 = o0 + w[c][e].x;
+          n1v = o1 + w[c][e].y;
+        } else if (a.mode == XMODE_DGO) {
+          n0 = a.Eb[c] + w[c][e].x;
+          n1v = a.Eb[c] + w[c][e].y;
+        } else if (a.mode == XMODE_INIT) {
+          n0 = a.Eb[c];
+          n1v = a.Eb[c];
+        } else {
+          n0 = o0;
+          n1v = o1;
+        }
+        if (a.mode == XMODE_DGO && valid) {
+          const double d0 = (double)n0 - (double)o0, d1 = (double)n1v - (double)o1;
+          sums[6] += d0 * d0 + d1 * d1;
+        }
+        if (valid && write_eps) st2(a.eps + c * N + idx, n0, n1v);
+        ev[c][0] = n0;
+        ev[c][1] = n1v;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T tr = ev[0][h] + ev[1][h] + ev[2][h];
+        const T l = lam[e][h], m2 = T(2) * mu[e][h];
+        const T lp = a.polarisation ? l - a.lam0 : l;
+        const T mp2 = a.polarisation ? m2 - T(2) * a.mu0 : m2;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T sg = l * tr + m2 * ev[c][h];
+          if (valid) sums[c] += (double)sg;
+          const T fin = a.polarisation ? lp * tr + mp2 * ev[c][h] : sg;
+          if (h == 0) w[c][e].x = fin; else w[c][e].y = fin;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cplx<T> xn = r2c_line<T, L, E>(w[c], t, lane, sl, a.tw);
+      if (valid) {
+        cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[c][e];
+        if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xn;
+      }
+    }
+  }
+
+  // ------------------------------------------------ shear components 23, 13, 12
+#pragma unroll 1
+  for (int c = 3; c < 6; ++c) {
+    cplx<T> w[E];
+    if (need_delta) {
+      const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
+      cplx<T> xn{T(0), T(0)};
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[e] = valid ? src[t + TPC * e] : cplx<T>{T(0), T(0)};
+      if (valid && t == 0) xn = a.nyq[(long long)c * a.d.rows + row];
+      c2r_line<T, L, E>(w, xn, t, lane, sl, a.tw);
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[e] = cplx<T>{T(0), T(0)};
+    }
+    const T Ebc = a.Eb[c];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = row * n1 + 2 * (t + TPC * e);
+      T o0 = T(0), o1 = T(0);
+      if (valid && (need_old || a.mode == XMODE_EXTERNAL))
+        ld2((a.mode == XMODE_EXTERNAL ? a.eps_in : a.eps) + c * N + idx, o0, o1);
+      T n0, n1v;
+      if (a.mode == XMODE_UPDATE) {
+        n0 = o0 + w[e].x;
+        n1v = o1 + w[e].y;
+      } else if (a.mode == XMODE_DGO) {
+        n0 = Ebc + w[e].x;
+        n1v = Ebc + w[e].y;
+      } else if (a.mode == XMODE_INIT) {
+        n0 = Ebc;
+        n1v = Ebc;
+      } else {
+        n0 = o0;
+        n1v = o1;
+      }
+      if (a.mode == XMODE_DGO && valid) {
+        const double d0 = (double)n0 - (double)o0, d1 = (double)n1v - (double)o1;
+        sums[6] += 2.0 * (d0 * d0 + d1 * d1);
+      }
+      if (valid && write_eps) st2(a.eps + c * N + idx, n0, n1v);
+      const T m20 = T(2) * mu[e][0], m21 = T(2) * mu[e][1];
+      const T s0 = m20 * n0, s1 = m21 * n1v;
+      if (valid) sums[c] += (double)s0 + (double)s1;
+      if (a.polarisation) {
+        w[e] = cplx<T>{(m20 - T(2) * a.mu0) * n0, (m21 - T(2) * a.mu0) * n1v};
+      } else {
+        w[e] = cplx<T>{s0, s1};
+      }
+    }
+    const cplx<T> xn = r2c_line<T, L, E>(w, t, lane, sl, a.tw);
+    if (valid) {
+      cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[e];
+      if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xn;
+    }
+  }
+
+  if (a.partial) {
+    block_sum<WG>(sums, 7, red);
+    if (tid == 0) {
+      double *dst = a.partial + (long long)blockIdx.x * 8;
+      for (int i = 0; i < 7; ++i) dst[i] = sums[i];
+      dst[7] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- y pass
+template <typename T> struct YArgs {
+  Dims d;
+  cplx<T> *spec;
+  cplx<T> *nyq;
+  const cplx<T> *tw;  // exp(-2 pi i m / n2)
+  const State *st;
+  long long main_blocks;
+};
+
+// Columns: main = (c, k3, kx) flattened, P consecutive per workgroup, stride
+// n1/2 between y points; Nyquist plane = (c, k3) rows, stride 1.
+template <typename T, int NY, int E, int P, bool FWD>
+__global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int TPC = NY / E;
+  __shared__ cplx<T> lds[NY * P];
+  const int tid = threadIdx.x;
+  const int p = tid % P, t = tid / P;
+  const int L = a.d.L;
+  cplx<T> *base;
+  long long stride;
+  bool valid;
+  if ((long long)blockIdx.x < a.main_blocks) {
+    const long long col = (long long)blockIdx.x * P + p;
+    const long long ncol = 6LL * a.d.n3 * L;
+    valid = col < ncol;
+    const long long slab = col / L, kx = col % L;
+    base = a.spec + slab * (long long)NY * L + kx;
+    stride = L;
+  } else {
+    const long long col = ((long long)blockIdx.x - a.main_blocks) * P + p;
+    valid = col < 6LL * a.d.n3;
+    base = a.nyq + col * NY;
+    stride = 1;
+  }
+  cplx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = valid ? base[(t + TPC * e) * stride] : cplx<T>{T(0), T(0)};
+  fft_pencil<T, NY, E, FWD>(v, t, lds + p, P, a.tw, 1);
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) base[(t + TPC * e) * stride] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------- z pass + Green
+template <typename T> struct ZArgs {
+  Dims d;
+  cplx<T> *spec;
+  cplx<T> *nyq;
+  const cplx<T> *tw;  // exp(-2 pi i m / n3)
+  GreenParams<T> g;
+  double *partial;    // [gridDim.x]
+  const State *st;
+  long long main_blocks;
+  int forward_only;   // 1: forward transform only (operator entry point)
+};
+
+template <typename T, int NZ, int E, int P>
+__global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int TPC = NZ / E;
+  constexpr int WG = P * TPC;
+  __shared__ cplx<T> lds[NZ * P];
+  __shared__ double red[(WG + 63) / 64 * 8];
+  const int tid = threadIdx.x;
+  const int p = tid % P, t = tid / P;
+  const int L = a.d.L;
+  cplx<T> *base;
+  long long zstride, cstride;
+  int i1, i2;
+  bool valid;
+  if ((long long)blockIdx.x < a.main_blocks) {
+    const long long col = (long long)blockIdx.x * P + p;
+    valid = col < (long long)a.d.n2 * L;
+    i2 = (int)(col / L);
+    i1 = (int)(col % L);
+    base = a.spec + col;
+    zstride = (long long)a.d.n2 * L;
+    cstride = a.d.comp_main;
+  } else {
+    const long long col = ((long long)blockIdx.x - a.main_blocks) * P + p;
+    valid = col < a.d.n2;
+    i2 = (int)col;
+    i1 = L;
+    base = a.nyq + col;
+    zstride = a.d.n2;
+    cstride = a.d.comp_nyq;
+  }
+  cplx<T> v[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
+    fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1);
+  }
+  if (a.forward_only) {
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
+    }
+    return;
+  }
+  double res = 0.0;
+  const double wgt = (i1 == 0 || i1 == L) ? 1.0 : 2.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cplx<T> s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[c] = v[c][e];
+    const double r = green_point(a.g, i1, valid ? i2 : 0, t + TPC * e, s);
+    if (valid) res += wgt * r;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c][e] = s[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
+    }
+  }
+  if (a.partial) {
+    double vals[1] = {res};
+    block_sum<WG>(vals, 1, red);
+    if (tid == 0) a.partial[blockIdx.x] = vals[0];
+  }
+}
+
+// ---------------------------------------------------------------- reduction
+struct ReduceArgs {
+  const double *px;   // x-pass block sums [nx][8]
+  int nx;
+  const double *pz;   // z-pass block sums [nz]
+  int nz;
+  State *st;
+  double *hist;
+  int k, maxit;
+  double tol;
+  int dgo;
+  double N;
+  double ebar_norm;   // |Ebar|_F
+  double div_factor;
+};
+
+__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+  if (a.st->done) return;
+  __shared__ double red[4 * 8];
+  double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < a.nx; i += 256)
+    for (int c = 0; c < 7; ++c) vals[c] += a.px[(long long)i * 8 + c];
+  for (int i = threadIdx.x; i < a.nz; i += 256) vals[7] += a.pz[i];
+  block_sum<256>(vals, 8, red);
+  if (threadIdx.x != 0) return;
+  State &s = *a.st;
+  double mean[6];
+  double sn = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    mean[c] = vals[c] / a.N;
+    sn += (c < 3 ? 1.0 : 2.0) * mean[c] * mean[c];
+  }
+  double r;
+  if (a.dgo) {
+    r = (a.k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * a.ebar_norm);
+  } else {
+    const double num = sqrt(vals[7]);
+    const double den = a.N * sqrt(sn);
+    r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : __builtin_huge_val());
+  }
+  a.hist[a.k] = r;
+  s.r = r;
+  for (int c = 0; c < 6; ++c) s.sig_mean[c] = mean[c];
+  s.iters = a.k;
+  const int first = a.dgo ? 1 : 0;
+  if (a.k == first) s.r0 = r;
+  int done = 0, status = 1;
+  const bool finite = (r == r) && (r < __builtin_huge_val());
+  if (a.dgo && a.k == 0) {
+    if (a.k == a.maxit) { done = 1; status = 1; }
+  } else if (r <= a.tol) {
+    done = 1;
+    status = 0;
+  } else if (!a.dgo && a.k == a.maxit) {
+    done = 1;
+    status = 1;
+  } else if (!finite || r > a.div_factor * fmax(s.r0, 1e-300)) {
+    done = 1;
+    status = 2;
+  } else if (a.dgo && a.k == a.maxit) {
+    done = 1;
+    status = 1;
+  }
+  if (done) {
+    s.status = status;
+    s.done = 1;
+  }
+}
+
+__global__ void k_state_init(State *s) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    s->done = 0;
+    s->status = 1;
+    s->iters = 0;
+    s->pad = 0;
+    s->r0 = 0.0;
+    s->r = 0.0;
+    for (int c = 0; c < 6; ++c) s->sig_mean[c] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- pointwise helpers
+template <typename T>
+__global__ void k_hooke_out(const T *__restrict__ eps, const T *__restrict__ lam, const T *__restrict__ mu,
+                            T *__restrict__ sig, long long N) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const T e0 = eps[i], e1 = eps[N + i], e2 = eps[2 * N + i];
+    const T l = lam[i], m2 = T(2) * mu[i];
+    const T tr = e0 + e1 + e2;
+    sig[i] = l * tr + m2 * e0;
+    sig[N + i] = l * tr + m2 * e1;
+    sig[2 * N + i] = l * tr + m2 * e2;
+    sig[3 * N + i] = m2 * eps[3 * N + i];
+    sig[4 * N + i] = m2 * eps[4 * N + i];
+    sig[5 * N + i] = m2 * eps[5 * N + i];
+  }
+}
+
+// internal (main + Nyquist plane) <-> standard half spectrum [6][n3][n2][L+1]
+template <typename T>
+__global__ void k_to_standard(const cplx<T> *__restrict__ spec, const cplx<T> *__restrict__ nyq,
+                              cplx<T> *__restrict__ out, Dims d) {
+  const long long total = 6LL * d.rows * (d.L + 1);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / (d.L + 1);
+    const int k = (int)(i % (d.L + 1));
+    out[i] = (k < d.L) ? spec[r * d.L + k] : nyq[r];
+  }
+}
+
+template <typename T>
+__global__ void k_from_standard(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ spec,
+                                cplx<T> *__restrict__ nyq, Dims d) {
+  const long long total = 6LL * d.rows * (d.L + 1);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / (d.L + 1);
+    const int k = (int)(i % (d.L + 1));
+    if (k < d.L) spec[r * d.L + k] = in[i];
+    else nyq[r] = in[i];
+  }
+}
+
+// Green step at every frequency of a standard half spectrum (operator entry point).
+template <typename T>
+__global__ void k_green_only(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, GreenParams<T> g, Dims d,
+                             double *partial) {
+  const long long nf = d.rows * (d.L + 1);
+  const long long cs = nf;
+  double res = 0.0;
+  for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(f % (d.L + 1));
+    const long long r = f / (d.L + 1);
+    const int i2 = (int)(r % d.n2), i3 = (int)(r / d.n2);
+    cplx<T> s[6];
+    for (int c = 0; c < 6; ++c) s[c] = in[c * cs + f];
+    const double w = (i1 == 0 || i1 == d.L) ? 1.0 : 2.0;
+    res += w * green_point(g, i1, i2, i3, s);
+    for (int c = 0; c < 6; ++c) out[c * cs + f] = s[c];
+  }
+  __shared__ double red[4 * 8];
+  double vals[1] = {res};
+  block_sum<256>(vals, 1, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = vals[0];
+}
+
+// ---------------------------------------------------------------- DGO table
+// One thread per half-spectrum frequency: P_ij = sum_nu w n_i n_j and
+// Q_ijkl = sum_nu w n_i n_j n_k n_l over the periodic images of Sec. 5.4,
+// weight w = prod_r sinc^p(pi (kappa_r + nu_r n_r) / n_r), n = k/|k|,
+// k_r = 2 pi (kappa_r + nu_r n_r) / (n_r h_r).  nu_r in [-M, M], and
+// [-M, M+1] at the Nyquist index (symmetric image set).
+template <typename T>
+__global__ void k_dgo_build(T *main, T *nyq, Dims d, int M, int p, double h1, double h2, double h3) {
+  const long long nf = d.rows * (d.L + 1);
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int i1 = (int)(f % (d.L + 1));
+  const long long r = f / (d.L + 1);
+  const int i2 = (int)(r % d.n2), i3 = (int)(r / d.n2);
+  const int n[3] = {d.n1, d.n2, d.n3};
+  const int idx[3] = {i1, i2, i3};
+  const double h[3] = {h1, h2, h3};
+  int kap[3];
+  double sv[3];
+  int hi[3];
+  for (int q = 0; q < 3; ++q) {
+    kap[q] = (2 * idx[q] < n[q]) ? idx[q] : idx[q] - n[q];
+    sv[q] = sinpi((double)kap[q] / n[q]);
+    hi[q] = (2 * kap[q] == -n[q]) ? M + 1 : M;
+  }
+  double P[6] = {0, 0, 0, 0, 0, 0}, Q[15];
+  for (int q = 0; q < 15; ++q) Q[q] = 0.0;
+  const bool dc = (kap[0] == 0 && kap[1] == 0 && kap[2] == 0);
+  if (!dc) {
+    for (int v3 = -M; v3 <= hi[2]; ++v3) {
+      double w3, k3;
+      {
+        const int m = kap[2] + v3 * n[2];
+        if (kap[2] == 0) { w3 = (v3 == 0) ? 1.0 : 0.0; }
+        else { w3 = ((v3 & 1) ? -sv[2] : sv[2]) / (M_PI * ((double)kap[2] / n[2] + v3)); }
+        k3 = 2.0 * M_PI * m / (n[2] * h[2]);
+        if (p == 2) w3 *= w3;
+      }
+      if (w3 == 0.0) continue;
+      for (int v2 = -M; v2 <= hi[1]; ++v2) {
+        double w2, k2;
+        {
+          const int m = kap[1] + v2 * n[1];
+          if (kap[1] == 0) { w2 = (v2 == 0) ? 1.0 : 0.0; }
+          else { w2 = ((v2 & 1) ? -sv[1] : sv[1]) / (M_PI * ((double)kap[1] / n[1] + v2)); }
+          k2 = 2.0 * M_PI * m / (n[1] * h[1]);
+          if (p == 2) w2 *= w2;
+        }
+        if (w2 == 0.0) continue;
+        for (int v1 = -M; v1 <= hi[0]; ++v1) {
+          double w1, k1;
+          const int m = kap[0] + v1 * n[0];
+          if (kap[0] == 0) { w1 = (v1 == 0) ? 1.0 : 0.0; }
+          else { w1 = ((v1 & 1) ? -sv[0] : sv[0]) / (M_PI * ((double)kap[0] / n[0] + v1)); }
+          k1 = 2.0 * M_PI * m / (n[0] * h[0]);
+          if (p == 2) w1 *= w1;
+          if (w1 == 0.0) continue;
+          const double w = w1 * w2 * w3;
+          const double kk = k1 * k1 + k2 * k2 + k3 * k3;
+          const double inv = 1.0 / sqrt(kk);
+          const double nv[3] = {k1 * inv, k2 * inv, k3 * inv};
+          P[0] += w * nv[0] * nv[0];
+          P[1] += w * nv[1] * nv[1];
+          P[2] += w * nv[2] * nv[2];
+          P[3] += w * nv[1] * nv[2];
+          P[4] += w * nv[0] * nv[2];
+          P[5] += w * nv[0] * nv[1];
+          for (int a4 = 0; a4 <= 4; ++a4)
+            for (int b4 = 0; b4 <= 4 - a4; ++b4) {
+              const int c4 = 4 - a4 - b4;
+              double mnm = w;
+              for (int q = 0; q < a4; ++q) mnm *= nv[0];
+              for (int q = 0; q < b4; ++q) mnm *= nv[1];
+              for (int q = 0; q < c4; ++q) mnm *= nv[2];
+              Q[qidx(a4, b4)] += mnm;
+            }
+        }
+      }
+    }
+  }
+  if (i1 < d.L) {
+    const long long o = ((long long)i3 * d.n2 + i2) * d.L + i1;
+    const long long cs = d.rows * d.L;
+    for (int q = 0; q < 6; ++q) main[q * cs + o] = (T)P[q];
+    for (int q = 0; q < 15; ++q) main[(6 + q) * cs + o] = (T)Q[q];
+  } else {
+    const long long o = (long long)i3 * d.n2 + i2;
+    const long long cs = d.rows;
+    for (int q = 0; q < 6; ++q) nyq[q * cs + o] = (T)P[q];
+    for (int q = 0; q < 15; ++q) nyq[(6 + q) * cs + o] = (T)Q[q];
+  }
+}
+
+}  // namespace lsfft

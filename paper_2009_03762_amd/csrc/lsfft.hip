@@ -1,0 +1,727 @@
+// Host side of the C ABI declared in include/lsfft.h: validation, device
+// buffers, per-axis tables, kernel dispatch over the supported transform
+// lengths, and the fixed-point loop with a device-side stop flag.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <vector>
+
+#include "../../include/lsfft.h"
+#include "kernels.hpp"
+
+using lsfft::cplx;
+using lsfft::Dims;
+using lsfft::State;
+
+namespace {
+
+// ------------------------------------------------------------------ sizes
+// Points per thread for each transform: powers of two use radix-8/4/2 passes
+// with 8 points per thread; lengths with a factor 3 use 6 (x, z: six tensor
+// components live in registers) or 12 points per thread (y).
+constexpr int e_pow2(int L) { return L < 8 ? L : 8; }
+constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : e_pow2(L); }
+constexpr int ey_of(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : e_pow2(n); }
+constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : e_pow2(n); }
+template <typename T> constexpr int pcols(int n, int E) {
+  const int tpc = n / E;
+  const int pmin = 128 / (int)sizeof(cplx<T>);
+  const int p = 256 / tpc;
+  return p > pmin ? p : pmin;
+}
+constexpr int XWG = 256;
+
+bool supported_len(int n) {
+  if (n < 4 || n > 512 || (n & 1)) return false;
+  int m = n;
+  while (m % 2 == 0) m /= 2;
+  while (m % 3 == 0) m /= 3;
+  return m == 1;
+}
+
+// ------------------------------------------------------------------ tables
+// exp(-2 pi i m / n) and friends, from long double with exact values at
+// multiples of a quarter turn.
+void cis_exact(long long num, long long den, long double &c, long double &s) {
+  // angle 2 pi num / den
+  long long q = ((num % den) + den) % den;
+  if ((4 * q) % den == 0) {
+    const int k = (int)((4 * q) / den) % 4;
+    const long double cc[4] = {1.0L, 0.0L, -1.0L, 0.0L};
+    const long double ss[4] = {0.0L, 1.0L, 0.0L, -1.0L};
+    c = cc[k];
+    s = ss[k];
+    return;
+  }
+  const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)q / (long double)den;
+  c = cosl(a);
+  s = sinl(a);
+}
+
+template <typename T> std::vector<cplx<T>> twiddles(int n) {
+  std::vector<cplx<T>> w(n);
+  for (int m = 0; m < n; ++m) {
+    long double c, s;
+    cis_exact(-m, n, c, s);
+    w[m] = cplx<T>{(T)c, (T)s};
+  }
+  return w;
+}
+
+int centred(int i, int n) { return (2 * i < n) ? i : i - n; }
+
+template <typename T> std::vector<T> axis_tables(const int n[3], const double h[3], int off[3], int &S) {
+  S = n[0] + n[1] + n[2];
+  off[0] = 0;
+  off[1] = n[0];
+  off[2] = n[0] + n[1];
+  std::vector<T> tab((size_t)lsfft::TAB_KINDS * S);
+  const long double PI = 3.14159265358979323846264338327950288L;
+  for (int r = 0; r < 3; ++r) {
+    for (int i = 0; i < n[r]; ++i) {
+      const int k = centred(i, n[r]);
+      const long double hr = h[r];
+      long double c2, s2, ch, sh;
+      cis_exact(k, n[r], c2, s2);       // angle 2 pi k / n
+      cis_exact(k, 2LL * n[r], ch, sh); // angle pi k / n
+      tab[lsfft::TAB_K * S + off[r] + i] = (T)(2.0L * PI * k / (n[r] * hr));
+      tab[lsfft::TAB_SH * S + off[r] + i] = (T)(2.0L * sh / hr);
+      tab[lsfft::TAB_C * S + off[r] + i] = (T)ch;
+      tab[lsfft::TAB_AR * S + off[r] + i] = (T)((c2 - 1.0L) / hr);
+      tab[lsfft::TAB_AI * S + off[r] + i] = (T)(s2 / hr);
+    }
+  }
+  return tab;
+}
+
+}  // namespace
+
+struct lsfft_solver_s {
+  int n[3];
+  double h[3];
+  double lam0, mu0;
+  int disc, scheme, prec, M, pw;
+  hipStream_t stream;
+  Dims d;
+  void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
+  void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
+  void *dgo_main = nullptr, *dgo_nyq = nullptr;
+  double *px = nullptr, *pz = nullptr, *pg = nullptr;
+  int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
+  long long y_main_blocks = 0, z_main_blocks = 0;
+  State *st = nullptr;
+  State *st_host = nullptr;
+  double *hist = nullptr;
+  int hist_cap = 0;
+  int last_iters = -1;
+  int tabS = 0, off[3] = {0, 0, 0};
+  int timing_kernel = -1;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double timing_mean = 0.0;
+  int timing_count = 0;
+};
+
+namespace {
+
+#define LSFFT_CHECK(call)                                  \
+  do {                                                     \
+    hipError_t _e = (call);                                \
+    if (_e != hipSuccess) {                                \
+      fprintf(stderr, "lsfft: %s failed: %s\n", #call,     \
+              hipGetErrorString(_e));                      \
+      return LSFFT_EDEVICE;                                \
+    }                                                      \
+  } while (0)
+
+// Lengths handled by the dispatch switches.  Every supported n_r = 2^a 3^b in
+// [4, 512] appears for y / z; x uses n1/2.
+#ifdef LSFFT_QUICK_BUILD
+#define LSFFT_YZ_LENGTHS(X) X(8) X(16) X(64) X(256)
+#define LSFFT_X_LENGTHS(X) X(4) X(8) X(32) X(128)
+#else
+#define LSFFT_YZ_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define LSFFT_X_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#endif
+
+template <typename T> struct Launch {
+  static hipError_t xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid) {
+    switch (s->d.L) {
+#define XCASE(Lv)                                                                                        \
+  case Lv:                                                                                               \
+    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid), dim3(XWG), 0, s->stream, a); \
+    return hipGetLastError();
+      LSFFT_X_LENGTHS(XCASE)
+#undef XCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  static int xgrid(int L, long long rows) {
+    int tpc = 1;
+    switch (L) {
+#define XG(Lv) \
+  case Lv:     \
+    tpc = Lv / ex_of(Lv); \
+    break;
+      LSFFT_X_LENGTHS(XG)
+#undef XG
+      default:
+        return 0;
+    }
+    const int P = XWG / tpc;
+    return (int)((rows + P - 1) / P);
+  }
+  template <bool FWD> static hipError_t ypass(lsfft_solver s, const lsfft::YArgs<T> &a, int grid) {
+    switch (s->d.n2) {
+#define YCASE(Nv)                                                                                     \
+  case Nv: {                                                                                          \
+    constexpr int E = ey_of(Nv), P = pcols<T>(Nv, E);                                                 \
+    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P, FWD>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    return hipGetLastError();                                                                          \
+  }
+      LSFFT_YZ_LENGTHS(YCASE)
+#undef YCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  static int ycols(int n) {
+    switch (n) {
+#define YC(Nv) \
+  case Nv:     \
+    return pcols<T>(Nv, ey_of(Nv));
+      LSFFT_YZ_LENGTHS(YC)
+#undef YC
+      default:
+        return 0;
+    }
+  }
+  static hipError_t zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+    switch (s->d.n3) {
+#define ZCASE(Nv)                                                                                   \
+  case Nv: {                                                                                        \
+    constexpr int E = ez_of(Nv), P = pcols<T>(Nv, E);                                               \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    return hipGetLastError();                                                                        \
+  }
+      LSFFT_YZ_LENGTHS(ZCASE)
+#undef ZCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  static int zcols(int n) {
+    switch (n) {
+#define ZC(Nv) \
+  case Nv:     \
+    return pcols<T>(Nv, ez_of(Nv));
+      LSFFT_YZ_LENGTHS(ZC)
+#undef ZC
+      default:
+        return 0;
+    }
+  }
+};
+
+template <typename T> lsfft::GreenParams<T> green_params(lsfft_solver s) {
+  lsfft::GreenParams<T> g;
+  g.scheme = s->scheme;
+  for (int r = 0; r < 3; ++r) {
+    g.n[r] = s->n[r];
+    g.off[r] = s->off[r];
+  }
+  g.tabS = s->tabS;
+  g.tab = (const T *)s->tab;
+  g.lam0 = (T)s->lam0;
+  g.mu0 = (T)s->mu0;
+  g.c1 = (T)(1.0 / s->mu0);
+  g.c2 = (T)((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
+  g.scale = (T)(1.0 / (double)s->d.N);
+  g.dgo_main = (const T *)s->dgo_main;
+  g.dgo_nyq = (const T *)s->dgo_nyq;
+  g.dgo_main_stride = s->d.rows * s->d.L;
+  g.dgo_nyq_stride = s->d.rows;
+  return g;
+}
+
+size_t esize(const lsfft_solver s) { return s->prec == LSFFT_F32 ? sizeof(float) : sizeof(double); }
+
+hipEvent_t next_event(lsfft_solver s) {
+  if (s->ev_used == s->ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->ev.push_back(e);
+  }
+  return s->ev[s->ev_used++];
+}
+
+struct Timed {
+  lsfft_solver s;
+  bool on;
+  Timed(lsfft_solver s_, int id) : s(s_), on(s_->timing_kernel == id) {
+    if (on) {
+      hipEvent_t e = next_event(s);
+      if (e) (void)hipEventRecord(e, s->stream);
+      else on = false;
+    }
+  }
+  ~Timed() {
+    if (on) {
+      hipEvent_t e = next_event(s);
+      if (e) (void)hipEventRecord(e, s->stream);
+    }
+  }
+};
+
+template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, const double Eb[6], int mode, const void *eps_in,
+                                             bool with_partial) {
+  lsfft::XArgs<T> a;
+  a.d = s->d;
+  a.eps = (T *)s->eps;
+  a.eps_in = (const T *)eps_in;
+  a.lam = (const T *)s->lam;
+  a.mu = (const T *)s->mu;
+  a.spec = (cplx<T> *)s->spec;
+  a.nyq = (cplx<T> *)s->nyq;
+  a.tw = (const cplx<T> *)s->twx;
+  for (int c = 0; c < 6; ++c) a.Eb[c] = (T)(Eb ? Eb[c] : 0.0);
+  a.lam0 = (T)s->lam0;
+  a.mu0 = (T)s->mu0;
+  a.partial = with_partial ? s->px : nullptr;
+  a.st = with_partial ? s->st : nullptr;
+  a.mode = mode;
+  a.polarisation = (s->scheme == LSFFT_DGO) ? 1 : 0;
+  return a;
+}
+
+template <typename T> lsfft::YArgs<T> yargs(lsfft_solver s, bool flag) {
+  lsfft::YArgs<T> a;
+  a.d = s->d;
+  a.spec = (cplx<T> *)s->spec;
+  a.nyq = (cplx<T> *)s->nyq;
+  a.tw = (const cplx<T> *)s->twy;
+  a.st = flag ? s->st : nullptr;
+  a.main_blocks = s->y_main_blocks;
+  return a;
+}
+
+template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forward_only) {
+  lsfft::ZArgs<T> a;
+  a.d = s->d;
+  a.spec = (cplx<T> *)s->spec;
+  a.nyq = (cplx<T> *)s->nyq;
+  a.tw = (const cplx<T> *)s->twz;
+  a.g = green_params<T>(s);
+  a.partial = flag ? s->pz : nullptr;
+  a.st = flag ? s->st : nullptr;
+  a.main_blocks = s->z_main_blocks;
+  a.forward_only = forward_only;
+  return a;
+}
+
+template <typename T>
+lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit) {
+  using L = Launch<T>;
+  if (maxit + 1 > s->hist_cap) {
+    if (s->hist) (void)hipFree(s->hist);
+    s->hist = nullptr;
+    int cap = maxit + 1 < 1024 ? 1024 : maxit + 1;
+    if (hipMalloc(&s->hist, sizeof(double) * cap) != hipSuccess) return LSFFT_ENOMEM;
+    s->hist_cap = cap;
+  }
+  s->ev_used = 0;
+  double en = 0.0;
+  for (int c = 0; c < 6; ++c) en += (c < 3 ? 1.0 : 2.0) * Eb[c] * Eb[c];
+  en = std::sqrt(en);
+  const bool dgo = (s->scheme == LSFFT_DGO);
+  hipLaunchKernelGGL(lsfft::k_state_init, dim3(1), dim3(1), 0, s->stream, s->st);
+  LSFFT_CHECK(hipGetLastError());
+  {
+    Timed tm(s, 0);
+    LSFFT_CHECK(L::xpass(s, xargs<T>(s, Eb, lsfft::XMODE_INIT, nullptr, true), s->nxb));
+  }
+  const lsfft::YArgs<T> ya = yargs<T>(s, true);
+  const lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
+  const lsfft::XArgs<T> xa = xargs<T>(s, Eb, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
+  lsfft::ReduceArgs ra;
+  ra.px = s->px;
+  ra.nx = s->nxb;
+  ra.pz = s->pz;
+  ra.nz = s->nzb;
+  ra.st = s->st;
+  ra.hist = s->hist;
+  ra.maxit = maxit;
+  ra.tol = tol;
+  ra.dgo = dgo ? 1 : 0;
+  ra.N = (double)s->d.N;
+  ra.ebar_norm = en;
+  ra.div_factor = 1e6;
+  int k = 0;
+  int chunk = (tol == 0.0) ? maxit + 1 : 2;
+  for (;;) {
+    const int nenq = std::min(chunk, maxit + 1 - k);
+    for (int j = 0; j < nenq; ++j, ++k) {
+      {
+        Timed tm(s, 1);
+        LSFFT_CHECK(L::template ypass<true>(s, ya, s->nyb));
+      }
+      {
+        Timed tm(s, 2);
+        LSFFT_CHECK(L::zpass(s, za, s->nzb));
+      }
+      ra.k = k;
+      {
+        Timed tm(s, 5);
+        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1), dim3(256), 0, s->stream, ra);
+        LSFFT_CHECK(hipGetLastError());
+      }
+      {
+        Timed tm(s, 3);
+        LSFFT_CHECK(L::template ypass<false>(s, ya, s->nyb));
+      }
+      {
+        Timed tm(s, 0);
+        LSFFT_CHECK(L::xpass(s, xa, s->nxb));
+      }
+    }
+    LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State), hipMemcpyDeviceToHost, s->stream));
+    LSFFT_CHECK(hipStreamSynchronize(s->stream));
+    if (s->st_host->done || k > maxit) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+  if (!s->st_host->done) return LSFFT_EDEVICE;
+  s->last_iters = s->st_host->iters;
+  if (s->timing_kernel >= 0 && s->ev_used >= 2) {
+    double tot = 0.0;
+    int cnt = 0;
+    for (size_t i = 0; i + 1 < s->ev_used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]) == hipSuccess) {
+        tot += ms;
+        ++cnt;
+      }
+    }
+    s->timing_mean = cnt ? tot / cnt : 0.0;
+    s->timing_count = cnt;
+  }
+  return (lsfft_status)s->st_host->status;
+}
+
+template <typename T> lsfft_status finish_outputs(lsfft_solver s, void *eps_out, void *sig_out, bool host) {
+  const size_t bytes = 6 * (size_t)s->d.N * sizeof(T);
+  if (eps_out) {
+    if (host) {
+      std::vector<T> tmp(6 * (size_t)s->d.N);
+      LSFFT_CHECK(hipMemcpyAsync(tmp.data(), s->eps, bytes, hipMemcpyDeviceToHost, s->stream));
+      LSFFT_CHECK(hipStreamSynchronize(s->stream));
+      double *o = (double *)eps_out;
+      for (size_t i = 0; i < tmp.size(); ++i) o[i] = (double)tmp[i];
+    } else {
+      LSFFT_CHECK(hipMemcpyAsync(eps_out, s->eps, bytes, hipMemcpyDeviceToDevice, s->stream));
+    }
+  }
+  if (sig_out) {
+    T *dst = nullptr;
+    bool tmp_dev = host;
+    if (host) {
+      LSFFT_CHECK(hipMalloc(&dst, bytes));
+    } else {
+      dst = (T *)sig_out;
+    }
+    const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
+    hipLaunchKernelGGL(lsfft::k_hooke_out<T>, dim3(blocks), dim3(256), 0, s->stream, (const T *)s->eps,
+                       (const T *)s->lam, (const T *)s->mu, dst, s->d.N);
+    LSFFT_CHECK(hipGetLastError());
+    if (tmp_dev) {
+      std::vector<T> tmp(6 * (size_t)s->d.N);
+      LSFFT_CHECK(hipMemcpyAsync(tmp.data(), dst, bytes, hipMemcpyDeviceToHost, s->stream));
+      LSFFT_CHECK(hipStreamSynchronize(s->stream));
+      (void)hipFree(dst);
+      double *o = (double *)sig_out;
+      for (size_t i = 0; i < tmp.size(); ++i) o[i] = (double)tmp[i];
+    }
+  }
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  return LSFFT_OK;
+}
+
+bool finite_all(const double *p, long long n) {
+  for (long long i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename T> lsfft_status upload_moduli(lsfft_solver s, const double *lam, const double *mu) {
+  const size_t N = (size_t)s->d.N;
+  std::vector<T> a(N), b(N);
+  for (size_t i = 0; i < N; ++i) {
+    a[i] = (T)lam[i];
+    b[i] = (T)mu[i];
+  }
+  LSFFT_CHECK(hipMemcpy(s->lam, a.data(), N * sizeof(T), hipMemcpyHostToDevice));
+  LSFFT_CHECK(hipMemcpy(s->mu, b.data(), N * sizeof(T), hipMemcpyHostToDevice));
+  return LSFFT_OK;
+}
+
+template <typename T> lsfft_status upload_tables(lsfft_solver s) {
+  std::vector<T> tab = axis_tables<T>(s->n, s->h, s->off, s->tabS);
+  LSFFT_CHECK(hipMalloc(&s->tab, tab.size() * sizeof(T)));
+  LSFFT_CHECK(hipMemcpy(s->tab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice));
+  auto wx = twiddles<T>(s->n[0]);
+  auto wy = twiddles<T>(s->n[1]);
+  auto wz = twiddles<T>(s->n[2]);
+  LSFFT_CHECK(hipMalloc(&s->twx, wx.size() * sizeof(cplx<T>)));
+  LSFFT_CHECK(hipMalloc(&s->twy, wy.size() * sizeof(cplx<T>)));
+  LSFFT_CHECK(hipMalloc(&s->twz, wz.size() * sizeof(cplx<T>)));
+  LSFFT_CHECK(hipMemcpy(s->twx, wx.data(), wx.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
+  LSFFT_CHECK(hipMemcpy(s->twy, wy.data(), wy.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
+  LSFFT_CHECK(hipMemcpy(s->twz, wz.data(), wz.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
+  s->nxb = Launch<T>::xgrid(s->d.L, s->d.rows);
+  const int py = Launch<T>::ycols(s->n[1]);
+  s->y_main_blocks = (6LL * s->n[2] * s->d.L + py - 1) / py;
+  s->nyb = (int)(s->y_main_blocks + (6LL * s->n[2] + py - 1) / py);
+  const int pzc = Launch<T>::zcols(s->n[2]);
+  s->z_main_blocks = ((long long)s->n[1] * s->d.L + pzc - 1) / pzc;
+  s->nzb = (int)(s->z_main_blocks + ((long long)s->n[1] + pzc - 1) / pzc);
+  if (s->nxb <= 0 || py <= 0 || pzc <= 0) return LSFFT_EINVAL;
+  return LSFFT_OK;
+}
+
+template <typename T> lsfft_status build_dgo(lsfft_solver s) {
+  const size_t nm = 21 * (size_t)s->d.rows * s->d.L, nn = 21 * (size_t)s->d.rows;
+  LSFFT_CHECK(hipMalloc(&s->dgo_main, nm * sizeof(T)));
+  LSFFT_CHECK(hipMalloc(&s->dgo_nyq, nn * sizeof(T)));
+  const long long nf = s->d.rows * (s->d.L + 1);
+  hipLaunchKernelGGL(lsfft::k_dgo_build<T>, dim3((unsigned)((nf + 127) / 128)), dim3(128), 0, s->stream,
+                     (T *)s->dgo_main, (T *)s->dgo_nyq, s->d, s->M, s->pw, s->h[0], s->h[1], s->h[2]);
+  LSFFT_CHECK(hipGetLastError());
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  return LSFFT_OK;
+}
+
+void release(lsfft_solver s) {
+  void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz,
+                  s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->st, s->hist};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->st_host) (void)hipHostFree(s->st_host);
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  s->ev.clear();
+}
+
+template <typename T> lsfft_status stress_spectrum_impl(lsfft_solver s, const void *eps_dev, void *out) {
+  LSFFT_CHECK(Launch<T>::xpass(s, xargs<T>(s, nullptr, lsfft::XMODE_EXTERNAL, eps_dev, false), s->nxb));
+  LSFFT_CHECK(Launch<T>::template ypass<true>(s, yargs<T>(s, false), s->nyb));
+  LSFFT_CHECK(Launch<T>::zpass(s, zargs<T>(s, false, 1), s->nzb));
+  const long long total = 6LL * s->d.rows * (s->d.L + 1);
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(lsfft::k_to_standard<T>, dim3(blocks), dim3(256), 0, s->stream, (const cplx<T> *)s->spec,
+                     (const cplx<T> *)s->nyq, (cplx<T> *)out, s->d);
+  LSFFT_CHECK(hipGetLastError());
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  return LSFFT_OK;
+}
+
+template <typename T> lsfft_status green_impl(lsfft_solver s, const void *in, void *out, double *res_sq) {
+  const long long nf = s->d.rows * (s->d.L + 1);
+  const int blocks = (int)std::min<long long>((nf + 255) / 256, s->ngb);
+  lsfft::GreenParams<T> g = green_params<T>(s);
+  g.scale = T(1);  // the operator entry point returns the unnormalised increment
+  hipLaunchKernelGGL(lsfft::k_green_only<T>, dim3(blocks), dim3(256), 0, s->stream, (const cplx<T> *)in,
+                     (cplx<T> *)out, g, s->d, s->pg);
+  LSFFT_CHECK(hipGetLastError());
+  std::vector<double> part(blocks);
+  LSFFT_CHECK(hipMemcpyAsync(part.data(), s->pg, sizeof(double) * blocks, hipMemcpyDeviceToHost, s->stream));
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  double tot = 0.0;
+  for (double v : part) tot += v;
+  if (res_sq) *res_sq = tot;
+  return LSFFT_OK;
+}
+
+bool ok_moduli(double l, double m) { return std::isfinite(l) && std::isfinite(m) && m > 0.0 && 3.0 * l + 2.0 * m > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *lsfft_version(void) { return "lsfft 0.1 (gfx950)"; }
+
+const char *lsfft_status_string(lsfft_status st) {
+  switch (st) {
+    case LSFFT_OK: return "converged";
+    case LSFFT_ENOTCONV: return "maximum iterations reached";
+    case LSFFT_EDIVERGED: return "diverged";
+    case LSFFT_EINVAL: return "invalid argument";
+    case LSFFT_ENOMEM: return "device allocation failed";
+    case LSFFT_EDEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char *lsfft_kernel_name(int32_t id) {
+  static const char *names[] = {"k_xpass", "k_ypass(forward)", "k_zpass", "k_ypass(inverse)", "unused", "k_reduce"};
+  return (id >= 0 && id < 6) ? names[id] : "none";
+}
+
+lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
+  if (!cfg || !out || !cfg->lambda || !cfg->mu) return LSFFT_EINVAL;
+  *out = nullptr;
+  for (int r = 0; r < 3; ++r) {
+    if (!supported_len(cfg->n[r])) return LSFFT_EINVAL;
+    if (!(cfg->h[r] >= 0.0) || !std::isfinite(cfg->h[r])) return LSFFT_EINVAL;
+  }
+  if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
+  if (cfg->scheme < LSFFT_BASIC || cfg->scheme > LSFFT_DGO) return LSFFT_EINVAL;
+  if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
+  if (cfg->scheme == LSFFT_DGO) {
+    if (cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
+    if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
+    if (cfg->dgo_weight_power != 1 && cfg->dgo_weight_power != 2) return LSFFT_EINVAL;
+  }
+  if (!ok_moduli(cfg->lambda0, cfg->mu0)) return LSFFT_EINVAL;
+  const long long N = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  for (long long i = 0; i < N; ++i)
+    if (!ok_moduli(cfg->lambda[i], cfg->mu[i])) return LSFFT_EINVAL;
+
+  lsfft_solver s = new lsfft_solver_s();
+  for (int r = 0; r < 3; ++r) {
+    s->n[r] = cfg->n[r];
+    s->h[r] = cfg->h[r] > 0.0 ? cfg->h[r] : 1.0;
+  }
+  s->lam0 = cfg->lambda0;
+  s->mu0 = cfg->mu0;
+  s->disc = cfg->disc;
+  s->scheme = cfg->scheme;
+  s->prec = cfg->prec;
+  s->M = cfg->dgo_images;
+  s->pw = cfg->dgo_weight_power;
+  s->stream = (hipStream_t)cfg->stream;
+  s->d.n1 = s->n[0];
+  s->d.n2 = s->n[1];
+  s->d.n3 = s->n[2];
+  s->d.L = s->n[0] / 2;
+  s->d.N = N;
+  s->d.rows = (long long)s->n[1] * s->n[2];
+  s->d.comp_main = s->d.rows * s->d.L;
+  s->d.comp_nyq = s->d.rows;
+
+  const size_t es = esize(s);
+  const size_t cs = 2 * es;
+  lsfft_status st = LSFFT_OK;
+  auto fail = [&](lsfft_status e) {
+    release(s);
+    delete s;
+    return e;
+  };
+  if (hipMalloc(&s->eps, 6 * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->lam, (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->mu, (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->spec, 6 * (size_t)s->d.comp_main * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->nyq, 6 * (size_t)s->d.comp_nyq * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->st, sizeof(State)) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipHostMalloc(&s->st_host, sizeof(State), 0) != hipSuccess) return fail(LSFFT_ENOMEM);
+  st = (s->prec == LSFFT_F32) ? upload_moduli<float>(s, cfg->lambda, cfg->mu)
+                              : upload_moduli<double>(s, cfg->lambda, cfg->mu);
+  if (st != LSFFT_OK) return fail(st);
+  st = (s->prec == LSFFT_F32) ? upload_tables<float>(s) : upload_tables<double>(s);
+  if (st != LSFFT_OK) return fail(st);
+  if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)s->nxb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->pz, sizeof(double) * (size_t)s->nzb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  s->ngb = 1024;
+  if (hipMalloc(&s->pg, sizeof(double) * (size_t)s->ngb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (s->scheme == LSFFT_DGO) {
+    st = (s->prec == LSFFT_F32) ? build_dgo<float>(s) : build_dgo<double>(s);
+    if (st != LSFFT_OK) return fail(st);
+  }
+  *out = s;
+  return LSFFT_OK;
+}
+
+static lsfft_status check_solve_args(lsfft_solver s, const double *Eb, double tol, int32_t maxit) {
+  if (!s || !Eb) return LSFFT_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return LSFFT_EINVAL;
+  if (!finite_all(Eb, 6)) return LSFFT_EINVAL;
+  return LSFFT_OK;
+}
+
+static lsfft_status solve_common(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, void *eps,
+                                 void *sig, double sig_mean[6], int32_t *iters, double *residual, bool host) {
+  lsfft_status st = check_solve_args(s, Ebar, tol, maxit);
+  if (st != LSFFT_OK) return st;
+  lsfft_status rs = (s->prec == LSFFT_F32) ? run_solve<float>(s, Ebar, tol, maxit)
+                                           : run_solve<double>(s, Ebar, tol, maxit);
+  if (rs < 0) return rs;
+  lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, eps, sig, host)
+                                           : finish_outputs<double>(s, eps, sig, host);
+  if (os != LSFFT_OK) return os;
+  if (sig_mean)
+    for (int c = 0; c < 6; ++c) sig_mean[c] = s->st_host->sig_mean[c];
+  if (iters) *iters = s->st_host->iters;
+  if (residual) *residual = s->st_host->r;
+  return rs;
+}
+
+lsfft_status lsfft_solve(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, double *eps, double *sig,
+                         double sig_mean[6], int32_t *iters, double *residual) {
+  return solve_common(s, Ebar, tol, maxit, eps, sig, sig_mean, iters, residual, true);
+}
+
+lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, void *eps_dev,
+                                void *sig_dev, double sig_mean[6], int32_t *iters, double *residual) {
+  return solve_common(s, Ebar, tol, maxit, eps_dev, sig_dev, sig_mean, iters, residual, false);
+}
+
+lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count) {
+  if (!s || !out || cap < 0 || s->last_iters < 0) return LSFFT_EINVAL;
+  const int n = std::min(cap, s->last_iters + 1);
+  if (count) *count = s->last_iters + 1;
+  if (n > 0) {
+    LSFFT_CHECK(hipMemcpyAsync(out, s->hist, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
+    LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  }
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_stress_spectrum(lsfft_solver s, const void *eps_dev, void *sig_hat_dev) {
+  if (!s || !eps_dev || !sig_hat_dev) return LSFFT_EINVAL;
+  return (s->prec == LSFFT_F32) ? stress_spectrum_impl<float>(s, eps_dev, sig_hat_dev)
+                                : stress_spectrum_impl<double>(s, eps_dev, sig_hat_dev);
+}
+
+lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev, double *res_sq) {
+  if (!s || !in_dev || !out_dev) return LSFFT_EINVAL;
+  return (s->prec == LSFFT_F32) ? green_impl<float>(s, in_dev, out_dev, res_sq)
+                                : green_impl<double>(s, in_dev, out_dev, res_sq);
+}
+
+lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id) {
+  if (!s || kernel_id < -1 || kernel_id > 5) return LSFFT_EINVAL;
+  s->timing_kernel = kernel_id;
+  s->timing_mean = 0.0;
+  s->timing_count = 0;
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_get_timing(lsfft_solver s, double *mean_ms, int32_t *launches) {
+  if (!s) return LSFFT_EINVAL;
+  if (mean_ms) *mean_ms = s->timing_mean;
+  if (launches) *launches = s->timing_count;
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_destroy(lsfft_solver s) {
+  if (!s) return LSFFT_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  release(s);
+  delete s;
+  return LSFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+"""Thin ctypes binding to liblsfft.so (C ABI: include/lsfft.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions below carry the C names without the `lsfft_` prefix; `Solver`
+is a small convenience wrapper owning one handle.  PyTorch is used only for
+device memory and the current HIP stream.  If the library has not been
+built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsfft.so")
+
+OK, ENOTCONV, EDIVERGED, EINVAL, ENOMEM, EDEVICE = 0, 1, 2, -1, -2, -3
+TD, PCD = 0, 1
+BASIC, FB, AFB, DGO = 0, 1, 2, 3
+F64, F32 = 0, 1
+SCHEMES = {"basic": BASIC, "fb": FB, "afb": AFB, "dgo": DGO}
+PRECS = {"f64": F64, "f32": F32}
+DISCS = {"td": TD, "pcd": PCD}
+KERNELS = {"xpass": 0, "ypass_fwd": 1, "zpass": 2, "ypass_inv": 3, "reduce": 5}
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("h", C.c_double * 3),
+        ("lam", C.POINTER(C.c_double)),
+        ("mu", C.POINTER(C.c_double)),
+        ("lambda0", C.c_double),
+        ("mu0", C.c_double),
+        ("disc", C.c_int32),
+        ("scheme", C.c_int32),
+        ("prec", C.c_int32),
+        ("dgo_images", C.c_int32),
+        ("dgo_weight_power", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                           "`python -m paper_2009_03762_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(_LIB_PATH)
+    dp = C.POINTER(C.c_double)
+    h = C.c_void_p
+    sig = {
+        "lsfft_create": (C.c_int, [C.POINTER(Config), C.POINTER(h)]),
+        "lsfft_solve": (C.c_int, [h, dp, C.c_double, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), dp]),
+        "lsfft_solve_device": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
+                                         C.POINTER(C.c_int32), dp]),
+        "lsfft_residual_history": (C.c_int, [h, dp, C.c_int32, C.POINTER(C.c_int32)]),
+        "lsfft_stress_spectrum": (C.c_int, [h, C.c_void_p, C.c_void_p]),
+        "lsfft_green_apply": (C.c_int, [h, C.c_void_p, C.c_void_p, dp]),
+        "lsfft_set_timing": (C.c_int, [h, C.c_int32]),
+        "lsfft_get_timing": (C.c_int, [h, dp, C.POINTER(C.c_int32)]),
+        "lsfft_kernel_name": (C.c_char_p, [C.c_int32]),
+        "lsfft_destroy": (C.c_int, [h]),
+        "lsfft_status_string": (C.c_char_p, [C.c_int]),
+        "lsfft_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTS = ("lsfft_create", "lsfft_solve", "lsfft_solve_device", "lsfft_residual_history",
+           "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_set_timing", "lsfft_get_timing",
+           "lsfft_kernel_name", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
+
+
+class LsfftError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def status_string(st):
+    return _lib.lsfft_status_string(int(st)).decode()
+
+
+def version():
+    return _lib.lsfft_version().decode()
+
+
+def kernel_name(i):
+    return _lib.lsfft_kernel_name(int(i)).decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
+           dgo_images=4, dgo_weight_power=1, stream=None):
+    """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    if lam.ndim != 3 or lam.shape != mu.shape:
+        raise ValueError("lam and mu must be 3D arrays of equal shape (n3, n2, n1)")
+    n3, n2, n1 = lam.shape
+    cfg = Config()
+    cfg.n[:] = (n1, n2, n3)
+    cfg.h[:] = tuple(float(v) for v in h)
+    cfg.lam = _dptr(lam)
+    cfg.mu = _dptr(mu)
+    cfg.lambda0 = float(lambda0)
+    cfg.mu0 = float(mu0)
+    cfg.disc = DISCS[disc.lower()] if isinstance(disc, str) else int(disc)
+    cfg.scheme = SCHEMES[scheme.lower()] if isinstance(scheme, str) else int(scheme)
+    cfg.prec = PRECS[prec.lower()] if isinstance(prec, str) else int(prec)
+    cfg.dgo_images = int(dgo_images)
+    cfg.dgo_weight_power = int(dgo_weight_power)
+    cfg.stream = _stream_handle(stream)
+    handle = C.c_void_p()
+    st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
+    if st != OK:
+        raise LsfftError(st, "lsfft_create")
+    return handle
+
+
+def destroy(handle):
+    return _lib.lsfft_destroy(handle)
+
+
+def solve(handle, Ebar, tol, maxit, eps=None, sig=None):
+    """lsfft_solve with host outputs.  eps / sig: float64 arrays (6, n3, n2, n1) or None.
+    Returns (status, sig_mean (6,), iters, residual)."""
+    Eb = np.ascontiguousarray(Ebar, dtype=np.float64)
+    sm = np.zeros(6)
+    it = C.c_int32(0)
+    r = C.c_double(0.0)
+    for a in (eps, sig):
+        if a is not None and (a.dtype != np.float64 or not a.flags.c_contiguous):
+            raise ValueError("host outputs must be C-contiguous float64")
+    st = _lib.lsfft_solve(handle, _dptr(Eb), float(tol), int(maxit), _dptr(eps), _dptr(sig), _dptr(sm),
+                          C.byref(it), C.byref(r))
+    if st < 0:
+        raise LsfftError(st, "lsfft_solve")
+    return st, sm, it.value, r.value
+
+
+def solve_device(handle, Ebar, tol, maxit, eps_dev=None, sig_dev=None):
+    """lsfft_solve_device.  eps_dev / sig_dev: contiguous device tensors of the
+    solver precision with 6 N elements, or None."""
+    Eb = np.ascontiguousarray(Ebar, dtype=np.float64)
+    sm = np.zeros(6)
+    it = C.c_int32(0)
+    r = C.c_double(0.0)
+    pe = eps_dev.data_ptr() if eps_dev is not None else None
+    ps = sig_dev.data_ptr() if sig_dev is not None else None
+    st = _lib.lsfft_solve_device(handle, _dptr(Eb), float(tol), int(maxit), pe, ps, _dptr(sm),
+                                 C.byref(it), C.byref(r))
+    if st < 0:
+        raise LsfftError(st, "lsfft_solve_device")
+    return st, sm, it.value, r.value
+
+
+def residual_history(handle, cap=1 << 20):
+    cnt = C.c_int32(0)
+    probe = np.zeros(1)
+    st = _lib.lsfft_residual_history(handle, _dptr(probe), 0, C.byref(cnt))
+    if st != OK:
+        raise LsfftError(st, "lsfft_residual_history")
+    out = np.zeros(min(cnt.value, cap))
+    st = _lib.lsfft_residual_history(handle, _dptr(out), len(out), C.byref(cnt))
+    if st != OK:
+        raise LsfftError(st, "lsfft_residual_history")
+    return out
+
+
+def stress_spectrum(handle, eps_dev, out_dev):
+    st = _lib.lsfft_stress_spectrum(handle, eps_dev.data_ptr(), out_dev.data_ptr())
+    if st != OK:
+        raise LsfftError(st, "lsfft_stress_spectrum")
+
+
+def green_apply(handle, in_dev, out_dev):
+    r = C.c_double(0.0)
+    st = _lib.lsfft_green_apply(handle, in_dev.data_ptr(), out_dev.data_ptr(), C.byref(r))
+    if st != OK:
+        raise LsfftError(st, "lsfft_green_apply")
+    return r.value
+
+
+def set_timing(handle, kernel_id):
+    st = _lib.lsfft_set_timing(handle, int(kernel_id))
+    if st != OK:
+        raise LsfftError(st, "lsfft_set_timing")
+
+
+def get_timing(handle):
+    ms = C.c_double(0.0)
+    n = C.c_int32(0)
+    st = _lib.lsfft_get_timing(handle, C.byref(ms), C.byref(n))
+    if st != OK:
+        raise LsfftError(st, "lsfft_get_timing")
+    return ms.value, n.value
+
+
+class Solver:
+    """One solver handle; see `create` for the arguments."""
+
+    def __init__(self, lam, mu, lambda0, mu0, **kw):
+        self.shape = tuple(np.shape(lam))
+        self.prec = kw.get("prec", "f64")
+        self.handle = create(lam, mu, lambda0, mu0, **kw)
+
+    def solve(self, Ebar, tol=1e-6, maxit=1000, fields=True):
+        n3, n2, n1 = self.shape
+        eps = np.zeros((6, n3, n2, n1)) if fields else None
+        sig = np.zeros((6, n3, n2, n1)) if fields else None
+        st, sm, it, r = solve(self.handle, Ebar, tol, maxit, eps, sig)
+        return {"status": st, "eps": eps, "sig": sig, "sig_mean": sm, "iters": it, "residual": r}
+
+    def solve_device(self, Ebar, tol=1e-6, maxit=1000, eps_dev=None, sig_dev=None):
+        st, sm, it, r = solve_device(self.handle, Ebar, tol, maxit, eps_dev, sig_dev)
+        return {"status": st, "sig_mean": sm, "iters": it, "residual": r}
+
+    def residual_history(self):
+        return residual_history(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

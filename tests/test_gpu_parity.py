@@ -1,0 +1,205 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: FP64 results within 1e-12 relative L2 of the oracle (1e-11 where a
+long iteration accumulates rounding), FP32 results within 1e-5 on fields and
+1e-6 on the effective stiffness.  Sizes span several workgroup tiles and
+ragged shapes (radix-3 axes, unequal axes).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import green, solve3d  # noqa: E402
+from paper_2009_03762_amd import inputs  # noqa: E402
+
+from oracle_ref import (dgo_apply_half, green_increment_half, half_spectrum, hooke_voigt,  # noqa: E402
+                        rel)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _dt(prec):
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _ref(lam, mu):
+    return 0.5 * (lam.min() + lam.max()), 0.5 * (mu.min() + mu.max())
+
+
+SHAPES = [(16, 16, 16), (32, 24, 8), (12, 16, 48), (64, 8, 6)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stress_spectrum(L, shape, prec):
+    print(f"\n[stress_spectrum] shape={shape} prec={prec}", flush=True)
+    n1, n2, n3 = shape
+    lam, mu = inputs.random_moduli(shape, seed=2)
+    eps = inputs.random_strain_field(shape, seed=3)
+    s = L.Solver(lam, mu, *_ref(lam, mu), scheme="afb", prec=prec)
+    e_dev = torch.tensor(eps, dtype=_dt(prec), device="cuda").contiguous()
+    out = torch.zeros((6, n3, n2, n1 // 2 + 1, 2), dtype=_dt(prec), device="cuda")
+    L.stress_spectrum(s.handle, e_dev, out)
+    torch.cuda.synchronize()
+    got = out.cpu().double().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = half_spectrum(hooke_voigt(lam, mu, eps))
+    tol = 1e-13 if prec == "f64" else 2e-6
+    assert rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("scheme", ["basic", "fb", "afb"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (24, 8, 12)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_green_apply(L, scheme, shape, prec):
+    print(f"\n[green_apply] scheme={scheme} shape={shape} prec={prec}", flush=True)
+    n1, n2, n3 = shape
+    lam, mu = inputs.random_moduli(shape, seed=4)
+    l0, m0 = 2.3, 1.1
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec)
+    rng = np.random.default_rng(5)
+    sig = rng.standard_normal((6, n3, n2, n1))
+    half = half_spectrum(sig)
+    inp = np.stack([half.real, half.imag], axis=-1)
+    d_in = torch.tensor(inp, dtype=_dt(prec), device="cuda").contiguous()
+    d_out = torch.zeros_like(d_in)
+    res = L.green_apply(s.handle, d_in, d_out)
+    got = d_out.cpu().double().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref, res_ref = green_increment_half(half, scheme, l0, m0)
+    tol = 1e-13 if prec == "f64" else 2e-6
+    assert rel(got, ref) < tol
+    assert abs(res - res_ref) / res_ref < tol
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_green_apply_dgo(L, p, prec):
+    shape = (8, 6, 4)
+    print(f"\n[green_apply_dgo] p={p} prec={prec}", flush=True)
+    n1, n2, n3 = shape
+    lam, mu = inputs.random_moduli(shape, seed=6)
+    l0, m0 = 2.0, 1.2
+    M = 2
+    s = L.Solver(lam, mu, l0, m0, scheme="dgo", disc="pcd", prec=prec, dgo_images=M, dgo_weight_power=p)
+    rng = np.random.default_rng(7)
+    half = half_spectrum(rng.standard_normal((6, n3, n2, n1)))
+    inp = np.stack([half.real, half.imag], axis=-1)
+    d_in = torch.tensor(inp, dtype=_dt(prec), device="cuda").contiguous()
+    d_out = torch.zeros_like(d_in)
+    L.green_apply(s.handle, d_in, d_out)
+    got = d_out.cpu().double().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    Gc = green.dgo_voigt(shape, l0, m0, M, p)
+    ref = dgo_apply_half(half, Gc)
+    tol = 1e-13 if prec == "f64" else 2e-6
+    assert rel(got, ref) < tol
+
+
+SOLVE_CASES = [
+    ("basic", (16, 16, 16)),
+    ("fb", (16, 16, 16)),
+    ("afb", (16, 16, 16)),
+    ("afb", (32, 24, 8)),
+    ("fb", (12, 16, 48)),
+    ("basic", (24, 8, 12)),
+]
+
+
+@pytest.mark.parametrize("scheme,shape", SOLVE_CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fixed_iterations_match_oracle(L, scheme, shape, prec):
+    print(f"\n[fixed_iter] scheme={scheme} shape={shape} prec={prec}", flush=True)
+    K = 12
+    n1, n2, n3 = shape
+    side = tuple(v // 2 for v in shape)
+    lam, mu = inputs.cubic_inclusion(shape, side, 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    Eb = np.array([1e-3, 2e-4, -1e-4, 3e-4, -2e-4, 5e-4])
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec)
+    out = s.solve(Eb, tol=0.0, maxit=K)
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
+                            tol=0.0, maxit=K)
+    assert out["iters"] == K and out["status"] == L.ENOTCONV
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert rel(out["eps"], ref.eps) < tol
+    assert rel(out["sig"], ref.sig) < tol
+    assert rel(out["sig_mean"], ref.sig_mean) < tol
+    assert abs(out["residual"] - ref.residual) / ref.residual < (1e-9 if prec == "f64" else 1e-3)
+    hist = s.residual_history()
+    assert len(hist) == K + 1
+    assert rel(hist, np.array(ref.history)) < (1e-9 if prec == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("scheme", ["basic", "fb", "afb"])
+def test_converged_matches_oracle_fp64(L, scheme):
+    shape = (16, 16, 16)
+    print(f"\n[converged] scheme={scheme}", flush=True)
+    lam, mu = inputs.cubic_inclusion(16, 8, 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    Eb = inputs.macro_strain("11", 1e-3)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f64")
+    out = s.solve(Eb, tol=1e-8, maxit=2000)
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
+                            tol=1e-8, maxit=2000)
+    assert out["status"] == L.OK and ref.status == solve3d.OK
+    assert out["iters"] == ref.iters
+    assert rel(out["eps"], ref.eps) < 1e-11
+    assert rel(out["sig_mean"], ref.sig_mean) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("p", [1, 2])
+def test_dgo_fixed_iterations_match_oracle(L, prec, p):
+    shape = (8, 8, 8)
+    print(f"\n[dgo_fixed] prec={prec} p={p}", flush=True)
+    K = 10
+    M = 2
+    lam, mu = inputs.cubic_inclusion(8, 4, 1.0, 5.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 5.0)
+    Eb = inputs.macro_strain("12", 1e-3)
+    s = L.Solver(lam, mu, l0, m0, scheme="dgo", disc="pcd", prec=prec, dgo_images=M, dgo_weight_power=p)
+    out = s.solve(Eb, tol=0.0, maxit=K)
+    Gc = green.dgo_voigt(shape, l0, m0, M, p)
+    ref = solve3d.solve_dgo(lam, mu, Eb, l0, m0, Gc, tol=0.0, maxit=K)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < tol
+    assert rel(out["sig"], ref.sig) < tol
+    assert abs(out["residual"] - ref.residual) / ref.residual < (1e-9 if prec == "f64" else 1e-3)
+
+
+def test_homogeneous_is_exact(L):
+    lam = np.full((8, 16, 16), 2.0)
+    mu = np.full((8, 16, 16), 1.5)
+    Eb = np.array([1e-3, 2e-4, -3e-4, 1e-4, 5e-5, 2e-4])
+    for scheme in ("basic", "fb", "afb"):
+        s = L.Solver(lam, mu, 1.0, 1.0, scheme=scheme, prec="f64")
+        out = s.solve(Eb, tol=1e-12, maxit=10)
+        assert out["status"] == L.OK and out["iters"] == 0
+        assert out["residual"] <= 1e-14
+        assert np.allclose(out["eps"], Eb[:, None, None, None], atol=1e-18)
+
+
+def test_solve_device_matches_host(L):
+    lam, mu = inputs.cubic_inclusion(16, 8, 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    Eb = inputs.macro_strain("12", 1e-3)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32")
+    host = s.solve(Eb, tol=0.0, maxit=5)
+    e = torch.zeros((6, 16, 16, 16), dtype=torch.float32, device="cuda")
+    g = torch.zeros_like(e)
+    dev = s.solve_device(Eb, tol=0.0, maxit=5, eps_dev=e, sig_dev=g)
+    torch.cuda.synchronize()
+    assert np.array_equal(e.cpu().double().numpy(), host["eps"])
+    assert np.array_equal(g.cpu().double().numpy(), host["sig"])
+    assert dev["iters"] == host["iters"] == 5
