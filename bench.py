@@ -1,0 +1,256 @@
+"""Throughput of the AFB fixed point on one MI355X.
+
+Workload: 256^3 periodic cell, centred cubic inclusion of side 128 voxels
+(sharp interface), inclusion/matrix Young's modulus 1e3 / 1, nu = 0.3 in both
+phases, reference medium C0 = mean of the phase Lame moduli, macroscopic
+shear eps_12 = 1e-3, PCD discretisation, AFB (= rotated) scheme.  One step is
+one full fixed-point iteration (x-pass with Hooke, forward y, z-pass with the
+Green step and residual, reduction, inverse y).  The tolerance is 0, so
+exactly `--steps` iterations run; inputs are resident in HBM before timing.
+
+Prints one JSON line: value = GVoxel-iterations/s of the FP32 path (FP32
+transforms and Green step, FP64 reductions); the FP64 path is reported under
+"fp64".  "roofline" is for the dominant kernel, timed with HIP events on the
+solver's stream inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_IDS = {"k_xpass": 0, "k_ypass(forward)": 1, "k_zpass": 2, "k_ypass(inverse)": 3, "k_reduce": 5}
+
+
+def workload(n):
+    from paper_2009_03762_amd import inputs
+    lam, mu = inputs.cubic_inclusion(n, n // 2, 1.0, 1e3, 0.3)
+    l0, m0 = inputs.reference_medium_mean(1.0, 1e3, 0.3)
+    Eb = inputs.macro_strain("12", 1e-3)
+    return lam, mu, l0, m0, Eb
+
+
+def algorithmic_bytes(kernel, n, esize, scheme="afb"):
+    """Bytes a kernel must move per launch (one read and one write of each
+    field it transforms; the x-pass also reads and writes the strain and
+    reads the two moduli)."""
+    n1 = n2 = n3 = n
+    N = n1 * n2 * n3
+    spec = 6 * n3 * n2 * (n1 // 2 + 1) * 2 * esize  # half spectrum, 6 components
+    if kernel == "k_xpass":
+        return 2 * spec + 2 * 6 * N * esize + 2 * N * esize
+    if kernel in ("k_ypass(forward)", "k_ypass(inverse)"):
+        return 2 * spec
+    if kernel == "k_zpass":
+        extra = 21 * n3 * n2 * (n1 // 2 + 1) * esize if scheme == "dgo" else 0
+        return 2 * spec + extra
+    return 0
+
+
+def bytes_per_iteration(n, esize):
+    return sum(algorithmic_bytes(k, n, esize) for k in ("k_xpass", "k_ypass(forward)", "k_zpass",
+                                                         "k_ypass(inverse)"))
+
+
+def source_sha():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2009_03762_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, prec, n):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record, if it was taken on the current kernel sources and this workload."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("source_sha") != source_sha() or n != 256:
+        return None
+    ent = rec.get("kernels", {}).get(kernel, {}).get(prec)
+    if not ent:
+        return None
+    return ent["read_bytes"] + ent["write_bytes"]
+
+
+def run_gpu(prec, n, steps, warmup, breakdown=True):
+    import torch
+
+    from paper_2009_03762_amd import lsfft
+    lam, mu, l0, m0, Eb = workload(n)
+    esize = 4 if prec == "f32" else 8
+    torch.cuda.synchronize()
+    s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec)
+    print(f"[bench] {prec}: solver created for {n}^3", file=sys.stderr, flush=True)
+    s.solve_device(Eb, tol=0.0, maxit=warmup)
+    torch.cuda.synchronize()
+    kernels = {}
+    if breakdown:
+        for name, kid in KERNEL_IDS.items():
+            lsfft.set_timing(s.handle, kid)
+            s.solve_device(Eb, tol=0.0, maxit=10)
+            ms, cnt = lsfft.get_timing(s.handle)
+            kernels[name] = {"mean_ms": ms, "launches": cnt}
+        # launches per iteration: 1 of each (the x-pass runs once more at start)
+        dominant = max((k for k in kernels if k != "k_reduce"), key=lambda k: kernels[k]["mean_ms"])
+    else:
+        dominant = "k_xpass"
+    lsfft.set_timing(s.handle, KERNEL_IDS[dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.solve_device(Eb, tol=0.0, maxit=steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms, dom_cnt = lsfft.get_timing(s.handle)
+    lsfft.set_timing(s.handle, -1)
+    T = t1 - t0
+    N = n ** 3
+    value = N * steps / T / 1e9
+    ab = algorithmic_bytes(dominant, n, esize)
+    achieved = ab / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    res = {
+        "value": value,
+        "ms_per_step": T / steps * 1e3,
+        "residual_final": out["residual"],
+        "iters": out["iters"],
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": measured_traffic(dominant, prec, n),
+            "bytes_per_launch": ab,
+            "mean_launch_ms": dom_ms,
+            "launches_timed": dom_cnt,
+        },
+        "whole_iteration_hbm_frac": value * 1e9 * bytes_per_iteration(n, esize) / N / (HBM_PEAK_GBS * 1e9),
+        "kernels": kernels,
+    }
+    s.close()
+    torch.cuda.synchronize()
+    return res
+
+
+def cpu_baseline(n=128, iters=2):
+    """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
+    full iterations after setup, single-threaded numpy."""
+    code = f"""
+import time, json, sys
+sys.path.insert(0, {ROOT!r})
+from paper_2009_03762_amd import inputs
+from oracle import solve3d
+lam, mu = inputs.cubic_inclusion({n}, {n // 2}, 1.0, 1e3, 0.3)
+l0, m0 = inputs.reference_medium_mean(1.0, 1e3, 0.3)
+Eb = inputs.macro_strain('12', 1e-3)
+ts = []
+solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme='AFB', tol=0.0, maxit={iters}, disc='PCD',
+                  callback=lambda k, e, T, r: ts.append(time.perf_counter()))
+print(json.dumps({{"seconds": ts[-1] - ts[0], "iters": {iters}}}))
+"""
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[v] = "1"
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if out.returncode != 0:
+        return {"error": out.stderr[-500:]}
+    d = json.loads(out.stdout.strip().splitlines()[-1])
+    return {
+        "value": n ** 3 * d["iters"] / d["seconds"] / 1e9,
+        "unit": "GVoxel-iter/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 numpy oracle, AFB fixed point on the same cubic-inclusion cell at {n}^3 "
+                  f"(side {n // 2}, contrast 1e3), {d['iters']} full iterations timed after setup "
+                  f"({d['seconds']:.1f} s), single thread",
+    }
+
+
+def copy_probe(gib=1.0, reps=5):
+    """A plain device-to-device copy of known size (calibrates HBM byte counters)."""
+    import torch
+    n = int(gib * (1 << 30) // 4)
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GBps_read_plus_write": 2 * n * 4 / dt / 1e9}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--prec", choices=["f32", "f64", "both"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the solver is a "
+              "single-GPU library; multi-GPU sharding is a design note, not an implemented path.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown) \
+        if args.prec in ("f32", "both") else None
+    res64 = run_gpu("f64", args.size, args.steps, args.warmup, not args.no_breakdown) \
+        if args.prec in ("f64", "both") else None
+    head = res32 if res32 is not None else res64
+    line = {
+        "metric": "GVoxel-iter/s, AFB fixed point 256^3 FP32 vs FP64; % HBM roofline",
+        "value": head["value"],
+        "unit": "GVoxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if res32 is not None else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.size}^3 cubic inclusion (side {args.size // 2}), E contrast 1e3, "
+                               "nu 0.3, C0 = phase mean, eps_12 = 1e-3, PCD AFB, tol 0",
+                   "grid": [args.size] * 3, "scheme": "AFB", "disc": "PCD",
+                   "reductions": "f64"},
+        "roofline": head["roofline"],
+        "whole_iteration_hbm_frac": head["whole_iteration_hbm_frac"],
+        "kernels": head["kernels"],
+    }
+    if res32 is not None and res64 is not None:
+        line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
+                                               "kernels")}
+        line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

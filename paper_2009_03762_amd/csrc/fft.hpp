@@ -123,13 +123,15 @@ template <typename T, bool FWD, int R> __device__ __forceinline__ void bfly(cplx
 
 // ---------------------------------------------------------------- Stockham pass
 // tw: table of exp(-2 pi i m / L) at tw[m * ts], m = 0..L-1.
-// lds: this pencil's scratch, point m at lds[m * ms].
-// Barrier protocol: every exchange is  barrier; write; barrier; read,  so the
-// scratch may be reused by consecutive transforms without extra barriers.
+// lds: this pencil's scratch, two buffers of L points: point m of buffer b at
+// lds[(b * L + m) * ms].  Exchanges alternate between the two buffers (the
+// uniform counter `buf` carries the parity across calls), so one barrier per
+// exchange suffices: a buffer is rewritten only after the barrier of the
+// exchange in between, which every thread reaches after its last read of it.
 template <typename T, int L, int E, bool FWD, int P>
 struct StockhamPass {
   __device__ __forceinline__ static void run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
-                                             const cplx<T> *__restrict__ tw, int ts) {
+                                             const cplx<T> *__restrict__ tw, int ts, int &buf) {
     using PL = Plan<L, E>;
     constexpr int NP = PL::npass();
     constexpr int R = PL::radix(P);
@@ -138,6 +140,7 @@ struct StockhamPass {
     constexpr int TPC = L / E;
     constexpr bool LAST = (P + 1 == NP);
     cplx<T> out[E];
+    cplx<T> *sb = lds + (buf ? L * ms : 0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + TPC * b;
@@ -158,10 +161,9 @@ struct StockhamPass {
 #pragma unroll
         for (int r = 0; r < R; ++r) out[b + r * NB] = a[r];
       } else {
-        if (b == 0) __syncthreads();
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ms] = a[r];
+        for (int r = 0; r < R; ++r) sb[(base + r * Ns) * ms] = a[r];
       }
     }
     if constexpr (LAST) {
@@ -170,16 +172,19 @@ struct StockhamPass {
     } else {
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds[(t + TPC * e) * ms];
-      StockhamPass<T, L, E, FWD, P + 1>::run(v, t, lds, ms, tw, ts);
+      for (int e = 0; e < E; ++e) v[e] = sb[(t + TPC * e) * ms];
+      buf ^= 1;
+      StockhamPass<T, L, E, FWD, P + 1>::run(v, t, lds, ms, tw, ts, buf);
     }
   }
 };
 
+// One transform of a pencil; `buf` is the workgroup-uniform buffer parity,
+// to be carried from one call to the next (start at 0).
 template <typename T, int L, int E, bool FWD>
 __device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
-                                           const cplx<T> *__restrict__ tw, int ts) {
-  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0>::run(v, t, lds, ms, tw, ts);
+                                           const cplx<T> *__restrict__ tw, int ts, int &buf) {
+  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0>::run(v, t, lds, ms, tw, ts, buf);
 }
 
 // Number of LDS exchanges the transform performs (passes - 1).

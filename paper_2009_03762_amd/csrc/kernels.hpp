@@ -21,6 +21,10 @@
 #include "fft.hpp"
 #include "green.hpp"
 
+#ifndef LSFFT_X_PRELOAD
+#define LSFFT_X_PRELOAD 1
+#endif
+
 namespace lsfft {
 
 struct Dims {
@@ -105,7 +109,7 @@ __device__ __forceinline__ void partner(const cplx<T> (&v)[E], cplx<T> (&pv)[E],
 // length 2L, via one complex inverse transform of length L.
 template <typename T, int L, int E>
 __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int lane, cplx<T> *lds,
-                                         const cplx<T> *__restrict__ tw) {
+                                         const cplx<T> *__restrict__ tw, int &buf) {
   constexpr int TPC = L / E;
   cplx<T> pv[E];
   partner<T, E, TPC>(v, pv, t, lane);
@@ -121,7 +125,7 @@ __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int
       v[e] = (v[e] + xp) + mul_i(w * (v[e] - xp));
     }
   }
-  fft_pencil<T, L, E, false>(v, t, lds, 1, tw, 2);
+  fft_pencil<T, L, E, false>(v, t, lds, 1, tw, 2, buf);
 }
 
 // Forward real transform of one x-line.  In: v[e] = (x[2m], x[2m+1]).
@@ -129,9 +133,9 @@ __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int
 // (in thread t = 0).
 template <typename T, int L, int E>
 __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cplx<T> *lds,
-                                            const cplx<T> *__restrict__ tw) {
+                                            const cplx<T> *__restrict__ tw, int &buf) {
   constexpr int TPC = L / E;
-  fft_pencil<T, L, E, true>(v, t, lds, 1, tw, 2);
+  fft_pencil<T, L, E, true>(v, t, lds, 1, tw, 2, buf);
   cplx<T> pv[E];
   partner<T, E, TPC>(v, pv, t, lane);
   cplx<T> xn{T(0), T(0)};
@@ -173,14 +177,27 @@ template <int WG> __device__ __forceinline__ void block_sum(double *vals, int nv
   }
 }
 
+// Map a physical workgroup id to a logical tile so that each XCD (workgroups
+// are dealt round-robin to the 8 XCDs) walks a contiguous range of tiles:
+// neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ long long xcd_tile(long long b, long long nblocks) {
+  const long long per = nblocks / 8;
+  if (b >= per * 8) return b;  // remainder keeps its own order
+  return (b % 8) * per + b / 8;
+}
+
 // One workgroup = P x-lines of L complex points (TPC = L/E threads each).
+// All global loads of the workgroup (six spectrum rows, the Nyquist values,
+// the moduli and, in FP32, the old strain) are issued before any transform so
+// that their latencies overlap.
 template <typename T, int L, int E, int WG>
 __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   if (a.st && a.st->done) return;
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
+  constexpr bool PRELOAD_EPS = (sizeof(T) == 4) && LSFFT_X_PRELOAD;
   static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
-  __shared__ cplx<T> lds[P * L];
+  __shared__ cplx<T> lds[2 * P * L];
   __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -189,12 +206,34 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   const bool valid = row < a.d.rows;
   const int n1 = 2 * L;
   const long long N = a.d.N;
-  cplx<T> *sl = lds + p * L;
+  cplx<T> *sl = lds + p * 2 * L;
+  int buf = 0;
   const bool need_delta = (a.mode == XMODE_UPDATE || a.mode == XMODE_DGO);
-  const bool need_old = (a.mode == XMODE_UPDATE || a.mode == XMODE_DGO);
+  const bool need_old = (a.mode != XMODE_INIT);
+  const T *eps_src = (a.mode == XMODE_EXTERNAL) ? a.eps_in : a.eps;
   const bool write_eps = (a.mode != XMODE_EXTERNAL);
+  const cplx<T> zero{T(0), T(0)};
 
+  cplx<T> w[6][E];
+  cplx<T> xn[6];
   T lam[E][2], mu[E][2];
+  T eo[PRELOAD_EPS ? 6 : 1][E][2];
+  if (need_delta && valid) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[c][e] = src[t + TPC * e];
+      xn[c] = (t == 0) ? a.nyq[(long long)c * a.d.rows + row] : zero;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) w[c][e] = zero;
+      xn[c] = zero;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const long long idx = row * n1 + 2 * (t + TPC * e);
@@ -205,141 +244,80 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
       lam[e][0] = lam[e][1] = mu[e][0] = mu[e][1] = T(0);
     }
   }
-  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-
-  // ------------------------------------------------ normal components 11, 22, 33
-  {
-    cplx<T> w[3][E];
+  if constexpr (PRELOAD_EPS) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (need_delta) {
-        const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
-        cplx<T> xn{T(0), T(0)};
+    for (int c = 0; c < 6; ++c)
 #pragma unroll
-        for (int e = 0; e < E; ++e) w[c][e] = valid ? src[t + TPC * e] : cplx<T>{T(0), T(0)};
-        if (valid && t == 0) xn = a.nyq[(long long)c * a.d.rows + row];
-        c2r_line<T, L, E>(w[c], xn, t, lane, sl, a.tw);
-      } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) w[c][e] = cplx<T>{T(0), T(0)};
+      for (int e = 0; e < E; ++e) {
+        const long long idx = row * n1 + 2 * (t + TPC * e);
+        if (valid && need_old) ld2(eps_src + c * N + idx, eo[c][e][0], eo[c][e][1]);
+        else eo[c][e][0] = eo[c][e][1] = T(0);
       }
-    }
-    // strain update and Hooke, two voxels (2m, 2m+1) per point
+  }
+  if (need_delta) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const long long idx = row * n1 + 2 * (t + TPC * e);
-      T ev[3][2];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T o0 = T(0), o1 = T(0);
-        if (valid && (need_old || a.mode == XMODE_EXTERNAL)) {
-          ld2((a.mode == XMODE_EXTERNAL ? a.eps_in : a.eps) + c * N + idx, o0, o1);
-        }
-        T n0, n1v;
-        if (a.mode == XMODE_UPDATE) {
-          n0 = o0 + w[c][e].x;
-          n1v = o1 + w[c][e].y;
-        } else if (a.mode == XMODE_DGO) {
-          n0 = a.Eb[c] + w[c][e].x;
-          n1v = a.Eb[c] + w[c][e].y;
-        } else if (a.mode == XMODE_INIT) {
-          n0 = a.Eb[c];
-          n1v = a.Eb[c];
-        } else {
-          n0 = o0;
-          n1v = o1;
-        }
-        if (a.mode == XMODE_DGO && valid) {
-          const double d0 = (double)n0 - (double)o0, d1 = (double)n1v - (double)o1;
-          sums[6] += d0 * d0 + d1 * d1;
-        }
-        if (valid && write_eps) st2(a.eps + c * N + idx, n0, n1v);
-        ev[c][0] = n0;
-        ev[c][1] = n1v;
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const T tr = ev[0][h] + ev[1][h] + ev[2][h];
-        const T l = lam[e][h], m2 = T(2) * mu[e][h];
-        const T lp = a.polarisation ? l - a.lam0 : l;
-        const T mp2 = a.polarisation ? m2 - T(2) * a.mu0 : m2;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const T sg = l * tr + m2 * ev[c][h];
-          if (valid) sums[c] += (double)sg;
-          const T fin = a.polarisation ? lp * tr + mp2 * ev[c][h] : sg;
-          if (h == 0) w[c][e].x = fin; else w[c][e].y = fin;
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cplx<T> xn = r2c_line<T, L, E>(w[c], t, lane, sl, a.tw);
-      if (valid) {
-        cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
-#pragma unroll
-        for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[c][e];
-        if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xn;
-      }
-    }
+    for (int c = 0; c < 6; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, a.tw, buf);
   }
 
-  // ------------------------------------------------ shear components 23, 13, 12
-#pragma unroll 1
-  for (int c = 3; c < 6; ++c) {
-    cplx<T> w[E];
-    if (need_delta) {
-      const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
-      cplx<T> xn{T(0), T(0)};
+  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int e = 0; e < E; ++e) w[e] = valid ? src[t + TPC * e] : cplx<T>{T(0), T(0)};
-      if (valid && t == 0) xn = a.nyq[(long long)c * a.d.rows + row];
-      c2r_line<T, L, E>(w, xn, t, lane, sl, a.tw);
-    } else {
+  for (int e = 0; e < E; ++e) {
+    const long long idx = row * n1 + 2 * (t + TPC * e);
+    T ev[6][2];
 #pragma unroll
-      for (int e = 0; e < E; ++e) w[e] = cplx<T>{T(0), T(0)};
-    }
-    const T Ebc = a.Eb[c];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const long long idx = row * n1 + 2 * (t + TPC * e);
-      T o0 = T(0), o1 = T(0);
-      if (valid && (need_old || a.mode == XMODE_EXTERNAL))
-        ld2((a.mode == XMODE_EXTERNAL ? a.eps_in : a.eps) + c * N + idx, o0, o1);
+    for (int c = 0; c < 6; ++c) {
+      T o0, o1;
+      if constexpr (PRELOAD_EPS) {
+        o0 = eo[c][e][0];
+        o1 = eo[c][e][1];
+      } else {
+        o0 = o1 = T(0);
+        if (valid && need_old) ld2(eps_src + c * N + idx, o0, o1);
+      }
       T n0, n1v;
       if (a.mode == XMODE_UPDATE) {
-        n0 = o0 + w[e].x;
-        n1v = o1 + w[e].y;
+        n0 = o0 + w[c][e].x;
+        n1v = o1 + w[c][e].y;
       } else if (a.mode == XMODE_DGO) {
-        n0 = Ebc + w[e].x;
-        n1v = Ebc + w[e].y;
+        n0 = a.Eb[c] + w[c][e].x;
+        n1v = a.Eb[c] + w[c][e].y;
       } else if (a.mode == XMODE_INIT) {
-        n0 = Ebc;
-        n1v = Ebc;
+        n0 = a.Eb[c];
+        n1v = a.Eb[c];
       } else {
         n0 = o0;
         n1v = o1;
       }
       if (a.mode == XMODE_DGO && valid) {
         const double d0 = (double)n0 - (double)o0, d1 = (double)n1v - (double)o1;
-        sums[6] += 2.0 * (d0 * d0 + d1 * d1);
+        sums[6] += (c < 3 ? 1.0 : 2.0) * (d0 * d0 + d1 * d1);
       }
       if (valid && write_eps) st2(a.eps + c * N + idx, n0, n1v);
-      const T m20 = T(2) * mu[e][0], m21 = T(2) * mu[e][1];
-      const T s0 = m20 * n0, s1 = m21 * n1v;
-      if (valid) sums[c] += (double)s0 + (double)s1;
-      if (a.polarisation) {
-        w[e] = cplx<T>{(m20 - T(2) * a.mu0) * n0, (m21 - T(2) * a.mu0) * n1v};
-      } else {
-        w[e] = cplx<T>{s0, s1};
+      ev[c][0] = n0;
+      ev[c][1] = n1v;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const T tr = ev[0][h] + ev[1][h] + ev[2][h];
+      const T l = lam[e][h], m2 = T(2) * mu[e][h];
+      const T lp = l - a.lam0, mp2 = m2 - T(2) * a.mu0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const T sg = (c < 3 ? l * tr : T(0)) + m2 * ev[c][h];
+        if (valid) sums[c] += (double)sg;
+        const T fin = a.polarisation ? (c < 3 ? lp * tr : T(0)) + mp2 * ev[c][h] : sg;
+        if (h == 0) w[c][e].x = fin; else w[c][e].y = fin;
       }
     }
-    const cplx<T> xn = r2c_line<T, L, E>(w, t, lane, sl, a.tw);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const cplx<T> x_nyq = r2c_line<T, L, E>(w[c], t, lane, sl, a.tw, buf);
     if (valid) {
       cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[e];
-      if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xn;
+      for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[c][e];
+      if (t == 0) a.nyq[(long long)c * a.d.rows + row] = x_nyq;
     }
   }
 
@@ -369,7 +347,7 @@ template <typename T, int NY, int E, int P, bool FWD>
 __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
   if (a.st && a.st->done) return;
   constexpr int TPC = NY / E;
-  __shared__ cplx<T> lds[NY * P];
+  __shared__ cplx<T> lds[2 * NY * P];
   const int tid = threadIdx.x;
   const int p = tid % P, t = tid / P;
   const int L = a.d.L;
@@ -377,7 +355,7 @@ __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
   long long stride;
   bool valid;
   if ((long long)blockIdx.x < a.main_blocks) {
-    const long long col = (long long)blockIdx.x * P + p;
+    const long long col = xcd_tile(blockIdx.x, a.main_blocks) * P + p;
     const long long ncol = 6LL * a.d.n3 * L;
     valid = col < ncol;
     const long long slab = col / L, kx = col % L;
@@ -392,7 +370,8 @@ __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
   cplx<T> v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = valid ? base[(t + TPC * e) * stride] : cplx<T>{T(0), T(0)};
-  fft_pencil<T, NY, E, FWD>(v, t, lds + p, P, a.tw, 1);
+  int buf = 0;
+  fft_pencil<T, NY, E, FWD>(v, t, lds + p, P, a.tw, 1, buf);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < E; ++e) base[(t + TPC * e) * stride] = v[e];
@@ -417,7 +396,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   if (a.st && a.st->done) return;
   constexpr int TPC = NZ / E;
   constexpr int WG = P * TPC;
-  __shared__ cplx<T> lds[NZ * P];
+  __shared__ cplx<T> lds[2 * NZ * P];
   __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int p = tid % P, t = tid / P;
@@ -427,7 +406,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   int i1, i2;
   bool valid;
   if ((long long)blockIdx.x < a.main_blocks) {
-    const long long col = (long long)blockIdx.x * P + p;
+    const long long col = xcd_tile(blockIdx.x, a.main_blocks) * P + p;
     valid = col < (long long)a.d.n2 * L;
     i2 = (int)(col / L);
     i1 = (int)(col % L);
@@ -444,13 +423,15 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
     cstride = a.d.comp_nyq;
   }
   cplx<T> v[6][E];
+  // every load of the tile first, then the transforms
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
+  for (int c = 0; c < 6; ++c)
 #pragma unroll
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
-    fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1);
-  }
+  int buf = 0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1, buf);
   if (a.forward_only) {
     if (valid) {
 #pragma unroll
@@ -474,7 +455,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1);
+    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1, buf);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
@@ -488,11 +469,17 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------- reduction
+// Two stages, both in a fixed order (deterministic): k_reduce_stage sums
+// contiguous chunks of the x-pass and z-pass block sums into RSTAGE rows of
+// 8 doubles; k_reduce sums those rows and takes the stop decision.
+constexpr int RSTAGE = 64;
+
 struct ReduceArgs {
-  const double *px;   // x-pass block sums [nx][8]
+  const double *px;   // x-pass block sums [nx][8] (6 stress sums, |d eps|^2, unused)
   int nx;
   const double *pz;   // z-pass block sums [nz]
   int nz;
+  double *stage;      // [RSTAGE][8]: 6 stress sums, |d eps|^2, residual
   State *st;
   double *hist;
   int k, maxit;
@@ -503,14 +490,29 @@ struct ReduceArgs {
   double div_factor;
 };
 
-__global__ __launch_bounds__(256) void k_reduce(ReduceArgs a) {
+__global__ __launch_bounds__(256) void k_reduce_stage(ReduceArgs a) {
   if (a.st->done) return;
   __shared__ double red[4 * 8];
+  const int b = blockIdx.x;
+  const long long cx = (a.nx + RSTAGE - 1) / RSTAGE, cz = (a.nz + RSTAGE - 1) / RSTAGE;
+  const long long x0 = b * cx, x1 = (x0 + cx < a.nx) ? x0 + cx : a.nx;
+  const long long z0 = b * cz, z1 = (z0 + cz < a.nz) ? z0 + cz : a.nz;
   double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < a.nx; i += 256)
-    for (int c = 0; c < 7; ++c) vals[c] += a.px[(long long)i * 8 + c];
-  for (int i = threadIdx.x; i < a.nz; i += 256) vals[7] += a.pz[i];
+  for (long long i = x0 + threadIdx.x; i < x1; i += 256)
+    for (int c = 0; c < 7; ++c) vals[c] += a.px[i * 8 + c];
+  for (long long i = z0 + threadIdx.x; i < z1; i += 256) vals[7] += a.pz[i];
   block_sum<256>(vals, 8, red);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 8; ++c) a.stage[b * 8 + c] = vals[c];
+}
+
+__global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
+  if (a.st->done) return;
+  __shared__ double red[8];
+  double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < RSTAGE; i += 64)
+    for (int c = 0; c < 8; ++c) vals[c] += a.stage[i * 8 + c];
+  block_sum<64>(vals, 8, red);
   if (threadIdx.x != 0) return;
   State &s = *a.st;
   double mean[6];

@@ -20,19 +20,32 @@ using lsfft::State;
 namespace {
 
 // ------------------------------------------------------------------ sizes
-// Points per thread for each transform: powers of two use radix-8/4/2 passes
-// with 8 points per thread; lengths with a factor 3 use 6 (x, z: six tensor
-// components live in registers) or 12 points per thread (y).
+// Points per thread for each transform: y and z use radix-8/4/2 passes with 8
+// points per thread, x uses 4 (its six strain and six spectrum components are
+// all held in registers); lengths with a factor 3 use 6 (x, z) or 12 (y).
+#ifndef LSFFT_XE
+#define LSFFT_XE 4
+#endif
+#ifndef LSFFT_ZE
+#define LSFFT_ZE 8
+#endif
+#ifndef LSFFT_ZSEG
+#define LSFFT_ZSEG 64
+#endif
 constexpr int e_pow2(int L) { return L < 8 ? L : 8; }
-constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : e_pow2(L); }
+constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : (L < LSFFT_XE ? L : LSFFT_XE); }
 constexpr int ey_of(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : e_pow2(n); }
-constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : e_pow2(n); }
-template <typename T> constexpr int pcols(int n, int E) {
+constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZE ? n : LSFFT_ZE); }
+// Columns per workgroup: at least `seg` bytes of each row (coalescing), at
+// least 256 threads per workgroup.
+template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
   const int tpc = n / E;
-  const int pmin = 128 / (int)sizeof(cplx<T>);
+  const int pmin = seg / (int)sizeof(cplx<T>);
   const int p = 256 / tpc;
   return p > pmin ? p : pmin;
 }
+template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n, E, 128); }
+template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
 constexpr int XWG = 256;
 
 bool supported_len(int n) {
@@ -110,7 +123,7 @@ struct lsfft_solver_s {
   void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
   void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
   void *dgo_main = nullptr, *dgo_nyq = nullptr;
-  double *px = nullptr, *pz = nullptr, *pg = nullptr;
+  double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
   int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
   long long y_main_blocks = 0, z_main_blocks = 0;
   State *st = nullptr;
@@ -205,7 +218,7 @@ template <typename T> struct Launch {
     switch (s->d.n3) {
 #define ZCASE(Nv)                                                                                   \
   case Nv: {                                                                                        \
-    constexpr int E = ez_of(Nv), P = pcols<T>(Nv, E);                                               \
+    constexpr int E = ez_of(Nv), P = pcols_z<T>(Nv, E);                                             \
     hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
     return hipGetLastError();                                                                        \
   }
@@ -219,7 +232,7 @@ template <typename T> struct Launch {
     switch (n) {
 #define ZC(Nv) \
   case Nv:     \
-    return pcols<T>(Nv, ez_of(Nv));
+    return pcols_z<T>(Nv, ez_of(Nv));
       LSFFT_YZ_LENGTHS(ZC)
 #undef ZC
       default:
@@ -353,6 +366,7 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
   ra.nx = s->nxb;
   ra.pz = s->pz;
   ra.nz = s->nzb;
+  ra.stage = s->pstage;
   ra.st = s->st;
   ra.hist = s->hist;
   ra.maxit = maxit;
@@ -377,7 +391,9 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
       ra.k = k;
       {
         Timed tm(s, 5);
-        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1), dim3(256), 0, s->stream, ra);
+        hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE), dim3(256), 0, s->stream, ra);
+        LSFFT_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1), dim3(64), 0, s->stream, ra);
         LSFFT_CHECK(hipGetLastError());
       }
       {
@@ -506,7 +522,7 @@ template <typename T> lsfft_status build_dgo(lsfft_solver s) {
 
 void release(lsfft_solver s) {
   void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz,
-                  s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->st, s->hist};
+                  s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->pstage, s->st, s->hist};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -633,6 +649,7 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   if (st != LSFFT_OK) return fail(st);
   if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)s->nxb) != hipSuccess) return fail(LSFFT_ENOMEM);
   if (hipMalloc(&s->pz, sizeof(double) * (size_t)s->nzb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->pstage, sizeof(double) * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
   s->ngb = 1024;
   if (hipMalloc(&s->pg, sizeof(double) * (size_t)s->ngb) != hipSuccess) return fail(LSFFT_ENOMEM);
   if (s->scheme == LSFFT_DGO) {
