@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_IDS = {"k_xpass": 0, "k_ypass(forward)": 1, "k_zpass": 2, "k_ypass(inverse)": 3, "k_reduce": 5}
 
 
 def workload(n):
@@ -39,26 +38,46 @@ def workload(n):
     return lam, mu, l0, m0, Eb
 
 
+KERNEL_NAMES = {
+    "strain": {0: "k_xpass", 1: "k_ypass(forward)", 2: "k_zpass", 3: "k_ypass(inverse)", 5: "k_reduce"},
+    "displacement": {0: "k_stencil", 1: "k_ypass(forward)", 2: "k_zpass_u", 3: "k_ypass(inverse)",
+                     4: "k_uxpass", 5: "k_reduce"},
+}
+
+
 def algorithmic_bytes(kernel, n, esize, scheme="afb"):
-    """Bytes a kernel must move per launch (one read and one write of each
-    field it transforms; the x-pass also reads and writes the strain and
-    reads the two moduli)."""
+    """Bytes a kernel must move per launch: one read and one write of every
+    field it transforms or updates, one read of every field it only uses.
+    Strain form: the x-pass reads and writes the six-component spectrum and
+    the strain and reads the two moduli.  Displacement form: the stencil
+    kernel reads u and the moduli and writes the three-component spectrum of
+    div sigma; the update reads that spectrum and reads and writes u."""
     n1 = n2 = n3 = n
     N = n1 * n2 * n3
-    spec = 6 * n3 * n2 * (n1 // 2 + 1) * 2 * esize  # half spectrum, 6 components
-    if kernel == "k_xpass":
-        return 2 * spec + 2 * 6 * N * esize + 2 * N * esize
-    if kernel in ("k_ypass(forward)", "k_ypass(inverse)"):
-        return 2 * spec
-    if kernel == "k_zpass":
-        extra = 21 * n3 * n2 * (n1 // 2 + 1) * esize if scheme == "dgo" else 0
-        return 2 * spec + extra
-    return 0
+    half = n3 * n2 * (n1 // 2 + 1) * 2 * esize  # one component of the half spectrum
+    spec6, spec3 = 6 * half, 3 * half
+    table = {
+        "k_xpass": 2 * spec6 + 2 * 6 * N * esize + 2 * N * esize,
+        "k_ypass(forward)": 2 * spec6,
+        "k_ypass(inverse)": 2 * spec6,
+        "k_zpass": 2 * spec6 + (21 * half // 2 if scheme == "dgo" else 0),
+        "k_stencil": 3 * N * esize + 2 * N * esize + spec3,
+        "k_uxpass": spec3 + 2 * 3 * N * esize,
+        "k_zpass_u": 2 * spec3,
+        "k_ypass(forward)/3": 2 * spec3,
+        "k_ypass(inverse)/3": 2 * spec3,
+    }
+    return table.get(kernel, 0)
 
 
-def bytes_per_iteration(n, esize):
-    return sum(algorithmic_bytes(k, n, esize) for k in ("k_xpass", "k_ypass(forward)", "k_zpass",
-                                                         "k_ypass(inverse)"))
+def kernel_bytes(name, form, n, esize):
+    if form == "displacement" and name.startswith("k_ypass"):
+        return algorithmic_bytes(name + "/3", n, esize)
+    return algorithmic_bytes(name, n, esize)
+
+
+def bytes_per_iteration(n, esize, form="strain"):
+    return sum(kernel_bytes(k, form, n, esize) for k in KERNEL_NAMES[form].values() if k != "k_reduce")
 
 
 def source_sha():
@@ -88,29 +107,30 @@ def measured_traffic(kernel, prec, n):
     return ent["read_bytes"] + ent["write_bytes"]
 
 
-def run_gpu(prec, n, steps, warmup, breakdown=True):
+def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
     import torch
 
     from paper_2009_03762_amd import lsfft
     lam, mu, l0, m0, Eb = workload(n)
     esize = 4 if prec == "f32" else 8
     torch.cuda.synchronize()
-    s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec)
-    print(f"[bench] {prec}: solver created for {n}^3", file=sys.stderr, flush=True)
+    s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec, form=form)
+    print(f"[bench] {prec}: solver created for {n}^3 ({form} form)", file=sys.stderr, flush=True)
     s.solve_device(Eb, tol=0.0, maxit=warmup)
     torch.cuda.synchronize()
+    names = KERNEL_NAMES[form]
+    ids = {v: k for k, v in names.items()}
     kernels = {}
     if breakdown:
-        for name, kid in KERNEL_IDS.items():
+        for kid, name in names.items():
             lsfft.set_timing(s.handle, kid)
             s.solve_device(Eb, tol=0.0, maxit=10)
             ms, cnt = lsfft.get_timing(s.handle)
             kernels[name] = {"mean_ms": ms, "launches": cnt}
-        # launches per iteration: 1 of each (the x-pass runs once more at start)
         dominant = max((k for k in kernels if k != "k_reduce"), key=lambda k: kernels[k]["mean_ms"])
     else:
-        dominant = "k_xpass"
-    lsfft.set_timing(s.handle, KERNEL_IDS[dominant])
+        dominant = names[0]
+    lsfft.set_timing(s.handle, ids[dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = s.solve_device(Eb, tol=0.0, maxit=steps)
@@ -121,7 +141,7 @@ def run_gpu(prec, n, steps, warmup, breakdown=True):
     T = t1 - t0
     N = n ** 3
     value = N * steps / T / 1e9
-    ab = algorithmic_bytes(dominant, n, esize)
+    ab = kernel_bytes(dominant, form, n, esize)
     achieved = ab / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
     res = {
         "value": value,
@@ -140,7 +160,9 @@ def run_gpu(prec, n, steps, warmup, breakdown=True):
             "mean_launch_ms": dom_ms,
             "launches_timed": dom_cnt,
         },
-        "whole_iteration_hbm_frac": value * 1e9 * bytes_per_iteration(n, esize) / N / (HBM_PEAK_GBS * 1e9),
+        "whole_iteration_hbm_frac": value * 1e9 * bytes_per_iteration(n, esize, form) / N / (HBM_PEAK_GBS * 1e9),
+        "bytes_per_voxel_iteration": bytes_per_iteration(n, esize, form) / N,
+        "form": form,
         "kernels": kernels,
     }
     s.close()
@@ -207,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the solver is a "
@@ -216,9 +239,9 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown) \
+    res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form) \
         if args.prec in ("f32", "both") else None
-    res64 = run_gpu("f64", args.size, args.steps, args.warmup, not args.no_breakdown) \
+    res64 = run_gpu("f64", args.size, args.steps, args.warmup, not args.no_breakdown, args.form) \
         if args.prec in ("f64", "both") else None
     head = res32 if res32 is not None else res64
     line = {
@@ -236,15 +259,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.size}^3 cubic inclusion (side {args.size // 2}), E contrast 1e3, "
                                "nu 0.3, C0 = phase mean, eps_12 = 1e-3, PCD AFB, tol 0",
-                   "grid": [args.size] * 3, "scheme": "AFB", "disc": "PCD",
+                   "grid": [args.size] * 3, "scheme": "AFB", "disc": "PCD", "form": args.form,
                    "reductions": "f64"},
         "roofline": head["roofline"],
         "whole_iteration_hbm_frac": head["whole_iteration_hbm_frac"],
+        "bytes_per_voxel_iteration": head["bytes_per_voxel_iteration"],
         "kernels": head["kernels"],
     }
     if res32 is not None and res64 is not None:
         line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
-                                               "kernels")}
+                                               "bytes_per_voxel_iteration", "kernels")}
         line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

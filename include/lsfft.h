@@ -87,6 +87,14 @@ typedef struct {
   int32_t dgo_weight_power;/* DGO only: 1 = the single sinc weight as printed,
                               2 = squared sinc weight                          */
   void *stream;            /* hipStream_t for all work; NULL = default stream   */
+  int32_t form;            /* FB and AFB only: 0 = automatic, 1 = strain form
+                              (six transformed stress components, Green step
+                              -Gamma_0), 2 = displacement form (the paper's
+                              u-iteration of Sec. 5.2 with the gradient and
+                              divergence applied as real-space stencils, three
+                              transformed components; identical iterates).
+                              Automatic picks 2 when its workgroup fits in LDS
+                              (n1 <= 512 in F32, n1 <= 256 in F64).           */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda
@@ -95,7 +103,7 @@ typedef struct {
  * table (Sec. 5.4).  EINVAL: NULL pointers, unsupported n, h < 0, any
  * mu <= 0 or 3 lambda + 2 mu <= 0 (not positive definite), the same for
  * C_H, non-finite moduli, DGO with TD, dgo_images < 0 or > 64, a weight
- * power other than 1 or 2, unknown enum values.  On success *out owns
+ * power other than 1 or 2, unknown enum values, form 2 where it does not fit.  On success *out owns
  * device memory until lsfft_destroy. */
 lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out);
 
@@ -141,9 +149,10 @@ lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev
 /* Per-kernel event timing for benchmarking.  lsfft_set_timing(s, id) makes
  * every later solve record HIP events around each launch of kernel `id`
  * (0 = x-pass, 1 = forward y-pass, 2 = z-pass + Green, 3 = inverse y-pass,
- * 4 = packed kx = 0 / Nyquist planes, 5 = reduction; -1 = off).
+ * 4 = displacement update, 5 = reduction; -1 = off).
  * lsfft_get_timing returns the mean duration in ms and the launch count
- * of the last timed solve. */
+ * of the last timed solve.  In the displacement form id 0 is the stencil
+ * kernel and id 4 the displacement update. */
 lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id);
 lsfft_status lsfft_get_timing(lsfft_solver s, double *mean_ms, int32_t *launches);
 const char *lsfft_kernel_name(int32_t kernel_id);

@@ -1,0 +1,521 @@
+// Displacement form of the TD algorithm of Sec. 5.2 for the FB and AFB
+// schemes, with the finite-difference operators applied as real-space
+// stencils.  One iteration:
+//
+//   k_uxpass    u += IDFT(Delta u_hat)            (x-lines, three components)
+//   k_stencil   eps = Ebar + sym(grad^a u)  at the cells,   sigma = C : eps,
+//               f = div^b sigma  at the nodes,  f_hat_x = forward x transform
+//   k_ypass     forward y (three components)
+//   k_zpass_u   Delta u_hat = K(q)^{-1} f_hat (x) / N,  forward + inverse z
+//   k_ypass     inverse y
+//
+// AFB: grad^a = the average forward difference over the eight corners of a
+// cell (eq. (36) carried to 3D, symbol q^AFD of eq. (43)); div^b = the
+// average backward difference over the eight cells around a node (symbol
+// q^ABD).  Because q^AFD = Phi q^AhC and q^ABD = conj(Phi) q^AhC with one
+// scalar phase Phi, G(q^AFD, q^AhC) sigma_hat q^AhC = K(k)^{-1} sigma_hat q^ABD,
+// K(k) = mu0 |k|^2 I + (lam0 + mu0) k (x) k at the rotated wavevector k
+// (eq. (34)): these are exactly the iterates of the (AFD, AhC) algorithm.
+// FB: grad^a = forward difference, div^b = backward difference (q^b =
+// conj(q^FD) = -q^BD), K = mu0 |a|^2 I + mu0 a (x) conj(a) + lam0 conj(a) (x) a.
+// The equilibrium residual needs no spectrum: sum_xi |sigma_hat q^b|^2 =
+// N sum_x |f(x)|^2 (Parseval), accumulated in FP64 by k_stencil.
+#pragma once
+#include "kernels.hpp"
+
+namespace lsfft {
+
+// Delta u_hat = K^{-1} f_hat * scale at spectrum indices (i1, i2, i3).
+template <typename T>
+__device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, int i1, int i2, int i3,
+                                                 cplx<T> (&f)[3]) {
+  const int idx[3] = {i1, i2, i3};
+  if (g.scheme == SCHEME_FB) {
+    cplx<T> a[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a[r] = cplx<T>{tabv(g, TAB_AR, r, idx[r]), tabv(g, TAB_AI, r, idx[r])};
+    const T aa = norm2(a[0]) + norm2(a[1]) + norm2(a[2]);
+    if (aa == T(0)) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) f[i] = cplx<T>{T(0), T(0)};
+      return;
+    }
+    cplx<T> K[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        cplx<T> e = g.mu0 * (a[i] * conjg(a[j])) + g.lam0 * (conjg(a[i]) * a[j]);
+        if (i == j) e.x += g.mu0 * aa;
+        K[i][j] = e;
+      }
+    const cplx<T> c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+    const cplx<T> c01 = K[1][2] * K[2][0] - K[1][0] * K[2][2];
+    const cplx<T> c02 = K[1][0] * K[2][1] - K[1][1] * K[2][0];
+    const cplx<T> det = K[0][0] * c00 + K[0][1] * c01 + K[0][2] * c02;
+    cplx<T> adj[3][3];
+    adj[0][0] = c00;
+    adj[1][0] = c01;
+    adj[2][0] = c02;
+    adj[0][1] = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+    adj[1][1] = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+    adj[2][1] = K[0][1] * K[2][0] - K[0][0] * K[2][1];
+    adj[0][2] = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+    adj[1][2] = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+    adj[2][2] = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+    cplx<T> w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      w[i] = g.scale * cdiv(adj[i][0] * f[0] + adj[i][1] * f[1] + adj[i][2] * f[2], det);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = w[i];
+    return;
+  }
+  // AFB: rotated wavevector
+  T k[3];
+  {
+    T sh[3], c[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      sh[r] = tabv(g, TAB_SH, r, idx[r]);
+      c[r] = tabv(g, TAB_C, r, idx[r]);
+    }
+    k[0] = sh[0] * c[1] * c[2];
+    k[1] = sh[1] * c[2] * c[0];
+    k[2] = sh[2] * c[0] * c[1];
+  }
+  const T kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  if (kk == T(0)) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = cplx<T>{T(0), T(0)};
+    return;
+  }
+  // K^{-1} = (1 / (mu0 |k|^2)) [I - beta k (x) k / |k|^2],  beta = (lam0+mu0)/(lam0+2mu0)
+  const T inv = T(1) / kk;
+  const T a1 = g.c1 * inv * g.scale;
+  const cplx<T> kf = k[0] * f[0] + k[1] * f[1] + k[2] * f[2];
+  const cplx<T> a2 = (g.beta * inv) * kf;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) f[i] = a1 * (f[i] - k[i] * a2);
+}
+
+// ---------------------------------------------------------------- u update (x-lines)
+template <typename T> struct UArgs {
+  Dims d;
+  T *u;               // [3][n3][n2][n1]
+  const cplx<T> *spec;
+  const cplx<T> *nyq;
+  const cplx<T> *tw;  // exp(-2 pi i m / n1)
+  const State *st;
+};
+
+template <typename T, int L, int E, int WG>
+__global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int TPC = L / E;
+  constexpr int P = WG / TPC;
+  static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
+  __shared__ cplx<T> lds[2 * P * L];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int p = tid / TPC, t = tid % TPC;
+  const long long row = (long long)blockIdx.x * P + p;
+  const bool valid = row < a.d.rows;
+  const int n1 = 2 * L;
+  const long long N = a.d.N;
+  cplx<T> *sl = lds + p * 2 * L;
+  int buf = 0;
+  const cplx<T> zero{T(0), T(0)};
+  cplx<T> w[3][E];
+  cplx<T> xn[3];
+  T uo[3][E][2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[c][e] = valid ? src[t + TPC * e] : zero;
+    xn[c] = (valid && t == 0) ? a.nyq[(long long)c * a.d.rows + row] : zero;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = row * n1 + 2 * (t + TPC * e);
+      if (valid) ld2(a.u + c * N + idx, uo[c][e][0], uo[c][e][1]);
+      else uo[c][e][0] = uo[c][e][1] = T(0);
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, a.tw, buf);
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const long long idx = row * n1 + 2 * (t + TPC * e);
+        st2(a.u + c * N + idx, uo[c][e][0] + w[c][e].x, uo[c][e][1] + w[c][e].y);
+      }
+  }
+}
+
+// ---------------------------------------------------------------- stencil kernel
+// One workgroup owns output node lines y in [y0, y0 + T2) for planes
+// z in [z0, z0 + Z) and marches along z.  LDS holds two u planes over the
+// node lines [y0-1, y0+T2], two sigma planes over the cell lines
+// [y0-1, y0+T2), and the divergence f of the current plane.  A cell (c1, c2, c3)
+// has corners (c1..c1+1, c2..c2+1, c3..c3+1); node n gathers the cells
+// n - {0,1}^3 (all indices periodic).
+template <typename T> struct SArgs {
+  Dims d;
+  const T *u;
+  const T *lam;
+  const T *mu;
+  cplx<T> *spec;
+  cplx<T> *nyq;
+  const cplx<T> *tw;   // exp(-2 pi i m / n1)
+  T Eb[6];
+  T ih[3];             // 1 / h_r
+  double *partial;     // [gridDim.x][8]: 6 stress sums, sum |f|^2
+  const State *st;
+  int Z;               // planes per workgroup
+  int zero_u;          // u is identically zero (first pass): skip its loads
+};
+
+template <int SCHEME> struct Stencil;
+
+// Average forward difference over the cell, eq. (36) carried to 3D.
+template <> struct Stencil<SCHEME_AFB> {
+  template <typename T>
+  __device__ __forceinline__ static void grad(const T (&c)[2][2][2], const T (&ih)[3], T (&gr)[3]) {
+    // c[a][b][d]: value at corner offsets (x a, y b, z d)
+    gr[0] = T(0.25) * ih[0] * ((c[1][0][0] - c[0][0][0]) + (c[1][1][0] - c[0][1][0]) + (c[1][0][1] - c[0][0][1]) +
+                               (c[1][1][1] - c[0][1][1]));
+    gr[1] = T(0.25) * ih[1] * ((c[0][1][0] - c[0][0][0]) + (c[1][1][0] - c[1][0][0]) + (c[0][1][1] - c[0][0][1]) +
+                               (c[1][1][1] - c[1][0][1]));
+    gr[2] = T(0.25) * ih[2] * ((c[0][0][1] - c[0][0][0]) + (c[1][0][1] - c[1][0][0]) + (c[0][1][1] - c[0][1][0]) +
+                               (c[1][1][1] - c[1][1][0]));
+  }
+  // s[a][b][d]: value at the cell node - (a, b, d); returns the average
+  // backward difference of component direction r.
+  template <typename T>
+  __device__ __forceinline__ static T div(const T (&s)[2][2][2], int r, const T (&ih)[3]) {
+    if (r == 0)
+      return T(0.25) * ih[0] * ((s[0][0][0] - s[1][0][0]) + (s[0][1][0] - s[1][1][0]) + (s[0][0][1] - s[1][0][1]) +
+                                (s[0][1][1] - s[1][1][1]));
+    if (r == 1)
+      return T(0.25) * ih[1] * ((s[0][0][0] - s[0][1][0]) + (s[1][0][0] - s[1][1][0]) + (s[0][0][1] - s[0][1][1]) +
+                                (s[1][0][1] - s[1][1][1]));
+    return T(0.25) * ih[2] * ((s[0][0][0] - s[0][0][1]) + (s[1][0][0] - s[1][0][1]) + (s[0][1][0] - s[0][1][1]) +
+                              (s[1][1][0] - s[1][1][1]));
+  }
+};
+
+// Forward difference (gradient) / backward difference (divergence).
+template <> struct Stencil<SCHEME_FB> {
+  template <typename T>
+  __device__ __forceinline__ static void grad(const T (&c)[2][2][2], const T (&ih)[3], T (&gr)[3]) {
+    gr[0] = ih[0] * (c[1][0][0] - c[0][0][0]);
+    gr[1] = ih[1] * (c[0][1][0] - c[0][0][0]);
+    gr[2] = ih[2] * (c[0][0][1] - c[0][0][0]);
+  }
+  template <typename T>
+  __device__ __forceinline__ static T div(const T (&s)[2][2][2], int r, const T (&ih)[3]) {
+    if (r == 0) return ih[0] * (s[0][0][0] - s[1][0][0]);
+    if (r == 1) return ih[1] * (s[0][0][0] - s[0][1][0]);
+    return ih[2] * (s[0][0][0] - s[0][0][1]);
+  }
+};
+
+template <typename T, int N1, int E, int SCHEME, int T2>
+__global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int WG = 256;
+  constexpr int L = N1 / 2;
+  constexpr int TPC = L / E;
+  constexpr int NUL = T2 + 2;   // node lines of u
+  constexpr int NSL = T2 + 1;   // cell lines of sigma
+  constexpr int UPL = NUL * 3 * N1;
+  constexpr int SPL = NSL * 6 * N1;
+  static_assert(6 * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
+  static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
+  static_assert(7 * 2 * L * 2 <= SPL, "transform scratch must fit in one sigma plane");
+  __shared__ T U[2 * UPL];
+  __shared__ T S[2 * SPL];
+  __shared__ T F[T2 * 3 * N1];
+  __shared__ double red[(WG / 64) * 8];
+  const int tid = threadIdx.x;
+  const int n2 = a.d.n2, n3 = a.d.n3;
+  const long long N = a.d.N;
+  const int ny_blocks = n2 / T2;
+  const int y0 = (blockIdx.x % ny_blocks) * T2;
+  const int z0 = (blockIdx.x / ny_blocks) * a.Z;
+  const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
+  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+  // Software pipeline: the u plane z+2 and the moduli of cell plane z+1 are
+  // loaded into registers while plane z is computed, then stored to LDS /
+  // used at the next step.
+  constexpr int UQ = (UPL + WG - 1) / WG;          // u values per thread per plane
+  constexpr int CQ = (NSL * N1 + WG - 1) / WG;     // cells per thread per plane
+  T ureg[UQ];
+  T lreg[CQ], mreg[CQ];
+  auto fetch_u = [&](int zz) {
+    const int zg = ((zz % n3) + n3) % n3;
+#pragma unroll
+    for (int j = 0; j < UQ; ++j) {
+      const int q = tid + WG * j;
+      T v = T(0);
+      if (q < UPL && !a.zero_u) {
+        const int x = q % N1;
+        const int lc = q / N1;  // line * 3 + comp
+        const int l = lc / 3, c = lc % 3;
+        const int yg = ((y0 - 1 + l) % n2 + n2) % n2;
+        v = a.u[c * N + ((long long)zg * n2 + yg) * N1 + x];
+      }
+      ureg[j] = v;
+    }
+  };
+  auto stash_u = [&](int pb) {
+#pragma unroll
+    for (int j = 0; j < UQ; ++j) {
+      const int q = tid + WG * j;
+      if (q < UPL) U[pb * UPL + q] = ureg[j];
+    }
+  };
+  auto fetch_lm = [&](int zz) {
+    const int zg = ((zz % n3) + n3) % n3;
+#pragma unroll
+    for (int j = 0; j < CQ; ++j) {
+      const int q = tid + WG * j;
+      if (q < NSL * N1) {
+        const int x = q % N1, l = q / N1;
+        const int yg = ((y0 - 1 + l) % n2 + n2) % n2;
+        const long long gi = ((long long)zg * n2 + yg) * N1 + x;
+        lreg[j] = a.lam[gi];
+        mreg[j] = a.mu[gi];
+      }
+    }
+  };
+
+  fetch_u(z0 - 1);
+  stash_u((z0 - 1) & 1);
+  fetch_u(z0);
+  fetch_lm(z0 - 1);
+  for (int z = z0 - 1; z < z0 + a.Z; ++z) {
+    stash_u((z + 1) & 1);
+    T lcur[CQ], mcur[CQ];
+#pragma unroll
+    for (int j = 0; j < CQ; ++j) {
+      lcur[j] = lreg[j];
+      mcur[j] = mreg[j];
+    }
+    if (z + 2 <= z0 + a.Z) fetch_u(z + 2);
+    if (z + 1 < z0 + a.Z) fetch_lm(z + 1);
+    __syncthreads();
+    // ---- sigma at the cells of plane c3 = z, cell lines [y0-1, y0+T2)
+    {
+      const T *U0 = U + (z & 1) * UPL;        // nodes at plane z
+      const T *U1 = U + ((z + 1) & 1) * UPL;  // nodes at plane z + 1
+      T *Sp = S + (z & 1) * SPL;
+#pragma unroll
+      for (int j = 0; j < CQ; ++j) {
+        const int q = tid + WG * j;
+        if (q >= NSL * N1) break;
+        const int x = q % N1, l = q / N1;
+        const int x1 = (x + 1) % N1;
+        const T lm = lcur[j], m2 = T(2) * mcur[j];
+        T gr[3][3];  // gr[i][j] = d u_i / d x_j
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T cv[2][2][2];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int base = ((l + b) * 3 + c) * N1;
+            cv[0][b][0] = U0[base + x];
+            cv[1][b][0] = U0[base + x1];
+            cv[0][b][1] = U1[base + x];
+            cv[1][b][1] = U1[base + x1];
+          }
+          Stencil<SCHEME>::grad(cv, ih, gr[c]);
+        }
+        T e[6];
+        e[0] = a.Eb[0] + gr[0][0];
+        e[1] = a.Eb[1] + gr[1][1];
+        e[2] = a.Eb[2] + gr[2][2];
+        e[3] = a.Eb[3] + T(0.5) * (gr[1][2] + gr[2][1]);
+        e[4] = a.Eb[4] + T(0.5) * (gr[0][2] + gr[2][0]);
+        e[5] = a.Eb[5] + T(0.5) * (gr[0][1] + gr[1][0]);
+        const T tr = e[0] + e[1] + e[2];
+        T sg[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = (c < 3 ? lm * tr : T(0)) + m2 * e[c];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Sp[(l * 6 + c) * N1 + x] = sg[c];
+        if (l >= 1 && z >= z0) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sums[c] += (double)sg[c];
+        }
+      }
+    }
+    __syncthreads();
+    if (z < z0) continue;
+    // ---- f = div sigma at the nodes of plane z, node lines [y0, y0+T2)
+    {
+      const T *S1 = S + (z & 1) * SPL;        // cells at c3 = z
+      const T *S0 = S + ((z - 1) & 1) * SPL;  // cells at c3 = z - 1
+      for (int q = tid; q < T2 * N1; q += WG) {
+        const int x = q % N1, m = q / N1;
+        const int xm = (x + N1 - 1) % N1;
+        // cell lines: node line m (y0 + m) gathers cell lines y0 + m (l = m + 1) and y0 + m - 1 (l = m)
+        T f3[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T acc = T(0);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int c = voigt(i, j);
+            T s[2][2][2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int base = ((m + 1 - b) * 6 + c) * N1;
+              s[0][b][0] = S1[base + x];
+              s[1][b][0] = S1[base + xm];
+              s[0][b][1] = S0[base + x];
+              s[1][b][1] = S0[base + xm];
+            }
+            acc += Stencil<SCHEME>::div(s, j, ih);
+          }
+          f3[i] = acc;
+          F[(m * 3 + i) * N1 + x] = acc;
+        }
+        sums[6] += (double)f3[0] * f3[0] + (double)f3[1] * f3[1] + (double)f3[2] * f3[2];
+      }
+    }
+    __syncthreads();
+    // ---- forward x transforms of the T2 x 3 f lines; scratch in the free sigma plane
+    {
+      const int pid = tid / TPC, t = tid % TPC;
+      const bool act = pid < T2 * 3;
+      const int m = act ? pid / 3 : 0, c = act ? pid % 3 : 0;
+      cplx<T> v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int xx = 2 * (t + TPC * e);
+        v[e] = act ? cplx<T>{F[(m * 3 + c) * N1 + xx], F[(m * 3 + c) * N1 + xx + 1]} : cplx<T>{T(0), T(0)};
+      }
+      // idle threads (pid >= 6) share one dummy scratch area
+      cplx<T> *scr = reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : 6) * 2 * L;
+      int buf = 0;
+      const cplx<T> xnq = r2c_line<T, L, E>(v, t, tid & 63, scr, a.tw, buf);
+      if (act) {
+        const int zg = z % n3;
+        const long long row = (long long)zg * n2 + (y0 + m);
+        cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[t + TPC * e] = v[e];
+        if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xnq;
+      }
+    }
+  }
+  if (a.partial) {
+    block_sum<WG>(sums, 7, red);
+    if (tid == 0) {
+      double *dst = a.partial + (long long)blockIdx.x * 8;
+      for (int i = 0; i < 7; ++i) dst[i] = sums[i];
+      dst[7] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- z pass, displacement form
+template <typename T, int NZ, int E, int P>
+__global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int TPC = NZ / E;
+  __shared__ cplx<T> lds[2 * NZ * P];
+  const int tid = threadIdx.x;
+  const int p = tid % P, t = tid / P;
+  const int L = a.d.L;
+  cplx<T> *base;
+  long long zstride, cstride;
+  int i1, i2;
+  bool valid;
+  if ((long long)blockIdx.x < a.main_blocks) {
+    const long long col = xcd_tile(blockIdx.x, a.main_blocks) * P + p;
+    valid = col < (long long)a.d.n2 * L;
+    i2 = (int)(col / L);
+    i1 = (int)(col % L);
+    base = a.spec + col;
+    zstride = (long long)a.d.n2 * L;
+    cstride = a.d.comp_main;
+  } else {
+    const long long col = ((long long)blockIdx.x - a.main_blocks) * P + p;
+    valid = col < a.d.n2;
+    i2 = (int)col;
+    i1 = L;
+    base = a.nyq + col;
+    zstride = a.d.n2;
+    cstride = a.d.comp_nyq;
+  }
+  cplx<T> v[3][E];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
+  int buf = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1, buf);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    cplx<T> f[3] = {v[0][e], v[1][e], v[2][e]};
+    green_disp_point(a.g, i1, valid ? i2 : 0, t + TPC * e, f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][e] = f[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1, buf);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- outputs
+// eps = Ebar + sym(grad^a u) at every cell, straight from global memory.
+template <typename T, int SCHEME>
+__global__ void k_strain_from_u(const T *__restrict__ u, T *__restrict__ eps, Dims d, T e0, T e1, T e2, T e3,
+                                T e4, T e5, T ih0, T ih1, T ih2) {
+  const T ih[3] = {ih0, ih1, ih2};
+  const long long N = d.N;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % d.n1);
+    const long long r = i / d.n1;
+    const int y = (int)(r % d.n2), z = (int)(r / d.n2);
+    T gr[3][3];
+    for (int c = 0; c < 3; ++c) {
+      T cv[2][2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          for (int dd = 0; dd < 2; ++dd) {
+            const long long j = ((long long)((z + dd) % d.n3) * d.n2 + (y + b) % d.n2) * d.n1 + (x + a) % d.n1;
+            cv[a][b][dd] = u[c * N + j];
+          }
+      Stencil<SCHEME>::grad(cv, ih, gr[c]);
+    }
+    eps[i] = e0 + gr[0][0];
+    eps[N + i] = e1 + gr[1][1];
+    eps[2 * N + i] = e2 + gr[2][2];
+    eps[3 * N + i] = e3 + T(0.5) * (gr[1][2] + gr[2][1]);
+    eps[4 * N + i] = e4 + T(0.5) * (gr[0][2] + gr[2][0]);
+    eps[5 * N + i] = e5 + T(0.5) * (gr[0][1] + gr[1][0]);
+  }
+}
+
+template <typename T> __global__ void k_fill_zero(T *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+}  // namespace lsfft

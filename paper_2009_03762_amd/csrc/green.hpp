@@ -38,6 +38,7 @@ template <typename T> struct GreenParams {
   const T *tab;
   T c1;     // 1 / mu0
   T c2;     // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
+  T beta;   // (lam0 + mu0) / (lam0 + 2 mu0)
   T lam0, mu0;
   T scale;  // 1 / N
   // DGO tables: 21 coefficient planes (P: 6, Q: 15) of the half spectrum,

@@ -339,6 +339,7 @@ template <typename T> struct YArgs {
   const cplx<T> *tw;  // exp(-2 pi i m / n2)
   const State *st;
   long long main_blocks;
+  int ncomp;          // components transformed (6 strain form, 3 displacement form)
 };
 
 // Columns: main = (c, k3, kx) flattened, P consecutive per workgroup, stride
@@ -356,14 +357,14 @@ __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
   bool valid;
   if ((long long)blockIdx.x < a.main_blocks) {
     const long long col = xcd_tile(blockIdx.x, a.main_blocks) * P + p;
-    const long long ncol = 6LL * a.d.n3 * L;
+    const long long ncol = (long long)a.ncomp * a.d.n3 * L;
     valid = col < ncol;
     const long long slab = col / L, kx = col % L;
     base = a.spec + slab * (long long)NY * L + kx;
     stride = L;
   } else {
     const long long col = ((long long)blockIdx.x - a.main_blocks) * P + p;
-    valid = col < 6LL * a.d.n3;
+    valid = col < (long long)a.ncomp * a.d.n3;
     base = a.nyq + col * NY;
     stride = 1;
   }
@@ -485,6 +486,7 @@ struct ReduceArgs {
   int k, maxit;
   double tol;
   int dgo;
+  int disp;           // displacement form: residual from sum_x |div sigma|^2 (x-side slot 6)
   double N;
   double ebar_norm;   // |Ebar|_F
   double div_factor;
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   if (a.dgo) {
     r = (a.k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * a.ebar_norm);
   } else {
-    const double num = sqrt(vals[7]);
+    const double num = a.disp ? sqrt(a.N * vals[6]) : sqrt(vals[7]);
     const double den = a.N * sqrt(sn);
     r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : __builtin_huge_val());
   }

@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/lsfft.h"
-#include "kernels.hpp"
+#include "disp.hpp"
 
 using lsfft::cplx;
 using lsfft::Dims;
@@ -47,6 +47,14 @@ template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
 template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n, E, 128); }
 template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
 constexpr int XWG = 256;
+// Stencil kernel: its 2 x 3 x-transforms must fit in 256 threads (<= 32 threads each).
+constexpr int es_of(int L) {
+  return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
+}
+// LDS of the stencil kernel: two u planes (4 lines x 3), two sigma planes
+// (3 lines x 6) and the f lines (2 x 3) of n1 values each.
+template <typename T> constexpr bool stencil_fits(int n1) { return 66LL * n1 * (long long)sizeof(T) <= 150000; }
+constexpr int ST2 = 2;
 
 bool supported_len(int n) {
   if (n < 4 || n > 512 || (n & 1)) return false;
@@ -123,6 +131,9 @@ struct lsfft_solver_s {
   void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
   void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
   void *dgo_main = nullptr, *dgo_nyq = nullptr;
+  void *u = nullptr;      // displacement (FB, AFB): [3][n3][n2][n1]
+  int disp = 0;           // 1: displacement-form path with real-space stencils
+  int sZ = 0, nsb = 0, nub = 0;
   double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
   int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
   long long y_main_blocks = 0, z_main_blocks = 0;
@@ -239,6 +250,52 @@ template <typename T> struct Launch {
         return 0;
     }
   }
+  static hipError_t uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid) {
+    switch (s->d.L) {
+#define UCASE(Lv)                                                                                         \
+  case Lv:                                                                                                \
+    hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid), dim3(XWG), 0, s->stream, a); \
+    return hipGetLastError();
+      LSFFT_X_LENGTHS(UCASE)
+#undef UCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  template <int SCH> static hipError_t stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
+    switch (s->n[0]) {
+#define SCASE(Lv)                                                                                      \
+  case 2 * Lv:                                                                                         \
+    if constexpr (stencil_fits<T>(2 * Lv)) {                                                           \
+      hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid), dim3(256), 0, \
+                         s->stream, a);                                                                \
+      return hipGetLastError();                                                                        \
+    } else {                                                                                           \
+      return hipErrorInvalidValue;                                                                     \
+    }
+      LSFFT_X_LENGTHS(SCASE)
+#undef SCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  static hipError_t stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
+    return s->scheme == LSFFT_FB ? stencil_s<lsfft::SCHEME_FB>(s, a, grid) : stencil_s<lsfft::SCHEME_AFB>(s, a, grid);
+  }
+  static hipError_t zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+    switch (s->d.n3) {
+#define ZUCASE(Nv)                                                                                    \
+  case Nv: {                                                                                          \
+    constexpr int E = ez_of(Nv), P = pcols_z<T>(Nv, E);                                               \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    return hipGetLastError();                                                                          \
+  }
+      LSFFT_YZ_LENGTHS(ZUCASE)
+#undef ZUCASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
 };
 
 template <typename T> lsfft::GreenParams<T> green_params(lsfft_solver s) {
@@ -254,6 +311,7 @@ template <typename T> lsfft::GreenParams<T> green_params(lsfft_solver s) {
   g.mu0 = (T)s->mu0;
   g.c1 = (T)(1.0 / s->mu0);
   g.c2 = (T)((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
+  g.beta = (T)((s->lam0 + s->mu0) / (s->lam0 + 2.0 * s->mu0));
   g.scale = (T)(1.0 / (double)s->d.N);
   g.dgo_main = (const T *)s->dgo_main;
   g.dgo_nyq = (const T *)s->dgo_nyq;
@@ -312,15 +370,22 @@ template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, const double Eb[6], 
   return a;
 }
 
-template <typename T> lsfft::YArgs<T> yargs(lsfft_solver s, bool flag) {
+template <typename T> lsfft::YArgs<T> yargs(lsfft_solver s, bool flag, int ncomp = 6) {
   lsfft::YArgs<T> a;
+  a.ncomp = ncomp;
   a.d = s->d;
   a.spec = (cplx<T> *)s->spec;
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twy;
   a.st = flag ? s->st : nullptr;
-  a.main_blocks = s->y_main_blocks;
+  const int py = Launch<T>::ycols(s->n[1]);
+  a.main_blocks = ((long long)ncomp * s->n[2] * s->d.L + py - 1) / py;
   return a;
+}
+
+template <typename T> int ygrid(lsfft_solver s, int ncomp) {
+  const int py = Launch<T>::ycols(s->n[1]);
+  return (int)(((long long)ncomp * s->n[2] * s->d.L + py - 1) / py + ((long long)ncomp * s->n[2] + py - 1) / py);
 }
 
 template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forward_only) {
@@ -335,6 +400,49 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
   a.main_blocks = s->z_main_blocks;
   a.forward_only = forward_only;
   return a;
+}
+
+template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, const double Eb[6], int zero_u) {
+  lsfft::SArgs<T> a;
+  a.d = s->d;
+  a.u = (const T *)s->u;
+  a.lam = (const T *)s->lam;
+  a.mu = (const T *)s->mu;
+  a.spec = (cplx<T> *)s->spec;
+  a.nyq = (cplx<T> *)s->nyq;
+  a.tw = (const cplx<T> *)s->twx;
+  for (int c = 0; c < 6; ++c) a.Eb[c] = (T)Eb[c];
+  for (int r = 0; r < 3; ++r) a.ih[r] = (T)(1.0 / s->h[r]);
+  a.partial = s->px;
+  a.st = s->st;
+  a.Z = s->sZ;
+  a.zero_u = zero_u;
+  return a;
+}
+
+template <typename T> lsfft::UArgs<T> uargs(lsfft_solver s) {
+  lsfft::UArgs<T> a;
+  a.d = s->d;
+  a.u = (T *)s->u;
+  a.spec = (const cplx<T> *)s->spec;
+  a.nyq = (const cplx<T> *)s->nyq;
+  a.tw = (const cplx<T> *)s->twx;
+  a.st = s->st;
+  return a;
+}
+
+template <typename T> hipError_t strain_from_u(lsfft_solver s, const double Eb[6]) {
+  const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
+  const T ih0 = (T)(1.0 / s->h[0]), ih1 = (T)(1.0 / s->h[1]), ih2 = (T)(1.0 / s->h[2]);
+  if (s->scheme == LSFFT_FB)
+    hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_FB>), dim3(blocks), dim3(256), 0, s->stream,
+                       (const T *)s->u, (T *)s->eps, s->d, (T)Eb[0], (T)Eb[1], (T)Eb[2], (T)Eb[3], (T)Eb[4],
+                       (T)Eb[5], ih0, ih1, ih2);
+  else
+    hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_AFB>), dim3(blocks), dim3(256), 0, s->stream,
+                       (const T *)s->u, (T *)s->eps, s->d, (T)Eb[0], (T)Eb[1], (T)Eb[2], (T)Eb[3], (T)Eb[4],
+                       (T)Eb[5], ih0, ih1, ih2);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -352,26 +460,39 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
   for (int c = 0; c < 6; ++c) en += (c < 3 ? 1.0 : 2.0) * Eb[c] * Eb[c];
   en = std::sqrt(en);
   const bool dgo = (s->scheme == LSFFT_DGO);
+  const bool disp = s->disp != 0;
+  const int ncomp = disp ? 3 : 6;
   hipLaunchKernelGGL(lsfft::k_state_init, dim3(1), dim3(1), 0, s->stream, s->st);
   LSFFT_CHECK(hipGetLastError());
-  {
+  if (disp) {
+    const long long nu = 3 * s->d.N;
+    hipLaunchKernelGGL(lsfft::k_fill_zero<T>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
+                       dim3(256), 0, s->stream, (T *)s->u, nu);
+    LSFFT_CHECK(hipGetLastError());
+    Timed tm(s, 0);
+    LSFFT_CHECK(L::stencil(s, sargs<T>(s, Eb, 1), s->nsb));
+  } else {
     Timed tm(s, 0);
     LSFFT_CHECK(L::xpass(s, xargs<T>(s, Eb, lsfft::XMODE_INIT, nullptr, true), s->nxb));
   }
-  const lsfft::YArgs<T> ya = yargs<T>(s, true);
+  const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
+  const int nyg = ygrid<T>(s, ncomp);
   const lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
   const lsfft::XArgs<T> xa = xargs<T>(s, Eb, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
+  const lsfft::SArgs<T> sa = sargs<T>(s, Eb, 0);
+  const lsfft::UArgs<T> ua = uargs<T>(s);
   lsfft::ReduceArgs ra;
   ra.px = s->px;
-  ra.nx = s->nxb;
+  ra.nx = disp ? s->nsb : s->nxb;
   ra.pz = s->pz;
-  ra.nz = s->nzb;
+  ra.nz = disp ? 0 : s->nzb;
   ra.stage = s->pstage;
   ra.st = s->st;
   ra.hist = s->hist;
   ra.maxit = maxit;
   ra.tol = tol;
   ra.dgo = dgo ? 1 : 0;
+  ra.disp = disp ? 1 : 0;
   ra.N = (double)s->d.N;
   ra.ebar_norm = en;
   ra.div_factor = 1e6;
@@ -382,11 +503,11 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
     for (int j = 0; j < nenq; ++j, ++k) {
       {
         Timed tm(s, 1);
-        LSFFT_CHECK(L::template ypass<true>(s, ya, s->nyb));
+        LSFFT_CHECK(L::template ypass<true>(s, ya, nyg));
       }
       {
         Timed tm(s, 2);
-        LSFFT_CHECK(L::zpass(s, za, s->nzb));
+        LSFFT_CHECK(disp ? L::zpass_u(s, za, s->nzb) : L::zpass(s, za, s->nzb));
       }
       ra.k = k;
       {
@@ -398,9 +519,16 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
       }
       {
         Timed tm(s, 3);
-        LSFFT_CHECK(L::template ypass<false>(s, ya, s->nyb));
+        LSFFT_CHECK(L::template ypass<false>(s, ya, nyg));
       }
-      {
+      if (disp) {
+        {
+          Timed tm(s, 4);
+          LSFFT_CHECK(L::uxpass(s, ua, s->nub));
+        }
+        Timed tm(s, 0);
+        LSFFT_CHECK(L::stencil(s, sa, s->nsb));
+      } else {
         Timed tm(s, 0);
         LSFFT_CHECK(L::xpass(s, xa, s->nxb));
       }
@@ -411,6 +539,9 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
     chunk = std::min(chunk * 2, 64);
   }
   if (!s->st_host->done) return LSFFT_EDEVICE;
+  if (disp) {
+    LSFFT_CHECK(strain_from_u<T>(s, Eb));
+  }
   s->last_iters = s->st_host->iters;
   if (s->timing_kernel >= 0 && s->ev_used >= 2) {
     double tot = 0.0;
@@ -521,7 +652,7 @@ template <typename T> lsfft_status build_dgo(lsfft_solver s) {
 }
 
 void release(lsfft_solver s) {
-  void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz,
+  void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->pstage, s->st, s->hist};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -581,7 +712,8 @@ const char *lsfft_status_string(lsfft_status st) {
 }
 
 const char *lsfft_kernel_name(int32_t id) {
-  static const char *names[] = {"k_xpass", "k_ypass(forward)", "k_zpass", "k_ypass(inverse)", "unused", "k_reduce"};
+  static const char *names[] = {"k_xpass", "k_ypass(forward)", "k_zpass", "k_ypass(inverse)", "k_uxpass",
+                                "k_reduce"};
   return (id >= 0 && id < 6) ? names[id] : "none";
 }
 
@@ -595,6 +727,7 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
   if (cfg->scheme < LSFFT_BASIC || cfg->scheme > LSFFT_DGO) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
+  if (cfg->form < 0 || cfg->form > 2) return LSFFT_EINVAL;
   if (cfg->scheme == LSFFT_DGO) {
     if (cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
     if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
@@ -647,7 +780,27 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   if (st != LSFFT_OK) return fail(st);
   st = (s->prec == LSFFT_F32) ? upload_tables<float>(s) : upload_tables<double>(s);
   if (st != LSFFT_OK) return fail(st);
-  if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)s->nxb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (s->scheme == LSFFT_FB || s->scheme == LSFFT_AFB) {
+    const bool fits = (s->prec == LSFFT_F32) ? stencil_fits<float>(s->n[0]) : stencil_fits<double>(s->n[0]);
+    if (cfg->form == 2 && !fits) return fail(LSFFT_EINVAL);
+    s->disp = (cfg->form == 1) ? 0 : (fits ? 1 : 0);
+  }
+  if (s->disp) {
+    if (hipMalloc(&s->u, 3 * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+    // planes per stencil workgroup: as many as keep >= 1024 workgroups, at least 2
+    int Z = 2;
+    for (int c : {32, 16, 8, 4}) {
+      if (s->n[2] % c == 0 && (long long)(s->n[1] / ST2) * (s->n[2] / c) >= 1024) {
+        Z = c;
+        break;
+      }
+    }
+    s->sZ = Z;
+    s->nsb = (s->n[1] / ST2) * (s->n[2] / Z);
+    s->nub = s->nxb;
+  }
+  if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)std::max(s->nxb, s->nsb)) != hipSuccess)
+    return fail(LSFFT_ENOMEM);
   if (hipMalloc(&s->pz, sizeof(double) * (size_t)s->nzb) != hipSuccess) return fail(LSFFT_ENOMEM);
   if (hipMalloc(&s->pstage, sizeof(double) * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
   s->ngb = 1024;

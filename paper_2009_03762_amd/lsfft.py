@@ -22,7 +22,7 @@ F64, F32 = 0, 1
 SCHEMES = {"basic": BASIC, "fb": FB, "afb": AFB, "dgo": DGO}
 PRECS = {"f64": F64, "f32": F32}
 DISCS = {"td": TD, "pcd": PCD}
-KERNELS = {"xpass": 0, "ypass_fwd": 1, "zpass": 2, "ypass_inv": 3, "reduce": 5}
+KERNELS = {"xpass": 0, "ypass_fwd": 1, "zpass": 2, "ypass_inv": 3, "uxpass": 4, "reduce": 5}
 
 
 class Config(C.Structure):
@@ -39,6 +39,7 @@ class Config(C.Structure):
         ("dgo_images", C.c_int32),
         ("dgo_weight_power", C.c_int32),
         ("stream", C.c_void_p),
+        ("form", C.c_int32),
     ]
 
 
@@ -107,8 +108,11 @@ def _stream_handle(stream):
     return int(stream.cuda_stream)
 
 
+FORMS = {"auto": 0, "strain": 1, "displacement": 2}
+
+
 def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None):
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto"):
     """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
@@ -128,6 +132,7 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
     cfg.dgo_images = int(dgo_images)
     cfg.dgo_weight_power = int(dgo_weight_power)
     cfg.stream = _stream_handle(stream)
+    cfg.form = FORMS[form] if isinstance(form, str) else int(form)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:

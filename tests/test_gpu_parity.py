@@ -117,15 +117,18 @@ SOLVE_CASES = [
 
 @pytest.mark.parametrize("scheme,shape", SOLVE_CASES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_fixed_iterations_match_oracle(L, scheme, shape, prec):
-    print(f"\n[fixed_iter] scheme={scheme} shape={shape} prec={prec}", flush=True)
+@pytest.mark.parametrize("form", ["strain", "auto"])
+def test_fixed_iterations_match_oracle(L, scheme, shape, prec, form):
+    if form == "auto" and scheme == "basic":
+        pytest.skip("the basic scheme has a single (strain) form")
+    print(f"\n[fixed_iter] scheme={scheme} shape={shape} prec={prec} form={form}", flush=True)
     K = 12
     n1, n2, n3 = shape
     side = tuple(v // 2 for v in shape)
     lam, mu = inputs.cubic_inclusion(shape, side, 1.0, 10.0)
     l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
     Eb = np.array([1e-3, 2e-4, -1e-4, 3e-4, -2e-4, 5e-4])
-    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec, form=form)
     out = s.solve(Eb, tol=0.0, maxit=K)
     ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
                             tol=0.0, maxit=K)
@@ -140,14 +143,15 @@ def test_fixed_iterations_match_oracle(L, scheme, shape, prec):
     assert rel(hist, np.array(ref.history)) < (1e-9 if prec == "f64" else 1e-3)
 
 
-@pytest.mark.parametrize("scheme", ["basic", "fb", "afb"])
-def test_converged_matches_oracle_fp64(L, scheme):
+@pytest.mark.parametrize("scheme,form", [("basic", "auto"), ("fb", "strain"), ("fb", "displacement"),
+                                         ("afb", "strain"), ("afb", "displacement")])
+def test_converged_matches_oracle_fp64(L, scheme, form):
     shape = (16, 16, 16)
-    print(f"\n[converged] scheme={scheme}", flush=True)
+    print(f"\n[converged] scheme={scheme} form={form}", flush=True)
     lam, mu = inputs.cubic_inclusion(16, 8, 1.0, 10.0)
     l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
     Eb = inputs.macro_strain("11", 1e-3)
-    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f64")
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f64", form=form)
     out = s.solve(Eb, tol=1e-8, maxit=2000)
     ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
                             tol=1e-8, maxit=2000)
