@@ -51,7 +51,8 @@ def algorithmic_bytes(kernel, n, esize, scheme="afb"):
     Strain form: the x-pass reads and writes the six-component spectrum and
     the strain and reads the two moduli.  Displacement form: the stencil
     kernel reads u and the moduli and writes the three-component spectrum of
-    div sigma; the update reads that spectrum and reads and writes u."""
+    div sigma; the update reads that spectrum and reads and writes u.  The
+    displacement u is held in FP64 in both precisions."""
     n1 = n2 = n3 = n
     N = n1 * n2 * n3
     half = n3 * n2 * (n1 // 2 + 1) * 2 * esize  # one component of the half spectrum
@@ -61,8 +62,8 @@ def algorithmic_bytes(kernel, n, esize, scheme="afb"):
         "k_ypass(forward)": 2 * spec6,
         "k_ypass(inverse)": 2 * spec6,
         "k_zpass": 2 * spec6 + (21 * half // 2 if scheme == "dgo" else 0),
-        "k_stencil": 3 * N * esize + 2 * N * esize + spec3,
-        "k_uxpass": spec3 + 2 * 3 * N * esize,
+        "k_stencil": 3 * N * 8 + 2 * N * esize + spec3,
+        "k_uxpass": spec3 + 2 * 3 * N * 8,
         "k_zpass_u": 2 * spec3,
         "k_ypass(forward)/3": 2 * spec3,
         "k_ypass(inverse)/3": 2 * spec3,

@@ -20,6 +20,14 @@
 // conj(q^FD) = -q^BD), K = mu0 |a|^2 I + mu0 a (x) conj(a) + lam0 conj(a) (x) a.
 // The equilibrium residual needs no spectrum: sum_xi |sigma_hat q^b|^2 =
 // N sum_x |f(x)|^2 (Parseval), accumulated in FP64 by k_stencil.
+//
+// Precision: u is stored and accumulated in FP64 whatever the solver
+// precision T.  u grows like |eps| n h, so a T-rounded u would lose about
+// log2(n) bits of the strain taken from its differences, and that rounding
+// would build up over the iterations.  The stencils take exact FP64
+// differences of neighbouring nodes and round those to T (the LDS variant
+// forms the whole gradient in FP64); sigma, f, the transforms and the Green
+// step run in T, with rounding relative to the strain and stress themselves.
 #pragma once
 #include "kernels.hpp"
 
@@ -102,7 +110,7 @@ __device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, int i1
 // ---------------------------------------------------------------- u update (x-lines)
 template <typename T> struct UArgs {
   Dims d;
-  T *u;               // [3][n3][n2][n1]
+  double *u;          // [3][n3][n2][n1], FP64 whatever T
   const cplx<T> *spec;
   const cplx<T> *nyq;
   const cplx<T> *tw;  // exp(-2 pi i m / n1)
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   const cplx<T> zero{T(0), T(0)};
   cplx<T> w[3][E];
   cplx<T> xn[3];
-  T uo[3][E][2];
+  double uo[3][E][2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
     for (int e = 0; e < E; ++e) {
       const long long idx = row * n1 + 2 * (t + TPC * e);
       if (valid) ld2(a.u + c * N + idx, uo[c][e][0], uo[c][e][1]);
-      else uo[c][e][0] = uo[c][e][1] = T(0);
+      else uo[c][e][0] = uo[c][e][1] = 0.0;
     }
 #pragma unroll
   for (int c = 0; c < 3; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, a.tw, buf);
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const long long idx = row * n1 + 2 * (t + TPC * e);
-        st2(a.u + c * N + idx, uo[c][e][0] + w[c][e].x, uo[c][e][1] + w[c][e].y);
+        st2(a.u + c * N + idx, uo[c][e][0] + (double)w[c][e].x, uo[c][e][1] + (double)w[c][e].y);
       }
   }
 }
@@ -161,19 +169,22 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
 // One workgroup owns output node lines y in [y0, y0 + T2) for planes
 // z in [z0, z0 + Z) and marches along z.  LDS holds two u planes over the
 // node lines [y0-1, y0+T2], two sigma planes over the cell lines
-// [y0-1, y0+T2), and the divergence f of the current plane.  A cell (c1, c2, c3)
+// [y0-1, y0+T2), and the divergence f of the current plane (u planes in
+// FP64, sigma and f in T).  A cell (c1, c2, c3)
 // has corners (c1..c1+1, c2..c2+1, c3..c3+1); node n gathers the cells
 // n - {0,1}^3 (all indices periodic).
 template <typename T> struct SArgs {
   Dims d;
-  const T *u;
+  const double *u;     // FP64 displacement
   const T *lam;
   const T *mu;
   cplx<T> *spec;
   cplx<T> *nyq;
   const cplx<T> *tw;   // exp(-2 pi i m / n1)
-  T Eb[6];
-  T ih[3];             // 1 / h_r
+  double Eb[6];
+  double hE[3][3];     // h_j Ebar_ij: the macroscopic part of an edge difference
+  double ihu[3];       // 1 / h_r for the FP64 gradient
+  T ih[3];             // 1 / h_r for the divergence
   double *partial;     // [gridDim.x][8]: 6 stress sums, sum |f|^2
   const State *st;
   int Z;               // planes per workgroup
@@ -209,6 +220,22 @@ template <> struct Stencil<SCHEME_AFB> {
   }
 };
 
+// The same AFB gradient from edge differences of the cell (x, l) between
+// planes z (a) and z+1 (b): dx = u(x+1) - u(x) on lines l, l+1 of each plane,
+// dy = u(l+1) - u(l) of the own column on each plane, dz = u(z+1) - u(z) of
+// the own column on lines l, l+1.  The neighbour column's y and z
+// differences follow from dy(x+1) = dy + dx(l+1) - dx(l) and dz(x+1) =
+// dz + dx_b - dx_a, so no FP64 corner value is needed once the exact
+// differences are taken.  The identities hold as well for differences of the
+// total displacement u + Ebar x.
+template <typename T>
+__device__ __forceinline__ void afb_grad_edges(T dxa0, T dxa1, T dxb0, T dxb1, T dya, T dyb, T dz0, T dz1,
+                                               const T (&ih)[3], T (&gr)[3]) {
+  gr[0] = T(0.25) * ih[0] * ((dxa0 + dxa1) + (dxb0 + dxb1));
+  gr[1] = T(0.25) * ih[1] * (T(2) * (dya + dyb) + ((dxa1 - dxa0) + (dxb1 - dxb0)));
+  gr[2] = T(0.25) * ih[2] * (T(2) * (dz0 + dz1) + ((dxb0 - dxa0) + (dxb1 - dxa1)));
+}
+
 // Forward difference (gradient) / backward difference (divergence).
 template <> struct Stencil<SCHEME_FB> {
   template <typename T>
@@ -225,6 +252,23 @@ template <> struct Stencil<SCHEME_FB> {
   }
 };
 
+// eps = Ebar + sym(gr) and sigma = lam tr(eps) I + 2 mu eps (Voigt order,
+// tensor components), all in FP64.  With a zero Ebar, gr is the gradient of
+// the total displacement.
+__device__ __forceinline__ void cell_stress(const double (&Eb)[6], const double (&gr)[3][3], double lm, double m2,
+                                            double (&sg)[6]) {
+  double e[6];
+  e[0] = Eb[0] + gr[0][0];
+  e[1] = Eb[1] + gr[1][1];
+  e[2] = Eb[2] + gr[2][2];
+  e[3] = Eb[3] + 0.5 * (gr[1][2] + gr[2][1]);
+  e[4] = Eb[4] + 0.5 * (gr[0][2] + gr[2][0]);
+  e[5] = Eb[5] + 0.5 * (gr[0][1] + gr[1][0]);
+  const double tr = e[0] + e[1] + e[2];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sg[c] = (c < 3 ? lm * tr : 0.0) + m2 * e[c];
+}
+
 template <typename T, int N1, int E, int SCHEME, int T2>
 __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   if (a.st && a.st->done) return;
@@ -238,7 +282,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   static_assert(6 * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
   static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
   static_assert(7 * 2 * L * 2 <= SPL, "transform scratch must fit in one sigma plane");
-  __shared__ T U[2 * UPL];
+  __shared__ double U[2 * UPL];
   __shared__ T S[2 * SPL];
   __shared__ T F[T2 * 3 * N1];
   __shared__ double red[(WG / 64) * 8];
@@ -249,6 +293,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   const int y0 = (blockIdx.x % ny_blocks) * T2;
   const int z0 = (blockIdx.x / ny_blocks) * a.Z;
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
+  const double ihu[3] = {a.ihu[0], a.ihu[1], a.ihu[2]};
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   // Software pipeline: the u plane z+2 and the moduli of cell plane z+1 are
@@ -256,14 +301,14 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   // used at the next step.
   constexpr int UQ = (UPL + WG - 1) / WG;          // u values per thread per plane
   constexpr int CQ = (NSL * N1 + WG - 1) / WG;     // cells per thread per plane
-  T ureg[UQ];
+  double ureg[UQ];
   T lreg[CQ], mreg[CQ];
   auto fetch_u = [&](int zz) {
     const int zg = ((zz % n3) + n3) % n3;
 #pragma unroll
     for (int j = 0; j < UQ; ++j) {
       const int q = tid + WG * j;
-      T v = T(0);
+      double v = 0.0;
       if (q < UPL && !a.zero_u) {
         const int x = q % N1;
         const int lc = q / N1;  // line * 3 + comp
@@ -313,8 +358,8 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
     __syncthreads();
     // ---- sigma at the cells of plane c3 = z, cell lines [y0-1, y0+T2)
     {
-      const T *U0 = U + (z & 1) * UPL;        // nodes at plane z
-      const T *U1 = U + ((z + 1) & 1) * UPL;  // nodes at plane z + 1
+      const double *U0 = U + (z & 1) * UPL;        // nodes at plane z
+      const double *U1 = U + ((z + 1) & 1) * UPL;  // nodes at plane z + 1
       T *Sp = S + (z & 1) * SPL;
 #pragma unroll
       for (int j = 0; j < CQ; ++j) {
@@ -322,11 +367,11 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
         if (q >= NSL * N1) break;
         const int x = q % N1, l = q / N1;
         const int x1 = (x + 1) % N1;
-        const T lm = lcur[j], m2 = T(2) * mcur[j];
-        T gr[3][3];  // gr[i][j] = d u_i / d x_j
+        const double lm = (double)lcur[j], m2 = 2.0 * (double)mcur[j];
+        double gr[3][3];  // gr[i][j] = d u_i / d x_j
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T cv[2][2][2];
+          double cv[2][2][2];
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             const int base = ((l + b) * 3 + c) * N1;
@@ -335,24 +380,15 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
             cv[0][b][1] = U1[base + x];
             cv[1][b][1] = U1[base + x1];
           }
-          Stencil<SCHEME>::grad(cv, ih, gr[c]);
+          Stencil<SCHEME>::grad(cv, ihu, gr[c]);
         }
-        T e[6];
-        e[0] = a.Eb[0] + gr[0][0];
-        e[1] = a.Eb[1] + gr[1][1];
-        e[2] = a.Eb[2] + gr[2][2];
-        e[3] = a.Eb[3] + T(0.5) * (gr[1][2] + gr[2][1]);
-        e[4] = a.Eb[4] + T(0.5) * (gr[0][2] + gr[2][0]);
-        e[5] = a.Eb[5] + T(0.5) * (gr[0][1] + gr[1][0]);
-        const T tr = e[0] + e[1] + e[2];
-        T sg[6];
+        double sg[6];
+        cell_stress(a.Eb, gr, lm, m2, sg);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sg[c] = (c < 3 ? lm * tr : T(0)) + m2 * e[c];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) Sp[(l * 6 + c) * N1 + x] = sg[c];
+        for (int c = 0; c < 6; ++c) Sp[(l * 6 + c) * N1 + x] = (T)sg[c];
         if (l >= 1 && z >= z0) {
 #pragma unroll
-          for (int c = 0; c < 6; ++c) sums[c] += (double)sg[c];
+          for (int c = 0; c < 6; ++c) sums[c] += sg[c];
         }
       }
     }
@@ -426,6 +462,259 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   }
 }
 
+// Register-resident variant for power-of-two n1: every thread owns fixed x
+// columns (XV of them) of one y-group and keeps its own u planes (z, z+1) and
+// sigma planes (z-1, z) in registers; LDS only carries the column exchange
+// with the x +- 1 neighbours, the f lines and the transform scratch.  A
+// workgroup holds G = 256 / n1 independent y-groups when n1 < 256.  The FP64
+// u exchange is single-buffered: each plane is published once and the
+// neighbour column it yields is kept in registers for the next step.
+#ifndef LSFFT_STENCIL_WAVES
+#define LSFFT_STENCIL_WAVES 1
+#endif
+template <typename T, int N1, int E, int SCHEME, int T2>
+__global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<T> a) {
+  if (a.st && a.st->done) return;
+  constexpr int WG = 256;
+  constexpr int L = N1 / 2;
+  constexpr int TPC = L / E;
+  constexpr int G = N1 >= WG ? 1 : WG / N1;     // y-groups per workgroup
+  constexpr int XV = N1 >= WG ? N1 / WG : 1;    // x columns per thread
+  constexpr int NX = N1 / XV;                    // threads per group
+  constexpr int NUL = T2 + 2, NSL = T2 + 1;
+  constexpr int UX = G * NUL * 3 * N1;           // the exchanged u plane (FP64)
+  constexpr int SX = G * NSL * 6 * N1;           // one exchanged sigma plane
+  constexpr int NPEN = G * T2 * 3;
+  static_assert(G * NX == WG, "n1 must be a power of two");
+  static_assert(NPEN * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
+  static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
+  static_assert((NPEN + 1) * 2 * L * 2 <= SX, "transform scratch must fit in one sigma plane");
+  __shared__ double Ux[UX];
+  __shared__ T Sx[2 * SX];
+  __shared__ T F[G * T2 * 3 * N1];
+  __shared__ double red[(WG / 64) * 8];
+  const int tid = threadIdx.x;
+  const int n2 = a.d.n2, n3 = a.d.n3;
+  const long long N = a.d.N;
+  const int ny_blocks = (n2 + G * T2 - 1) / (G * T2);
+  const int g = tid / NX, xt = tid % NX;
+  const int yg0 = (blockIdx.x % ny_blocks) * G * T2 + g * T2;
+  const bool gvalid = yg0 < n2;
+  const int z0 = (blockIdx.x / ny_blocks) * a.Z;
+  const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
+  double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bool load_u = gvalid && !a.zero_u;
+
+  // own columns (FP64): ub = plane z+1, un = plane z+2 in flight.  Edge
+  // differences of the TOTAL displacement u + Ebar x, exact in FP64, then
+  // rounded to T: dxa / dxb = x differences (neighbour - own) on planes
+  // z / z+1, dya / dyb = y differences on planes z / z+1, dz = z differences
+  // between planes z and z+1.  Their rounding is relative to the local total
+  // strain (and rotation), which is small in a stiff phase, where
+  // Ebar + grad u would cancel.
+  double ub[XV][NUL][3], un[XV][NUL][3];
+  T dxa[XV][NUL][3], dxb[XV][NUL][3];
+  T dya[XV][NSL][3], dyb[XV][NSL][3];
+  T dz[XV][NUL][3];
+  T sa[XV][NSL][6], sb[XV][NSL][6];
+  T lr[XV][NSL], mr[XV][NSL];
+  auto fetch_u = [&](int zz) {
+    const int zg = ((zz % n3) + n3) % n3;
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+#pragma unroll
+      for (int l = 0; l < NUL; ++l) {
+        const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
+        const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) un[v][l][c] = load_u ? a.u[c * N + gi] : 0.0;
+      }
+  };
+  auto fetch_lm = [&](int zz) {
+    const int zg = ((zz % n3) + n3) % n3;
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+#pragma unroll
+      for (int l = 0; l < NSL; ++l) {
+        const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
+        const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
+        lr[v][l] = gvalid ? a.lam[gi] : T(1);
+        mr[v][l] = gvalid ? a.mu[gi] : T(1);
+      }
+  };
+  auto ux_at = [&](int l, int c, int x) -> double & { return Ux[((g * NUL + l) * 3 + c) * N1 + x]; };
+  auto sx_at = [&](int pb, int l, int c, int x) -> T & { return Sx[pb * SX + ((g * NSL + l) * 6 + c) * N1 + x]; };
+  // ub becomes plane z+1: its y differences, then publish it and take the
+  // x differences against the x+1 neighbour column
+  auto take_plane = [&]() {
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+#pragma unroll
+      for (int l = 0; l < NSL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dyb[v][l][c] = (T)((ub[v][l + 1][c] - ub[v][l][c]) + a.hE[c][1]);
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+#pragma unroll
+      for (int l = 0; l < NUL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ux_at(l, c, xt + NX * v) = ub[v][l][c];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int x1 = (xt + NX * v + 1) % N1;
+#pragma unroll
+      for (int l = 0; l < NUL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dxb[v][l][c] = (T)((ux_at(l, c, x1) - ub[v][l][c]) + a.hE[c][0]);
+    }
+  };
+
+  fetch_u(z0 - 1);
+#pragma unroll
+  for (int v = 0; v < XV; ++v)
+#pragma unroll
+    for (int l = 0; l < NUL; ++l)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ub[v][l][c] = un[v][l][c];
+  take_plane();
+  fetch_u(z0);
+  fetch_lm(z0 - 1);
+  __syncthreads();  // the neighbour reads above precede the first publish below
+  for (int z = z0 - 1; z < z0 + a.Z; ++z) {
+    // rotate: plane z+1 arrived in un
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+#pragma unroll
+      for (int l = 0; l < NUL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dz[v][l][c] = (T)((un[v][l][c] - ub[v][l][c]) + a.hE[c][2]);
+          ub[v][l][c] = un[v][l][c];
+          dxa[v][l][c] = dxb[v][l][c];
+        }
+#pragma unroll
+      for (int l = 0; l < NSL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dya[v][l][c] = dyb[v][l][c];
+    }
+    T lc[XV][NSL], mc[XV][NSL];
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+#pragma unroll
+      for (int l = 0; l < NSL; ++l) {
+        lc[v][l] = lr[v][l];
+        mc[v][l] = mr[v][l];
+      }
+    if (z + 2 <= z0 + a.Z) fetch_u(z + 2);
+    if (z + 1 < z0 + a.Z) fetch_lm(z + 1);
+    // The previous step's last reads of Ux (its own exchange) and of the
+    // sigma plane reused here (its transform scratch) precede at least one
+    // barrier of that step or of this exchange.
+    take_plane();
+    // ---- sigma at the cells (x, lines 0..NSL-1, plane z) of this thread
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int x = xt + NX * v;
+#pragma unroll
+      for (int l = 0; l < NSL; ++l) {
+        double gr[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T g3[3];
+          if constexpr (SCHEME == SCHEME_AFB) {
+            afb_grad_edges(dxa[v][l][c], dxa[v][l + 1][c], dxb[v][l][c], dxb[v][l + 1][c], dya[v][l][c],
+                           dyb[v][l][c], dz[v][l][c], dz[v][l + 1][c], ih, g3);
+          } else {
+            g3[0] = ih[0] * dxa[v][l][c];
+            g3[1] = ih[1] * dya[v][l][c];
+            g3[2] = ih[2] * dz[v][l][c];
+          }
+#pragma unroll
+          for (int j = 0; j < 3; ++j) gr[c][j] = (double)g3[j];
+        }
+        double sg[6];
+        constexpr double zero6[6] = {0, 0, 0, 0, 0, 0};
+        cell_stress(zero6, gr, (double)lc[v][l], 2.0 * (double)mc[v][l], sg);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sa[v][l][c] = sb[v][l][c];
+          sb[v][l][c] = (T)sg[c];
+          sx_at(z & 1, l, c, x) = sb[v][l][c];
+          if (gvalid && l >= 1 && z >= z0) sums[c] += sg[c];
+        }
+      }
+    }
+    __syncthreads();
+    if (z < z0) continue;
+    // ---- f = div sigma at the nodes (x, lines 0..T2-1, plane z)
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int x = xt + NX * v;
+      const int xm = (x + N1 - 1) % N1;
+#pragma unroll
+      for (int m = 0; m < T2; ++m) {
+        T f3[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T acc = T(0);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int c = voigt(i, j);
+            T sv[2][2][2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int l = m + 1 - b;
+              sv[0][b][0] = sb[v][l][c];
+              sv[0][b][1] = sa[v][l][c];
+              sv[1][b][0] = sx_at(z & 1, l, c, xm);
+              sv[1][b][1] = sx_at((z - 1) & 1, l, c, xm);
+            }
+            acc += Stencil<SCHEME>::div(sv, j, ih);
+          }
+          f3[i] = acc;
+          F[((g * T2 + m) * 3 + i) * N1 + x] = acc;
+        }
+        if (gvalid) sums[6] += (double)f3[0] * f3[0] + (double)f3[1] * f3[1] + (double)f3[2] * f3[2];
+      }
+    }
+    __syncthreads();
+    // ---- forward x transforms of the G x T2 x 3 f lines; scratch in the free sigma plane
+    {
+      const int pid = tid / TPC, t = tid % TPC;
+      const bool act = pid < NPEN;
+      const int pg = act ? pid / (T2 * 3) : 0;
+      const int m = act ? (pid / 3) % T2 : 0, c = act ? pid % 3 : 0;
+      cplx<T> vv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int xx = 2 * (t + TPC * e);
+        const int o = ((pg * T2 + m) * 3 + c) * N1 + xx;
+        vv[e] = act ? cplx<T>{F[o], F[o + 1]} : cplx<T>{T(0), T(0)};
+      }
+      cplx<T> *scr = reinterpret_cast<cplx<T> *>(Sx + ((z - 1) & 1) * SX) + (act ? pid : NPEN) * 2 * L;
+      int buf = 0;
+      const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, a.tw, buf);
+      const int yrow = (blockIdx.x % ny_blocks) * G * T2 + pg * T2 + m;
+      if (act && yrow < n2) {
+        const long long row = (long long)(z % n3) * n2 + yrow;
+        cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[t + TPC * e] = vv[e];
+        if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xnq;
+      }
+    }
+  }
+  if (a.partial) {
+    block_sum<WG>(sums, 7, red);
+    if (tid == 0) {
+      double *dst = a.partial + (long long)blockIdx.x * 8;
+      for (int i = 0; i < 7; ++i) dst[i] = sums[i];
+      dst[7] = 0.0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- z pass, displacement form
 template <typename T, int NZ, int E, int P>
 __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
@@ -483,19 +772,20 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------- outputs
-// eps = Ebar + sym(grad^a u) at every cell, straight from global memory.
+// eps = Ebar + sym(grad^a u) at every cell, straight from global memory
+// (FP64 arithmetic, stored in T).
 template <typename T, int SCHEME>
-__global__ void k_strain_from_u(const T *__restrict__ u, T *__restrict__ eps, Dims d, T e0, T e1, T e2, T e3,
-                                T e4, T e5, T ih0, T ih1, T ih2) {
-  const T ih[3] = {ih0, ih1, ih2};
+__global__ void k_strain_from_u(const double *__restrict__ u, T *__restrict__ eps, Dims d, double e0, double e1,
+                                double e2, double e3, double e4, double e5, double ih0, double ih1, double ih2) {
+  const double ih[3] = {ih0, ih1, ih2};
   const long long N = d.N;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     const int x = (int)(i % d.n1);
     const long long r = i / d.n1;
     const int y = (int)(r % d.n2), z = (int)(r / d.n2);
-    T gr[3][3];
+    double gr[3][3];
     for (int c = 0; c < 3; ++c) {
-      T cv[2][2][2];
+      double cv[2][2][2];
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
           for (int dd = 0; dd < 2; ++dd) {
@@ -504,12 +794,12 @@ __global__ void k_strain_from_u(const T *__restrict__ u, T *__restrict__ eps, Di
           }
       Stencil<SCHEME>::grad(cv, ih, gr[c]);
     }
-    eps[i] = e0 + gr[0][0];
-    eps[N + i] = e1 + gr[1][1];
-    eps[2 * N + i] = e2 + gr[2][2];
-    eps[3 * N + i] = e3 + T(0.5) * (gr[1][2] + gr[2][1]);
-    eps[4 * N + i] = e4 + T(0.5) * (gr[0][2] + gr[2][0]);
-    eps[5 * N + i] = e5 + T(0.5) * (gr[0][1] + gr[1][0]);
+    eps[i] = (T)(e0 + gr[0][0]);
+    eps[N + i] = (T)(e1 + gr[1][1]);
+    eps[2 * N + i] = (T)(e2 + gr[2][2]);
+    eps[3 * N + i] = (T)(e3 + 0.5 * (gr[1][2] + gr[2][1]));
+    eps[4 * N + i] = (T)(e4 + 0.5 * (gr[0][2] + gr[2][0]));
+    eps[5 * N + i] = (T)(e5 + 0.5 * (gr[0][1] + gr[1][0]));
   }
 }
 

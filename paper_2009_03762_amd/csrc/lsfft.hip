@@ -51,10 +51,20 @@ constexpr int XWG = 256;
 constexpr int es_of(int L) {
   return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
 }
-// LDS of the stencil kernel: two u planes (4 lines x 3), two sigma planes
-// (3 lines x 6) and the f lines (2 x 3) of n1 values each.
-template <typename T> constexpr bool stencil_fits(int n1) { return 66LL * n1 * (long long)sizeof(T) <= 150000; }
-constexpr int ST2 = 2;
+#ifndef LSFFT_ST2
+#define LSFFT_ST2 2
+#endif
+constexpr int ST2 = LSFFT_ST2;
+constexpr bool stencil_reg_kernel(int n1) { return (n1 & (n1 - 1)) == 0 && n1 >= 8; }
+// LDS of the stencil kernels (n1 values per line): the register-resident one
+// holds one FP64 u plane (T2+2 lines x 3) per y-group, two sigma planes
+// (T2+1 lines x 6) and the f lines (T2 x 3); the other one two u planes.
+template <typename T> constexpr long long stencil_lds(int n1) {
+  const long long G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
+  const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
+  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + 256;
+}
+template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
 
 bool supported_len(int n) {
   if (n < 4 || n > 512 || (n & 1)) return false;
@@ -131,7 +141,7 @@ struct lsfft_solver_s {
   void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
   void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
   void *dgo_main = nullptr, *dgo_nyq = nullptr;
-  void *u = nullptr;      // displacement (FB, AFB): [3][n3][n2][n1]
+  void *u = nullptr;      // displacement (FB, AFB): [3][n3][n2][n1], FP64 in both precisions
   int disp = 0;           // 1: displacement-form path with real-space stencils
   int sZ = 0, nsb = 0, nub = 0;
   double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
@@ -266,7 +276,11 @@ template <typename T> struct Launch {
     switch (s->n[0]) {
 #define SCASE(Lv)                                                                                      \
   case 2 * Lv:                                                                                         \
-    if constexpr (stencil_fits<T>(2 * Lv)) {                                                           \
+    if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
+      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid), dim3(256), \
+                         0, s->stream, a);                                                             \
+      return hipGetLastError();                                                                        \
+    } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
       hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid), dim3(256), 0, \
                          s->stream, a);                                                                \
       return hipGetLastError();                                                                        \
@@ -405,14 +419,19 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
 template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, const double Eb[6], int zero_u) {
   lsfft::SArgs<T> a;
   a.d = s->d;
-  a.u = (const T *)s->u;
+  a.u = (const double *)s->u;
   a.lam = (const T *)s->lam;
   a.mu = (const T *)s->mu;
   a.spec = (cplx<T> *)s->spec;
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
-  for (int c = 0; c < 6; ++c) a.Eb[c] = (T)Eb[c];
-  for (int r = 0; r < 3; ++r) a.ih[r] = (T)(1.0 / s->h[r]);
+  for (int c = 0; c < 6; ++c) a.Eb[c] = Eb[c];
+  static const int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  for (int r = 0; r < 3; ++r) {
+    a.ihu[r] = 1.0 / s->h[r];
+    a.ih[r] = (T)(1.0 / s->h[r]);
+    for (int i = 0; i < 3; ++i) a.hE[i][r] = s->h[r] * Eb[vo[i][r]];
+  }
   a.partial = s->px;
   a.st = s->st;
   a.Z = s->sZ;
@@ -423,7 +442,7 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, const double Eb[6], 
 template <typename T> lsfft::UArgs<T> uargs(lsfft_solver s) {
   lsfft::UArgs<T> a;
   a.d = s->d;
-  a.u = (T *)s->u;
+  a.u = (double *)s->u;
   a.spec = (const cplx<T> *)s->spec;
   a.nyq = (const cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
@@ -433,15 +452,15 @@ template <typename T> lsfft::UArgs<T> uargs(lsfft_solver s) {
 
 template <typename T> hipError_t strain_from_u(lsfft_solver s, const double Eb[6]) {
   const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
-  const T ih0 = (T)(1.0 / s->h[0]), ih1 = (T)(1.0 / s->h[1]), ih2 = (T)(1.0 / s->h[2]);
+  const double ih0 = 1.0 / s->h[0], ih1 = 1.0 / s->h[1], ih2 = 1.0 / s->h[2];
   if (s->scheme == LSFFT_FB)
     hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_FB>), dim3(blocks), dim3(256), 0, s->stream,
-                       (const T *)s->u, (T *)s->eps, s->d, (T)Eb[0], (T)Eb[1], (T)Eb[2], (T)Eb[3], (T)Eb[4],
-                       (T)Eb[5], ih0, ih1, ih2);
+                       (const double *)s->u, (T *)s->eps, s->d, Eb[0], Eb[1], Eb[2], Eb[3], Eb[4], Eb[5], ih0,
+                       ih1, ih2);
   else
     hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_AFB>), dim3(blocks), dim3(256), 0, s->stream,
-                       (const T *)s->u, (T *)s->eps, s->d, (T)Eb[0], (T)Eb[1], (T)Eb[2], (T)Eb[3], (T)Eb[4],
-                       (T)Eb[5], ih0, ih1, ih2);
+                       (const double *)s->u, (T *)s->eps, s->d, Eb[0], Eb[1], Eb[2], Eb[3], Eb[4], Eb[5], ih0,
+                       ih1, ih2);
   return hipGetLastError();
 }
 
@@ -466,8 +485,8 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
   LSFFT_CHECK(hipGetLastError());
   if (disp) {
     const long long nu = 3 * s->d.N;
-    hipLaunchKernelGGL(lsfft::k_fill_zero<T>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
-                       dim3(256), 0, s->stream, (T *)s->u, nu);
+    hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
+                       dim3(256), 0, s->stream, (double *)s->u, nu);
     LSFFT_CHECK(hipGetLastError());
     Timed tm(s, 0);
     LSFFT_CHECK(L::stencil(s, sargs<T>(s, Eb, 1), s->nsb));
@@ -786,17 +805,22 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
     s->disp = (cfg->form == 1) ? 0 : (fits ? 1 : 0);
   }
   if (s->disp) {
-    if (hipMalloc(&s->u, 3 * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->u, 3 * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    // y-blocks: a power-of-two n1 < 256 packs 256/n1 independent y-groups per workgroup
+    const int n1 = s->n[0];
+    const bool pow2 = stencil_reg_kernel(n1);
+    const int G = (pow2 && n1 < 256) ? 256 / n1 : 1;
+    const int ny = (s->n[1] + G * ST2 - 1) / (G * ST2);
     // planes per stencil workgroup: as many as keep >= 1024 workgroups, at least 2
     int Z = 2;
     for (int c : {32, 16, 8, 4}) {
-      if (s->n[2] % c == 0 && (long long)(s->n[1] / ST2) * (s->n[2] / c) >= 1024) {
+      if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) >= 1024) {
         Z = c;
         break;
       }
     }
     s->sZ = Z;
-    s->nsb = (s->n[1] / ST2) * (s->n[2] / Z);
+    s->nsb = ny * (s->n[2] / Z);
     s->nub = s->nxb;
   }
   if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)std::max(s->nxb, s->nsb)) != hipSuccess)
