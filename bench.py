@@ -4,14 +4,22 @@ Workload: 256^3 periodic cell, centred cubic inclusion of side 128 voxels
 (sharp interface), inclusion/matrix Young's modulus 1e3 / 1, nu = 0.3 in both
 phases, reference medium C0 = mean of the phase Lame moduli, macroscopic
 shear eps_12 = 1e-3, PCD discretisation, AFB (= rotated) scheme.  One step is
-one full fixed-point iteration (x-pass with Hooke, forward y, z-pass with the
-Green step and residual, reduction, inverse y).  The tolerance is 0, so
-exactly `--steps` iterations run; inputs are resident in HBM before timing.
+one full fixed-point iteration; in the default displacement form: the stencil
+kernel (strain from u, Hooke, divergence, forward x transform), forward y,
+z-pass with the Green step, reduction of residual and mean stress, inverse y,
+and the displacement update with the inverse x transform (`--form strain`:
+x-pass with the strain update, Hooke and both x transforms, forward y, z-pass
+with the Green step, reduction, inverse y).  The tolerance is 0, so exactly
+`--steps` iterations run; inputs are resident in HBM before timing.
 
 Prints one JSON line: value = GVoxel-iterations/s of the FP32 path (FP32
 transforms and Green step, FP64 reductions); the FP64 path is reported under
 "fp64".  "roofline" is for the dominant kernel, timed with HIP events on the
-solver's stream inside the timed region.
+solver's stream inside the timed region.  "equal_accuracy" gives, for the
+FP64 path and the FP32 paths (displacement form, the same with five FP64
+warm-start iterations, strain form), the iterations and wall time needed to bring
+the strain field within a relative L2 error of 1e-5 and 1e-6 of a tight FP64
+solution, and the FP32 speedups at equal accuracy.
 """
 from __future__ import annotations
 
@@ -171,7 +179,65 @@ def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
     return res
 
 
-def cpu_baseline(n=128, iters=2):
+def equal_accuracy(n, targets=(1e-5, 1e-6), kmax=500, kstep=10):
+    """Iterations and wall time each path needs to bring the strain field to a
+    relative L2 error `target` against a tight FP64 solution (equilibrium
+    residual 1e-10) of the same workload, every error measured on the GPU."""
+    import torch
+
+    from paper_2009_03762_amd import lsfft
+    lam, mu, l0, m0, Eb = workload(n)
+    shape = (6, n, n, n)
+    ref = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec="f64", form="displacement")
+    r = s.solve_device(Eb, tol=1e-10, maxit=2000, eps_dev=ref)
+    s.close()
+    rn = torch.linalg.vector_norm(ref).item()
+    out = {"reference": f"FP64 displacement form stopped at r = {r['residual']:.2e} after {r['iters']} iterations",
+           "metric": "relative L2 error of the strain field", "paths": {}}
+    print(f"[bench] accuracy reference: {out['reference']}", file=sys.stderr, flush=True)
+    for name, prec, form, warm in (("f64", "f64", "displacement", 0), ("f32", "f32", "displacement", 0),
+                                   ("f32_warm5", "f32", "displacement", 5), ("f32_strain", "f32", "strain", 0)):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        e = torch.zeros(shape, dtype=dt, device="cuda")
+        s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec, form=form, f64_warmup=warm)
+        s.solve_device(Eb, tol=0.0, maxit=5, eps_dev=e)
+        found = {}
+        curve = []
+        k = kstep
+        while k <= kmax and len(found) < len(targets):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_device(Eb, tol=0.0, maxit=k, eps_dev=e)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            err = (torch.linalg.vector_norm(e.double() - ref) / rn).item()
+            curve.append((k, err))
+            for t in targets:
+                if t not in found and err <= t:
+                    found[t] = {"iters": k, "ms": ms, "field_err": err}
+            k += kstep
+        s.close()
+        del e
+        out["paths"][name] = {"form": form, "prec": prec, "f64_warmup_iters": warm,
+                              "targets": {f"{t:g}": found.get(t) for t in targets},
+                              "err_curve": [[k, float(f"{v:.3e}")] for k, v in curve]}
+        print(f"[bench] accuracy {name}: {out['paths'][name]['targets']}", file=sys.stderr, flush=True)
+    speed = {}
+    for t in targets:
+        key = f"{t:g}"
+        base = out["paths"]["f64"]["targets"][key]
+        for name in ("f32", "f32_warm5", "f32_strain"):
+            got = out["paths"][name]["targets"][key]
+            if base and got:
+                speed[f"{name}@{key}"] = base["ms"] / got["ms"]
+    out["speedup_over_f64"] = speed
+    del ref
+    torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(n=128, iters=8):
     """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
     full iterations after setup, single-threaded numpy."""
     code = f"""
@@ -229,6 +295,7 @@ def main():
     ap.add_argument("--prec", choices=["f32", "f64", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
     args = ap.parse_args()
@@ -271,6 +338,8 @@ def main():
         line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
                                                "bytes_per_voxel_iteration", "kernels")}
         line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
+    if not args.no_accuracy:
+        line["equal_accuracy"] = equal_accuracy(args.size)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

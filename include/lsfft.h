@@ -74,7 +74,7 @@ typedef enum {
 } lsfft_status;
 
 typedef struct {
-  int32_t n[3];            /* n1 (fastest), n2, n3: each even, 2^a 3^b, 4..512  */
+  int32_t n[3];            /* n1 (fastest), n2, n3: each 2^a or 3*2^a, 4..512  */
   double h[3];             /* grid spacing per axis; 0 means 1.0               */
   const double *lambda;    /* N Lame lambda values, HOST memory, field layout  */
   const double *mu;        /* N shear moduli mu, HOST memory, field layout     */
@@ -94,7 +94,17 @@ typedef struct {
                               divergence applied as real-space stencils, three
                               transformed components; identical iterates).
                               Automatic picks 2 when its workgroup fits in LDS
-                              (n1 <= 512 in F32, n1 <= 256 in F64).           */
+                              (every n1 in F32, n1 <= 256 in F64).           */
+  int32_t f64_warmup;      /* F32 displacement form with n1 <= 256 only (else
+                              ignored): run the first f64_warmup iterations of
+                              every solve in FP64 on the same displacement
+                              (identical iterates up to rounding), then
+                              continue in F32.  FP32 rounding of the large
+                              early updates otherwise leaves an error of order
+                              1e-6 (relative, at contrast 1e3) that only the
+                              slowest modes of the iteration remove.  0 = off;
+                              < 0 is EINVAL.  Costs the memory of an F64
+                              solver.                                          */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda

@@ -66,12 +66,12 @@ template <typename T> constexpr long long stencil_lds(int n1) {
 }
 template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
 
+// The transform lengths the kernels are instantiated for: 2^a or 3 * 2^a.
 bool supported_len(int n) {
   if (n < 4 || n > 512 || (n & 1)) return false;
   int m = n;
   while (m % 2 == 0) m /= 2;
-  while (m % 3 == 0) m /= 3;
-  return m == 1;
+  return m == 1 || m == 3;
 }
 
 // ------------------------------------------------------------------ tables
@@ -158,6 +158,12 @@ struct lsfft_solver_s {
   size_t ev_used = 0;
   double timing_mean = 0.0;
   int timing_count = 0;
+  // FP64 warm start of an F32 displacement-form solver: a second solver in
+  // F64 that borrows u, the device state and the residual history of this
+  // one and runs its first `warm` iterations.
+  lsfft_solver_s *twin = nullptr;
+  int warm = 0;
+  int borrowed = 0;  // u, st, st_host and hist belong to another solver
 };
 
 namespace {
@@ -464,32 +470,34 @@ template <typename T> hipError_t strain_from_u(lsfft_solver s, const double Eb[6
   return hipGetLastError();
 }
 
+// Iterations k_begin .. k_end-1 of a solve (maxit, tol as in lsfft_solve).
+// fresh: start from u = 0 / eps = Ebar with a new device state; otherwise the
+// state, history and u left by an earlier phase are continued (displacement
+// form), after re-evaluating the stencil on that u in this precision.
+// Returns LSFFT_OK when the iterations ran, even if the state is not done.
 template <typename T>
-lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit) {
+lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit, int k_begin, int k_end,
+                       bool fresh) {
   using L = Launch<T>;
-  if (maxit + 1 > s->hist_cap) {
-    if (s->hist) (void)hipFree(s->hist);
-    s->hist = nullptr;
-    int cap = maxit + 1 < 1024 ? 1024 : maxit + 1;
-    if (hipMalloc(&s->hist, sizeof(double) * cap) != hipSuccess) return LSFFT_ENOMEM;
-    s->hist_cap = cap;
-  }
-  s->ev_used = 0;
   double en = 0.0;
   for (int c = 0; c < 6; ++c) en += (c < 3 ? 1.0 : 2.0) * Eb[c] * Eb[c];
   en = std::sqrt(en);
   const bool dgo = (s->scheme == LSFFT_DGO);
   const bool disp = s->disp != 0;
   const int ncomp = disp ? 3 : 6;
-  hipLaunchKernelGGL(lsfft::k_state_init, dim3(1), dim3(1), 0, s->stream, s->st);
-  LSFFT_CHECK(hipGetLastError());
-  if (disp) {
-    const long long nu = 3 * s->d.N;
-    hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
-                       dim3(256), 0, s->stream, (double *)s->u, nu);
+  if (fresh) {
+    hipLaunchKernelGGL(lsfft::k_state_init, dim3(1), dim3(1), 0, s->stream, s->st);
     LSFFT_CHECK(hipGetLastError());
+  }
+  if (disp) {
+    if (fresh) {
+      const long long nu = 3 * s->d.N;
+      hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
+                         dim3(256), 0, s->stream, (double *)s->u, nu);
+      LSFFT_CHECK(hipGetLastError());
+    }
     Timed tm(s, 0);
-    LSFFT_CHECK(L::stencil(s, sargs<T>(s, Eb, 1), s->nsb));
+    LSFFT_CHECK(L::stencil(s, sargs<T>(s, Eb, fresh ? 1 : 0), s->nsb));
   } else {
     Timed tm(s, 0);
     LSFFT_CHECK(L::xpass(s, xargs<T>(s, Eb, lsfft::XMODE_INIT, nullptr, true), s->nxb));
@@ -515,10 +523,10 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
   ra.N = (double)s->d.N;
   ra.ebar_norm = en;
   ra.div_factor = 1e6;
-  int k = 0;
-  int chunk = (tol == 0.0) ? maxit + 1 : 2;
+  int k = k_begin;
+  int chunk = (tol == 0.0) ? k_end - k_begin : 2;
   for (;;) {
-    const int nenq = std::min(chunk, maxit + 1 - k);
+    const int nenq = std::min(chunk, k_end - k);
     for (int j = 0; j < nenq; ++j, ++k) {
       {
         Timed tm(s, 1);
@@ -545,8 +553,12 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
           Timed tm(s, 4);
           LSFFT_CHECK(L::uxpass(s, ua, s->nub));
         }
-        Timed tm(s, 0);
-        LSFFT_CHECK(L::stencil(s, sa, s->nsb));
+        // the last iteration of a phase leaves the stencil to the next one
+        // (at k = maxit the state is done and the stencil would return at once)
+        if (k + 1 < k_end) {
+          Timed tm(s, 0);
+          LSFFT_CHECK(L::stencil(s, sa, s->nsb));
+        }
       } else {
         Timed tm(s, 0);
         LSFFT_CHECK(L::xpass(s, xa, s->nxb));
@@ -554,11 +566,39 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
     }
     LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State), hipMemcpyDeviceToHost, s->stream));
     LSFFT_CHECK(hipStreamSynchronize(s->stream));
-    if (s->st_host->done || k > maxit) break;
+    if (s->st_host->done || k >= k_end) break;
     chunk = std::min(chunk * 2, 64);
   }
+  return LSFFT_OK;
+}
+
+template <typename T>
+lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit) {
+  if (maxit + 1 > s->hist_cap) {
+    if (s->hist) (void)hipFree(s->hist);
+    s->hist = nullptr;
+    int cap = maxit + 1 < 1024 ? 1024 : maxit + 1;
+    if (hipMalloc(&s->hist, sizeof(double) * cap) != hipSuccess) return LSFFT_ENOMEM;
+    s->hist_cap = cap;
+  }
+  s->ev_used = 0;
+  int k0 = 0;
+  if (s->twin && s->warm > 0) {
+    // FP64 iterations 0 .. k0-1 on the shared u, state and history
+    lsfft_solver t = s->twin;
+    t->hist = s->hist;
+    t->hist_cap = s->hist_cap;
+    t->timing_kernel = -1;
+    k0 = std::min(s->warm, maxit + 1);
+    lsfft_status ps = run_phase<double>(t, Eb, tol, maxit, 0, k0, true);
+    if (ps != LSFFT_OK) return ps;
+  }
+  if (k0 == 0 || (!s->st_host->done && k0 <= maxit)) {
+    lsfft_status ps = run_phase<T>(s, Eb, tol, maxit, k0, maxit + 1, k0 == 0);
+    if (ps != LSFFT_OK) return ps;
+  }
   if (!s->st_host->done) return LSFFT_EDEVICE;
-  if (disp) {
+  if (s->disp) {
     LSFFT_CHECK(strain_from_u<T>(s, Eb));
   }
   s->last_iters = s->st_host->iters;
@@ -671,6 +711,17 @@ template <typename T> lsfft_status build_dgo(lsfft_solver s) {
 }
 
 void release(lsfft_solver s) {
+  if (s->twin) {
+    release(s->twin);
+    delete s->twin;
+    s->twin = nullptr;
+  }
+  if (s->borrowed) {
+    s->u = nullptr;
+    s->st = nullptr;
+    s->st_host = nullptr;
+    s->hist = nullptr;
+  }
   void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->pstage, s->st, s->hist};
   for (void *p : ptrs)
@@ -747,6 +798,7 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   if (cfg->scheme < LSFFT_BASIC || cfg->scheme > LSFFT_DGO) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
   if (cfg->form < 0 || cfg->form > 2) return LSFFT_EINVAL;
+  if (cfg->f64_warmup < 0) return LSFFT_EINVAL;
   if (cfg->scheme == LSFFT_DGO) {
     if (cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
     if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
@@ -832,6 +884,24 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   if (s->scheme == LSFFT_DGO) {
     st = (s->prec == LSFFT_F32) ? build_dgo<float>(s) : build_dgo<double>(s);
     if (st != LSFFT_OK) return fail(st);
+  }
+  if (cfg->f64_warmup > 0 && s->prec == LSFFT_F32 && s->disp && stencil_fits<double>(s->n[0])) {
+    lsfft_config c2 = *cfg;
+    c2.prec = LSFFT_F64;
+    c2.form = 2;
+    c2.f64_warmup = 0;
+    lsfft_solver t = nullptr;
+    st = lsfft_create(&c2, &t);
+    if (st != LSFFT_OK) return fail(st);
+    (void)hipFree(t->u);
+    (void)hipFree(t->st);
+    (void)hipHostFree(t->st_host);
+    t->u = s->u;
+    t->st = s->st;
+    t->st_host = s->st_host;
+    t->borrowed = 1;
+    s->twin = t;
+    s->warm = cfg->f64_warmup;
   }
   *out = s;
   return LSFFT_OK;

@@ -40,6 +40,7 @@ class Config(C.Structure):
         ("dgo_weight_power", C.c_int32),
         ("stream", C.c_void_p),
         ("form", C.c_int32),
+        ("f64_warmup", C.c_int32),
     ]
 
 
@@ -112,7 +113,7 @@ FORMS = {"auto": 0, "strain": 1, "displacement": 2}
 
 
 def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None, form="auto"):
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
     """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
@@ -133,6 +134,7 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
     cfg.dgo_weight_power = int(dgo_weight_power)
     cfg.stream = _stream_handle(stream)
     cfg.form = FORMS[form] if isinstance(form, str) else int(form)
+    cfg.f64_warmup = int(f64_warmup)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:

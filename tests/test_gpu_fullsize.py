@@ -186,19 +186,20 @@ def test_converged_afb_contrast_1e3_fp64(L, contrast_1e3_oracle):
     assert rel(out["sig_mean"], ref.sig_mean) < 1e-9
 
 
-@pytest.mark.parametrize("form", ["displacement", "strain"])
-def test_fp32_accuracy_contrast_1e3(L, contrast_1e3_oracle, form):
+@pytest.mark.parametrize("form,warm", [("displacement", 0), ("strain", 0), ("displacement", 5)])
+def test_fp32_accuracy_contrast_1e3(L, contrast_1e3_oracle, form, warm):
     """FP32 at contrast 1e3: the fields reach the converged oracle solution
     within the FP32 bar although the equilibrium residual stalls at a floor
     of order u_32 x contrast (FP32 rounding feeds the slowest modes of the
     iteration, whose contraction factor with C0 = mean is about 0.998)."""
     lam, mu, l0, m0, Eb, ref = contrast_1e3_oracle
-    print(f"\n[fp32_1e3] form={form}", flush=True)
-    s = L.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec="f32", form=form)
+    print(f"\n[fp32_1e3] form={form} warm={warm}", flush=True)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec="f32", form=form, f64_warmup=warm)
     for K in (150, 400):   # no drift with more iterations
         out = s.solve(Eb, tol=0.0, maxit=K)
         assert out["iters"] == K
-        assert rel(out["eps"], ref.eps) < 1e-6, K
+        # the FP64 warm start removes the error the large early FP32 updates leave
+        assert rel(out["eps"], ref.eps) < (3e-7 if warm else 1e-6), K
         assert rel(out["sig_mean"], ref.sig_mean) < 1e-6, K
         assert out["residual"] < 1e-4, (K, out["residual"])
 

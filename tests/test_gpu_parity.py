@@ -207,3 +207,46 @@ def test_solve_device_matches_host(L):
     assert np.array_equal(e.cpu().double().numpy(), host["eps"])
     assert np.array_equal(g.cpu().double().numpy(), host["sig"])
     assert dev["iters"] == host["iters"] == 5
+
+
+@pytest.mark.parametrize("warm", [1, 5, 13])
+def test_f64_warmup_matches_oracle(L, warm):
+    """F32 solver with an FP64 warm start: iterations 0..warm-1 in FP64 on the
+    same displacement, the rest in FP32.  warm > maxit makes the whole solve
+    FP64, so it must meet the FP64 bar; otherwise the FP32 bar applies, and
+    the residual history is the FP64 one up to the switch."""
+    print(f"\n[f64_warmup] warm={warm}", flush=True)
+    K = 12
+    shape = (16, 16, 16)
+    lam, mu = inputs.cubic_inclusion(shape, (8, 8, 8), 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    Eb = np.array([1e-3, 2e-4, -1e-4, 3e-4, -2e-4, 5e-4])
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", f64_warmup=warm)
+    out = s.solve(Eb, tol=0.0, maxit=K)
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme="AFB", tol=0.0, maxit=K)
+    assert out["iters"] == K and out["status"] == L.ENOTCONV
+    hist = s.residual_history()
+    assert len(hist) == K + 1
+    h_ref = np.array(ref.history)
+    n64 = min(warm, K + 1)
+    assert rel(hist[:n64], h_ref[:n64]) < 1e-9
+    tol = 1e-12 if warm > K else 1e-5
+    # eps is stored in FP32 by an F32 solver: its rounding is the floor
+    assert rel(out["eps"], ref.eps) < max(tol, 1e-7)
+    assert rel(out["sig_mean"], ref.sig_mean) < max(tol, 1e-7)
+    s.close()
+
+
+def test_f64_warmup_converges_inside_warmup(L):
+    lam = np.full((8, 16, 16), 2.0)
+    mu = np.full((8, 16, 16), 1.5)
+    Eb = np.array([1e-3, 2e-4, -3e-4, 1e-4, 5e-5, 2e-4])
+    s = L.Solver(lam, mu, 1.0, 1.0, scheme="afb", prec="f32", form="displacement", f64_warmup=4)
+    out = s.solve(Eb, tol=1e-12, maxit=10)
+    assert out["status"] == L.OK and out["iters"] == 0
+    assert np.allclose(out["eps"], Eb[:, None, None, None], rtol=0, atol=1e-7 * np.max(np.abs(Eb)))
+    # a second solve on the same handle starts afresh
+    out2 = s.solve(2 * Eb, tol=1e-12, maxit=10)
+    assert out2["status"] == L.OK and out2["iters"] == 0
+    assert np.allclose(out2["eps"], 2 * Eb[:, None, None, None], rtol=0, atol=2e-7 * np.max(np.abs(Eb)))
+    s.close()

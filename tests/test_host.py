@@ -44,7 +44,8 @@ def _mat(shape, lam=1.0, mu=1.0):
     return np.full((n3, n2, n1), lam), np.full((n3, n2, n1), mu)
 
 
-@pytest.mark.parametrize("shape", [(10, 8, 8), (8, 7, 8), (8, 8, 1024), (2, 8, 8), (8, 8, 27)])
+@pytest.mark.parametrize("shape", [(10, 8, 8), (8, 7, 8), (8, 8, 1024), (2, 8, 8), (8, 8, 27), (18, 8, 8),
+                                   (8, 36, 8), (8, 8, 768)])
 def test_unsupported_sizes_rejected(L, shape):
     lam, mu = _mat(shape)
     with pytest.raises(L.LsfftError) as e:
@@ -65,7 +66,8 @@ def test_bad_moduli_rejected(L, lam, mu):
 @pytest.mark.parametrize("kw", [dict(lambda0=1.0, mu0=0.0), dict(lambda0=-1.0, mu0=1.0),
                                 dict(scheme="dgo", disc="td"), dict(scheme="dgo", disc="pcd", dgo_images=-1),
                                 dict(scheme="dgo", disc="pcd", dgo_weight_power=3),
-                                dict(scheme=7), dict(prec=5), dict(disc=4), dict(h=(1.0, -1.0, 1.0))])
+                                dict(scheme=7), dict(prec=5), dict(disc=4), dict(h=(1.0, -1.0, 1.0)),
+                                dict(form=3), dict(f64_warmup=-1)])
 def test_bad_config_rejected(L, kw):
     lam, mu = _mat((8, 8, 8))
     args = dict(lambda0=1.0, mu0=1.0)
