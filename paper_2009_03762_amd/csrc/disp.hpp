@@ -193,6 +193,16 @@ template <typename T> struct SArgs {
 
 template <int SCHEME> struct Stencil;
 
+// Tile of a stencil workgroup: y-blocks fastest, then z-blocks.  Each XCD
+// takes a contiguous range of tiles, so workgroups marching neighbouring
+// y-blocks side by side share their halo lines in that XCD's L2.
+#ifndef LSFFT_STENCIL_XCD
+#define LSFFT_STENCIL_XCD 1
+#endif
+__device__ __forceinline__ int stencil_tile() {
+  return LSFFT_STENCIL_XCD ? (int)xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+}
+
 // Average forward difference over the cell, eq. (36) carried to 3D.
 template <> struct Stencil<SCHEME_AFB> {
   template <typename T>
@@ -253,8 +263,7 @@ template <> struct Stencil<SCHEME_FB> {
 };
 
 // eps = Ebar + sym(gr) and sigma = lam tr(eps) I + 2 mu eps (Voigt order,
-// tensor components), all in FP64.  With a zero Ebar, gr is the gradient of
-// the total displacement.
+// tensor components), all in FP64.
 __device__ __forceinline__ void cell_stress(const double (&Eb)[6], const double (&gr)[3][3], double lm, double m2,
                                             double (&sg)[6]) {
   double e[6];
@@ -290,8 +299,9 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
   const int ny_blocks = n2 / T2;
-  const int y0 = (blockIdx.x % ny_blocks) * T2;
-  const int z0 = (blockIdx.x / ny_blocks) * a.Z;
+  const int tile = stencil_tile();
+  const int y0 = (tile % ny_blocks) * T2;
+  const int z0 = (tile / ny_blocks) * a.Z;
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
   const double ihu[3] = {a.ihu[0], a.ihu[1], a.ihu[2]};
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -497,10 +507,11 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
   const int ny_blocks = (n2 + G * T2 - 1) / (G * T2);
+  const int tile = stencil_tile();
   const int g = tid / NX, xt = tid % NX;
-  const int yg0 = (blockIdx.x % ny_blocks) * G * T2 + g * T2;
+  const int yg0 = (tile % ny_blocks) * G * T2 + g * T2;
   const bool gvalid = yg0 < n2;
-  const int z0 = (blockIdx.x / ny_blocks) * a.Z;
+  const int z0 = (tile / ny_blocks) * a.Z;
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bool load_u = gvalid && !a.zero_u;
@@ -618,30 +629,39 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
       const int x = xt + NX * v;
 #pragma unroll
       for (int l = 0; l < NSL; ++l) {
-        double gr[3][3];
+        T gr[3][3];  // gradient of the total displacement: eps = sym(gr)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T g3[3];
           if constexpr (SCHEME == SCHEME_AFB) {
             afb_grad_edges(dxa[v][l][c], dxa[v][l + 1][c], dxb[v][l][c], dxb[v][l + 1][c], dya[v][l][c],
-                           dyb[v][l][c], dz[v][l][c], dz[v][l + 1][c], ih, g3);
+                           dyb[v][l][c], dz[v][l][c], dz[v][l + 1][c], ih, gr[c]);
           } else {
-            g3[0] = ih[0] * dxa[v][l][c];
-            g3[1] = ih[1] * dya[v][l][c];
-            g3[2] = ih[2] * dz[v][l][c];
+            gr[c][0] = ih[0] * dxa[v][l][c];
+            gr[c][1] = ih[1] * dya[v][l][c];
+            gr[c][2] = ih[2] * dz[v][l][c];
           }
-#pragma unroll
-          for (int j = 0; j < 3; ++j) gr[c][j] = (double)g3[j];
         }
-        double sg[6];
-        constexpr double zero6[6] = {0, 0, 0, 0, 0, 0};
-        cell_stress(zero6, gr, (double)lc[v][l], 2.0 * (double)mc[v][l], sg);
+        const T e3 = T(0.5) * (gr[1][2] + gr[2][1]);
+        const T e4 = T(0.5) * (gr[0][2] + gr[2][0]);
+        const T e5 = T(0.5) * (gr[0][1] + gr[1][0]);
+        const T lt = lc[v][l] * (gr[0][0] + gr[1][1] + gr[2][2]);
+        const T m2 = T(2) * mc[v][l];
+        const T sg[6] = {lt + m2 * gr[0][0], lt + m2 * gr[1][1], lt + m2 * gr[2][2], m2 * e3, m2 * e4, m2 * e5};
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           sa[v][l][c] = sb[v][l][c];
-          sb[v][l][c] = (T)sg[c];
-          sx_at(z & 1, l, c, x) = sb[v][l][c];
-          if (gvalid && l >= 1 && z >= z0) sums[c] += sg[c];
+          sb[v][l][c] = sg[c];
+          sx_at(z & 1, l, c, x) = sg[c];
+        }
+      }
+      // mean stress: the T2 owned cell lines, summed in T per step, then in FP64
+      if (gvalid && z >= z0) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          T acc = T(0);
+#pragma unroll
+          for (int l = 1; l < NSL; ++l) acc += sb[v][l][c];
+          sums[c] += (double)acc;
         }
       }
     }
@@ -695,7 +715,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
       cplx<T> *scr = reinterpret_cast<cplx<T> *>(Sx + ((z - 1) & 1) * SX) + (act ? pid : NPEN) * 2 * L;
       int buf = 0;
       const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, a.tw, buf);
-      const int yrow = (blockIdx.x % ny_blocks) * G * T2 + pg * T2 + m;
+      const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;
       if (act && yrow < n2) {
         const long long row = (long long)(z % n3) * n2 + yrow;
         cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;

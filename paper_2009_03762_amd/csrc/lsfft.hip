@@ -46,6 +46,17 @@ template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
 }
 template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n, E, 128); }
 template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
+// z-pass of the displacement form (three components)
+#ifndef LSFFT_ZUE
+#define LSFFT_ZUE LSFFT_ZE
+#endif
+#ifndef LSFFT_ZUSEG
+#define LSFFT_ZUSEG LSFFT_ZSEG
+#endif
+constexpr int ezu_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZUE ? n : LSFFT_ZUE); }
+template <typename T> constexpr int pcols_zu(int n, int E) {
+  return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
+}
 constexpr int XWG = 256;
 // Stencil kernel: its 2 x 3 x-transforms must fit in 256 threads (<= 32 threads each).
 constexpr int es_of(int L) {
@@ -147,6 +158,8 @@ struct lsfft_solver_s {
   double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
   int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
   long long y_main_blocks = 0, z_main_blocks = 0;
+  long long zu_main_blocks = 0;  // displacement-form z-pass grid
+  int nzub = 0;
   State *st = nullptr;
   State *st_host = nullptr;
   double *hist = nullptr;
@@ -255,6 +268,17 @@ template <typename T> struct Launch {
         return hipErrorInvalidValue;
     }
   }
+  static int zucols(int n) {
+    switch (n) {
+#define ZUC(Nv) \
+  case Nv:      \
+    return pcols_zu<T>(Nv, ezu_of(Nv));
+      LSFFT_YZ_LENGTHS(ZUC)
+#undef ZUC
+      default:
+        return 0;
+    }
+  }
   static int zcols(int n) {
     switch (n) {
 #define ZC(Nv) \
@@ -306,7 +330,7 @@ template <typename T> struct Launch {
     switch (s->d.n3) {
 #define ZUCASE(Nv)                                                                                    \
   case Nv: {                                                                                          \
-    constexpr int E = ez_of(Nv), P = pcols_z<T>(Nv, E);                                               \
+    constexpr int E = ezu_of(Nv), P = pcols_zu<T>(Nv, E);                                             \
     hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
     return hipGetLastError();                                                                          \
   }
@@ -504,7 +528,8 @@ lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit
   }
   const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
   const int nyg = ygrid<T>(s, ncomp);
-  const lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
+  lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
+  if (disp) za.main_blocks = s->zu_main_blocks;
   const lsfft::XArgs<T> xa = xargs<T>(s, Eb, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
   const lsfft::SArgs<T> sa = sargs<T>(s, Eb, 0);
   const lsfft::UArgs<T> ua = uargs<T>(s);
@@ -534,7 +559,7 @@ lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit
       }
       {
         Timed tm(s, 2);
-        LSFFT_CHECK(disp ? L::zpass_u(s, za, s->nzb) : L::zpass(s, za, s->nzb));
+        LSFFT_CHECK(disp ? L::zpass_u(s, za, s->nzub) : L::zpass(s, za, s->nzb));
       }
       ra.k = k;
       {
@@ -874,6 +899,10 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
     s->sZ = Z;
     s->nsb = ny * (s->n[2] / Z);
     s->nub = s->nxb;
+    const int pzu = (s->prec == LSFFT_F32) ? Launch<float>::zucols(s->n[2]) : Launch<double>::zucols(s->n[2]);
+    if (pzu <= 0) return fail(LSFFT_EINVAL);
+    s->zu_main_blocks = ((long long)s->n[1] * s->d.L + pzu - 1) / pzu;
+    s->nzub = (int)(s->zu_main_blocks + ((long long)s->n[1] + pzu - 1) / pzu);
   }
   if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)std::max(s->nxb, s->nsb)) != hipSuccess)
     return fail(LSFFT_ENOMEM);
