@@ -36,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FIXED_BALG = 248.0  # bytes per voxel-iteration, FP32, of the six-component strain-form sweep
 
 
 def workload(n):
@@ -170,6 +171,9 @@ def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
             "launches_timed": dom_cnt,
         },
         "whole_iteration_hbm_frac": value * 1e9 * bytes_per_iteration(n, esize, form) / N / (HBM_PEAK_GBS * 1e9),
+        # the same with the fixed 248 B (FP32) / 496 B (FP64) per voxel-iteration of the six-component
+        # strain-form sweep (strain read + write, moduli, four six-component spectrum sweeps)
+        "whole_iteration_frac_fixed_balg": value * 1e9 * FIXED_BALG * (esize // 4) / (HBM_PEAK_GBS * 1e9),
         "bytes_per_voxel_iteration": bytes_per_iteration(n, esize, form) / N,
         "form": form,
         "kernels": kernels,
@@ -331,11 +335,13 @@ def main():
                    "reductions": "f64"},
         "roofline": head["roofline"],
         "whole_iteration_hbm_frac": head["whole_iteration_hbm_frac"],
+        "whole_iteration_frac_fixed_balg": head["whole_iteration_frac_fixed_balg"],
         "bytes_per_voxel_iteration": head["bytes_per_voxel_iteration"],
         "kernels": head["kernels"],
     }
     if res32 is not None and res64 is not None:
         line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
+                                               "whole_iteration_frac_fixed_balg",
                                                "bytes_per_voxel_iteration", "kernels")}
         line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
     if not args.no_accuracy:
