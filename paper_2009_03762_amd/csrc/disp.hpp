@@ -29,6 +29,8 @@
 // forms the whole gradient in FP64); sigma, f, the transforms and the Green
 // step run in T, with rounding relative to the strain and stress themselves.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace lsfft {
@@ -473,12 +475,14 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 }
 
 // Register-resident variant for power-of-two n1: every thread owns fixed x
-// columns (XV of them) of one y-group and keeps its own u planes (z, z+1) and
-// sigma planes (z-1, z) in registers; LDS only carries the column exchange
-// with the x +- 1 neighbours, the f lines and the transform scratch.  A
-// workgroup holds G = 256 / n1 independent y-groups when n1 < 256.  The FP64
-// u exchange is single-buffered: each plane is published once and the
-// neighbour column it yields is kept in registers for the next step.
+// columns (XV of them) of one y-group and keeps its own displacement planes,
+// edge differences and sigma planes in registers; LDS only carries the column
+// exchange with the x +- 1 neighbours, the f lines and the transform scratch.
+// A workgroup holds G = 256 / n1 independent y-groups when n1 < 256.  The FP64
+// u exchange is single-buffered: each plane is published once and the x
+// differences it yields are kept for the next step.  The z-march is unrolled
+// by two so that the per-plane buffers alternate by name (index P = z & 1)
+// instead of being copied.
 #ifndef LSFFT_STENCIL_WAVES
 #define LSFFT_STENCIL_WAVES 1
 #endif
@@ -502,34 +506,41 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
   __shared__ double Ux[UX];
   __shared__ T Sx[2 * SX];
   __shared__ T F[G * T2 * 3 * N1];
+  __shared__ cplx<T> twl[N1];   // the x twiddles, read by every transform below
   __shared__ double red[(WG / 64) * 8];
   const int tid = threadIdx.x;
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
   const int ny_blocks = (n2 + G * T2 - 1) / (G * T2);
   const int tile = stencil_tile();
+  for (int i = tid; i < N1; i += WG) twl[i] = a.tw[i];
   const int g = tid / NX, xt = tid % NX;
   const int yg0 = (tile % ny_blocks) * G * T2 + g * T2;
   const bool gvalid = yg0 < n2;
   const int z0 = (tile / ny_blocks) * a.Z;
+  // quarter inverse spacings: every AFB difference is an average of four edges
+  const T q[3] = {T(0.25) * a.ih[0], T(0.25) * a.ih[1], T(0.25) * a.ih[2]};
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const bool load_u = gvalid && !a.zero_u;
 
-  // own columns (FP64): ub = plane z+1, un = plane z+2 in flight.  Edge
-  // differences of the TOTAL displacement u + Ebar x, exact in FP64, then
-  // rounded to T: dxa / dxb = x differences (neighbour - own) on planes
-  // z / z+1, dya / dyb = y differences on planes z / z+1, dz = z differences
-  // between planes z and z+1.  Their rounding is relative to the local total
-  // strain (and rotation), which is small in a stiff phase, where
-  // Ebar + grad u would cancel.
-  double ub[XV][NUL][3], un[XV][NUL][3];
-  T dxa[XV][NUL][3], dxb[XV][NUL][3];
-  T dya[XV][NSL][3], dyb[XV][NSL][3];
+  // Per-plane buffers indexed by plane parity.  u: own columns (FP64), plane
+  // p in u[p & 1].  Edge differences of the TOTAL displacement u + Ebar x,
+  // exact in FP64, then rounded to T (their rounding is relative to the local
+  // total strain, which is small in a stiff phase, where Ebar + grad u would
+  // cancel): dx[p & 1] = x differences (neighbour - own) on plane p,
+  // dy[p & 1] = y differences on plane p, dz = between planes z and z+1.
+  // sg[p & 1] = sigma of cell plane p; lam, mu[p & 1] = moduli of cell plane p.
+  double u[2][XV][NUL][3];
+  T dx[2][XV][NUL][3], dy[2][XV][NSL][3];
   T dz[XV][NUL][3];
-  T sa[XV][NSL][6], sb[XV][NSL][6];
-  T lr[XV][NSL], mr[XV][NSL];
-  auto fetch_u = [&](int zz) {
+  T sg[2][XV][NSL][6];
+  T lam[2][XV][NSL], mu[2][XV][NSL];
+  // Prefetches are unconditional and unselected (every index wraps, so each
+  // load is in bounds; u of the first pass is zero-filled memory): a load
+  // whose result had to be merged with an old register value would force a
+  // wait right after it.  Groups past n2 compute on wrapped rows and store
+  // nothing.
+  auto fetch_u = [&](double (&dst)[XV][NUL][3], int zz) {
     const int zg = ((zz % n3) + n3) % n3;
 #pragma unroll
     for (int v = 0; v < XV; ++v)
@@ -538,10 +549,10 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
         const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
         const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) un[v][l][c] = load_u ? a.u[c * N + gi] : 0.0;
+        for (int c = 0; c < 3; ++c) dst[v][l][c] = a.u[c * N + gi];
       }
   };
-  auto fetch_lm = [&](int zz) {
+  auto fetch_lm = [&](T (&dl)[XV][NSL], T (&dm)[XV][NSL], int zz) {
     const int zg = ((zz % n3) + n3) % n3;
 #pragma unroll
     for (int v = 0; v < XV; ++v)
@@ -549,27 +560,26 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
       for (int l = 0; l < NSL; ++l) {
         const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
         const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
-        lr[v][l] = gvalid ? a.lam[gi] : T(1);
-        mr[v][l] = gvalid ? a.mu[gi] : T(1);
+        dl[v][l] = a.lam[gi];
+        dm[v][l] = a.mu[gi];
       }
   };
   auto ux_at = [&](int l, int c, int x) -> double & { return Ux[((g * NUL + l) * 3 + c) * N1 + x]; };
   auto sx_at = [&](int pb, int l, int c, int x) -> T & { return Sx[pb * SX + ((g * NSL + l) * 6 + c) * N1 + x]; };
-  // ub becomes plane z+1: its y differences, then publish it and take the
-  // x differences against the x+1 neighbour column
-  auto take_plane = [&]() {
+  // y differences of plane `src`, publish it, take its x differences
+  auto take_plane = [&](const double (&src)[XV][NUL][3], T (&ddx)[XV][NUL][3], T (&ddy)[XV][NSL][3]) {
 #pragma unroll
     for (int v = 0; v < XV; ++v)
 #pragma unroll
       for (int l = 0; l < NSL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dyb[v][l][c] = (T)((ub[v][l + 1][c] - ub[v][l][c]) + a.hE[c][1]);
+        for (int c = 0; c < 3; ++c) ddy[v][l][c] = (T)((src[v][l + 1][c] - src[v][l][c]) + a.hE[c][1]);
 #pragma unroll
     for (int v = 0; v < XV; ++v)
 #pragma unroll
       for (int l = 0; l < NUL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ux_at(l, c, xt + NX * v) = ub[v][l][c];
+        for (int c = 0; c < 3; ++c) ux_at(l, c, xt + NX * v) = src[v][l][c];
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
@@ -577,125 +587,137 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 #pragma unroll
       for (int l = 0; l < NUL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dxb[v][l][c] = (T)((ux_at(l, c, x1) - ub[v][l][c]) + a.hE[c][0]);
+        for (int c = 0; c < 3; ++c) ddx[v][l][c] = (T)((ux_at(l, c, x1) - src[v][l][c]) + a.hE[c][0]);
     }
   };
 
-  fetch_u(z0 - 1);
-#pragma unroll
-  for (int v = 0; v < XV; ++v)
-#pragma unroll
-    for (int l = 0; l < NUL; ++l)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ub[v][l][c] = un[v][l][c];
-  take_plane();
-  fetch_u(z0);
-  fetch_lm(z0 - 1);
-  __syncthreads();  // the neighbour reads above precede the first publish below
-  for (int z = z0 - 1; z < z0 + a.Z; ++z) {
-    // rotate: plane z+1 arrived in un
-#pragma unroll
-    for (int v = 0; v < XV; ++v) {
-#pragma unroll
-      for (int l = 0; l < NUL; ++l)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          dz[v][l][c] = (T)((un[v][l][c] - ub[v][l][c]) + a.hE[c][2]);
-          ub[v][l][c] = un[v][l][c];
-          dxa[v][l][c] = dxb[v][l][c];
-        }
-#pragma unroll
-      for (int l = 0; l < NSL; ++l)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dya[v][l][c] = dyb[v][l][c];
-    }
-    T lc[XV][NSL], mc[XV][NSL];
+  // One step: sigma of cell plane z (between node planes z and z+1) and, unless
+  // FIRST, f at node plane z and its x transforms.  Plane z is in u[P], plane
+  // z+1 has arrived in u[P^1].
+  auto step = [&](auto Pc, auto firstc, int z) {
+    constexpr int P = decltype(Pc)::value, Q = P ^ 1;
+    constexpr bool FIRST = decltype(firstc)::value;
 #pragma unroll
     for (int v = 0; v < XV; ++v)
 #pragma unroll
-      for (int l = 0; l < NSL; ++l) {
-        lc[v][l] = lr[v][l];
-        mc[v][l] = mr[v][l];
-      }
-    if (z + 2 <= z0 + a.Z) fetch_u(z + 2);
-    if (z + 1 < z0 + a.Z) fetch_lm(z + 1);
-    // The previous step's last reads of Ux (its own exchange) and of the
-    // sigma plane reused here (its transform scratch) precede at least one
-    // barrier of that step or of this exchange.
-    take_plane();
+      for (int l = 0; l < NUL; ++l)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dz[v][l][c] = (T)((u[Q][v][l][c] - u[P][v][l][c]) + a.hE[c][2]);
+    fetch_u(u[P], z + 2);
+    fetch_lm(lam[Q], mu[Q], z + 1);
+    // The previous step's last reads of Ux (its exchange) and of the sigma
+    // plane reused below (its transform scratch) precede a barrier of that
+    // step or the one inside this exchange.
+    take_plane(u[Q], dx[Q], dy[Q]);
     // ---- sigma at the cells (x, lines 0..NSL-1, plane z) of this thread
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int x = xt + NX * v;
+      T gr[NSL][3][3];  // gradient of the total displacement: eps = sym(gr)
 #pragma unroll
-      for (int l = 0; l < NSL; ++l) {
-        T gr[3][3];  // gradient of the total displacement: eps = sym(gr)
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (SCHEME == SCHEME_AFB) {
+          // line sums shared by the two cells on either side of a node line
+          T px[NUL], rz[NUL];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if constexpr (SCHEME == SCHEME_AFB) {
-            afb_grad_edges(dxa[v][l][c], dxa[v][l + 1][c], dxb[v][l][c], dxb[v][l + 1][c], dya[v][l][c],
-                           dyb[v][l][c], dz[v][l][c], dz[v][l + 1][c], ih, gr[c]);
-          } else {
-            gr[c][0] = ih[0] * dxa[v][l][c];
-            gr[c][1] = ih[1] * dya[v][l][c];
-            gr[c][2] = ih[2] * dz[v][l][c];
+          for (int l = 0; l < NUL; ++l) {
+            px[l] = dx[P][v][l][c] + dx[Q][v][l][c];
+            rz[l] = T(2) * dz[v][l][c] + (dx[Q][v][l][c] - dx[P][v][l][c]);
+          }
+#pragma unroll
+          for (int l = 0; l < NSL; ++l) {
+            gr[l][c][0] = q[0] * (px[l] + px[l + 1]);
+            gr[l][c][1] = q[1] * (T(2) * (dy[P][v][l][c] + dy[Q][v][l][c]) + (px[l + 1] - px[l]));
+            gr[l][c][2] = q[2] * (rz[l] + rz[l + 1]);
+          }
+        } else {
+#pragma unroll
+          for (int l = 0; l < NSL; ++l) {
+            gr[l][c][0] = ih[0] * dx[P][v][l][c];
+            gr[l][c][1] = ih[1] * dy[P][v][l][c];
+            gr[l][c][2] = ih[2] * dz[v][l][c];
           }
         }
-        const T e3 = T(0.5) * (gr[1][2] + gr[2][1]);
-        const T e4 = T(0.5) * (gr[0][2] + gr[2][0]);
-        const T e5 = T(0.5) * (gr[0][1] + gr[1][0]);
-        const T lt = lc[v][l] * (gr[0][0] + gr[1][1] + gr[2][2]);
-        const T m2 = T(2) * mc[v][l];
-        const T sg[6] = {lt + m2 * gr[0][0], lt + m2 * gr[1][1], lt + m2 * gr[2][2], m2 * e3, m2 * e4, m2 * e5};
+      }
+      T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int l = 0; l < NSL; ++l) {
+        const T lt = lam[P][v][l] * (gr[l][0][0] + gr[l][1][1] + gr[l][2][2]);
+        const T m1 = mu[P][v][l];
+        const T m2 = T(2) * m1;
+        const T s6[6] = {lt + m2 * gr[l][0][0], lt + m2 * gr[l][1][1], lt + m2 * gr[l][2][2],
+                         m1 * (gr[l][1][2] + gr[l][2][1]), m1 * (gr[l][0][2] + gr[l][2][0]),
+                         m1 * (gr[l][0][1] + gr[l][1][0])};
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          sa[v][l][c] = sb[v][l][c];
-          sb[v][l][c] = sg[c];
-          sx_at(z & 1, l, c, x) = sg[c];
+          sg[P][v][l][c] = s6[c];
+          sx_at(P, l, c, x) = s6[c];
+          if (l >= 1) acc[c] += s6[c];
         }
       }
       // mean stress: the T2 owned cell lines, summed in T per step, then in FP64
-      if (gvalid && z >= z0) {
+      if (gvalid && !FIRST) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          T acc = T(0);
-#pragma unroll
-          for (int l = 1; l < NSL; ++l) acc += sb[v][l][c];
-          sums[c] += (double)acc;
-        }
+        for (int c = 0; c < 6; ++c) sums[c] += (double)acc[c];
       }
     }
     __syncthreads();
-    if (z < z0) continue;
-    // ---- f = div sigma at the nodes (x, lines 0..T2-1, plane z)
+    if constexpr (FIRST) return;
+    // ---- f = div sigma at the nodes (x, lines 0..T2-1, plane z).  Node line
+    // m gathers cell lines m+1 (b = 0) and m (b = 1), cell planes z (d = 0) and
+    // z-1 (d = 1), columns x (a = 0) and x-1 (a = 1).
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int x = xt + NX * v;
       const int xm = (x + N1 - 1) % N1;
+      T f[T2][3];
+#pragma unroll
+      for (int m = 0; m < T2; ++m)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[m][i] = T(0);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int ci = vi(c), cj = vj(c);  // sigma_{ci cj}, ci <= cj
+        if constexpr (SCHEME == SCHEME_AFB) {
+          // z-pair sums and z differences per cell line, own and neighbour
+          T A[NSL], D[NSL], An[NSL], Dn[NSL];
+#pragma unroll
+          for (int l = 0; l < NSL; ++l) {
+            const T s0 = sg[P][v][l][c], s1 = sg[Q][v][l][c];
+            const T n0 = sx_at(P, l, c, xm), n1 = sx_at(Q, l, c, xm);
+            A[l] = s0 + s1;
+            D[l] = s0 - s1;
+            An[l] = n0 + n1;
+            Dn[l] = n0 - n1;
+          }
+#pragma unroll
+          for (int m = 0; m < T2; ++m) {
+            T dd[3];
+            dd[0] = q[0] * ((A[m + 1] + A[m]) - (An[m + 1] + An[m]));
+            dd[1] = q[1] * ((A[m + 1] + An[m + 1]) - (A[m] + An[m]));
+            dd[2] = q[2] * ((D[m + 1] + D[m]) + (Dn[m + 1] + Dn[m]));
+            // f_i += d_j sigma_ij over the (i, j) pairs this component serves
+            f[m][ci] += dd[cj];
+            if (ci != cj) f[m][cj] += dd[ci];
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < T2; ++m) {
+            const T own = sg[P][v][m + 1][c];
+            T dd[3];
+            dd[0] = ih[0] * (own - sx_at(P, m + 1, c, xm));
+            dd[1] = ih[1] * (own - sg[P][v][m][c]);
+            dd[2] = ih[2] * (own - sg[Q][v][m + 1][c]);
+            f[m][ci] += dd[cj];
+            if (ci != cj) f[m][cj] += dd[ci];
+          }
+        }
+      }
 #pragma unroll
       for (int m = 0; m < T2; ++m) {
-        T f3[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          T acc = T(0);
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            const int c = voigt(i, j);
-            T sv[2][2][2];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              const int l = m + 1 - b;
-              sv[0][b][0] = sb[v][l][c];
-              sv[0][b][1] = sa[v][l][c];
-              sv[1][b][0] = sx_at(z & 1, l, c, xm);
-              sv[1][b][1] = sx_at((z - 1) & 1, l, c, xm);
-            }
-            acc += Stencil<SCHEME>::div(sv, j, ih);
-          }
-          f3[i] = acc;
-          F[((g * T2 + m) * 3 + i) * N1 + x] = acc;
-        }
-        if (gvalid) sums[6] += (double)f3[0] * f3[0] + (double)f3[1] * f3[1] + (double)f3[2] * f3[2];
+        for (int i = 0; i < 3; ++i) F[((g * T2 + m) * 3 + i) * N1 + x] = f[m][i];
+        if (gvalid) sums[6] += (double)(f[m][0] * f[m][0] + f[m][1] * f[m][1] + f[m][2] * f[m][2]);
       }
     }
     __syncthreads();
@@ -712,9 +734,9 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
         const int o = ((pg * T2 + m) * 3 + c) * N1 + xx;
         vv[e] = act ? cplx<T>{F[o], F[o + 1]} : cplx<T>{T(0), T(0)};
       }
-      cplx<T> *scr = reinterpret_cast<cplx<T> *>(Sx + ((z - 1) & 1) * SX) + (act ? pid : NPEN) * 2 * L;
+      cplx<T> *scr = reinterpret_cast<cplx<T> *>(Sx + Q * SX) + (act ? pid : NPEN) * 2 * L;
       int buf = 0;
-      const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, a.tw, buf);
+      const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, twl, buf);
       const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;
       if (act && yrow < n2) {
         const long long row = (long long)(z % n3) * n2 + yrow;
@@ -724,6 +746,23 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
         if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xnq;
       }
     }
+  };
+
+  // prologue: plane z0-1 (odd parity, since Z and hence z0 are even) and its
+  // x and y differences, plane z0 in flight, moduli of cell plane z0-1
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using BT = std::integral_constant<bool, true>;
+  using BF = std::integral_constant<bool, false>;
+  fetch_u(u[1], z0 - 1);
+  take_plane(u[1], dx[1], dy[1]);
+  fetch_u(u[0], z0);
+  fetch_lm(lam[1], mu[1], z0 - 1);
+  __syncthreads();  // the neighbour reads above precede the first publish below
+  step(I1{}, BT{}, z0 - 1);
+  for (int z = z0; z < z0 + a.Z; z += 2) {
+    step(I0{}, BF{}, z);
+    step(I1{}, BF{}, z + 1);
   }
   if (a.partial) {
     block_sum<WG>(sums, 7, red);

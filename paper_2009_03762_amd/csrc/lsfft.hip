@@ -69,11 +69,14 @@ constexpr int ST2 = LSFFT_ST2;
 constexpr bool stencil_reg_kernel(int n1) { return (n1 & (n1 - 1)) == 0 && n1 >= 8; }
 // LDS of the stencil kernels (n1 values per line): the register-resident one
 // holds one FP64 u plane (T2+2 lines x 3) per y-group, two sigma planes
-// (T2+1 lines x 6) and the f lines (T2 x 3); the other one two u planes.
+// (T2+1 lines x 6), the f lines (T2 x 3) and the x twiddles; the other one
+// two u planes.
 template <typename T> constexpr long long stencil_lds(int n1) {
   const long long G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
   const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
-  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + 256;
+  const long long twiddles = stencil_reg_kernel(n1) ? 2LL * n1 * (long long)sizeof(T) : 0;
+  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + twiddles +
+         256;
 }
 template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
 
