@@ -122,6 +122,7 @@ template <typename T> struct UArgs {
 template <typename T, int L, int E, int WG>
 __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   if (a.st && a.st->done) return;
+  __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
   static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
       if (valid) ld2(a.u + c * N + idx, uo[c][e][0], uo[c][e][1]);
       else uo[c][e][0] = uo[c][e][1] = 0.0;
     }
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, a.tw, buf);
+  for (int c = 0; c < 3; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, twl, buf);
   if (valid) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -778,6 +780,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 template <typename T, int NZ, int E, int P>
 __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
   if (a.st && a.st->done) return;
+  __shared__ cplx<T> twl_[NZ];
   constexpr int TPC = NZ / E;
   __shared__ cplx<T> lds[2 * NZ * P];
   const int tid = threadIdx.x;
@@ -811,8 +814,9 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
   int buf = 0;
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1, buf);
+  for (int c = 0; c < 3; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, twl, 1, buf);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     cplx<T> f[3] = {v[0][e], v[1][e], v[2][e]};
@@ -822,7 +826,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1, buf);
+    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, twl, 1, buf);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];

@@ -187,6 +187,20 @@ __device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds,
   if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0>::run(v, t, lds, ms, tw, ts, buf);
 }
 
+// Copy a twiddle table of NT entries into LDS with all threads of the
+// workgroup, then synchronise.  Each radix pass reads its twiddles right
+// before use; from LDS that costs tens of cycles instead of a cache round trip.
+#ifndef LSFFT_LDS_TW
+#define LSFFT_LDS_TW 1
+#endif
+template <typename T, int NT>
+__device__ __forceinline__ const cplx<T> *stage_twiddles(cplx<T> (&dst)[NT], const cplx<T> *__restrict__ src) {
+  if constexpr (!LSFFT_LDS_TW) return src;
+  for (int i = threadIdx.x; i < NT; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return dst;
+}
+
 // Number of LDS exchanges the transform performs (passes - 1).
 template <int L, int E> constexpr int fft_exchanges() { return Plan<L, E>::npass() - 1; }
 

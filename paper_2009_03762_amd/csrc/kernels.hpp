@@ -193,6 +193,7 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nblocks) {
 template <typename T, int L, int E, int WG>
 __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   if (a.st && a.st->done) return;
+  __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
   constexpr bool PRELOAD_EPS = (sizeof(T) == 4) && LSFFT_X_PRELOAD;
@@ -254,9 +255,10 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
         else eo[c][e][0] = eo[c][e][1] = T(0);
       }
   }
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
   if (need_delta) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, a.tw, buf);
+    for (int c = 0; c < 6; ++c) c2r_line<T, L, E>(w[c], xn[c], t, lane, sl, twl, buf);
   }
 
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    const cplx<T> x_nyq = r2c_line<T, L, E>(w[c], t, lane, sl, a.tw, buf);
+    const cplx<T> x_nyq = r2c_line<T, L, E>(w[c], t, lane, sl, twl, buf);
     if (valid) {
       cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
@@ -347,6 +349,7 @@ template <typename T> struct YArgs {
 template <typename T, int NY, int E, int P, bool FWD>
 __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
   if (a.st && a.st->done) return;
+  __shared__ cplx<T> twl_[NY];
   constexpr int TPC = NY / E;
   __shared__ cplx<T> lds[2 * NY * P];
   const int tid = threadIdx.x;
@@ -372,7 +375,8 @@ __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = valid ? base[(t + TPC * e) * stride] : cplx<T>{T(0), T(0)};
   int buf = 0;
-  fft_pencil<T, NY, E, FWD>(v, t, lds + p, P, a.tw, 1, buf);
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
+  fft_pencil<T, NY, E, FWD>(v, t, lds + p, P, twl, 1, buf);
   if (valid) {
 #pragma unroll
     for (int e = 0; e < E; ++e) base[(t + TPC * e) * stride] = v[e];
@@ -395,6 +399,7 @@ template <typename T> struct ZArgs {
 template <typename T, int NZ, int E, int P>
 __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   if (a.st && a.st->done) return;
+  __shared__ cplx<T> twl_[NZ];
   constexpr int TPC = NZ / E;
   constexpr int WG = P * TPC;
   __shared__ cplx<T> lds[2 * NZ * P];
@@ -431,8 +436,9 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
   int buf = 0;
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, a.tw, 1, buf);
+  for (int c = 0; c < 6; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, twl, 1, buf);
   if (a.forward_only) {
     if (valid) {
 #pragma unroll
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, a.tw, 1, buf);
+    fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, twl, 1, buf);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
