@@ -35,15 +35,15 @@
 
 namespace lsfft {
 
-// Delta u_hat = K^{-1} f_hat * scale at spectrum indices (i1, i2, i3).
+// Delta u_hat = K^{-1} f_hat * scale at one frequency, with the per-axis
+// table values ax[r] = axis_val(g, r, index_r).
 template <typename T>
-__device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, int i1, int i2, int i3,
+__device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, const AxisVal<T> (&ax)[3],
                                                  cplx<T> (&f)[3]) {
-  const int idx[3] = {i1, i2, i3};
   if (g.scheme == SCHEME_FB) {
     cplx<T> a[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) a[r] = cplx<T>{tabv(g, TAB_AR, r, idx[r]), tabv(g, TAB_AI, r, idx[r])};
+    for (int r = 0; r < 3; ++r) a[r] = cplx<T>{ax[r].p, ax[r].q};
     const T aa = norm2(a[0]) + norm2(a[1]) + norm2(a[2]);
     if (aa == T(0)) {
 #pragma unroll
@@ -83,17 +83,9 @@ __device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, int i1
   }
   // AFB: rotated wavevector
   T k[3];
-  {
-    T sh[3], c[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      sh[r] = tabv(g, TAB_SH, r, idx[r]);
-      c[r] = tabv(g, TAB_C, r, idx[r]);
-    }
-    k[0] = sh[0] * c[1] * c[2];
-    k[1] = sh[1] * c[2] * c[0];
-    k[2] = sh[2] * c[0] * c[1];
-  }
+  k[0] = ax[0].p * ax[1].q * ax[2].q;
+  k[1] = ax[1].p * ax[2].q * ax[0].q;
+  k[2] = ax[2].p * ax[0].q * ax[1].q;
   const T kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
   if (kk == T(0)) {
 #pragma unroll
@@ -813,6 +805,10 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
+  const AxisVal<T> axx = axis_val(a.g, 0, i1), axy = axis_val(a.g, 1, valid ? i2 : 0);
+  AxisVal<T> axz[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) axz[e] = axis_val(a.g, 2, t + TPC * e);
   int buf = 0;
   const cplx<T> *twl = stage_twiddles(twl_, a.tw);
 #pragma unroll
@@ -820,7 +816,8 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     cplx<T> f[3] = {v[0][e], v[1][e], v[2][e]};
-    green_disp_point(a.g, i1, valid ? i2 : 0, t + TPC * e, f);
+    const AxisVal<T> ax[3] = {axx, axy, axz[e]};
+    green_disp_point(a.g, ax, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c][e] = f[c];
   }

@@ -186,10 +186,25 @@ __device__ __forceinline__ void green_dgo(const GreenParams<T> &g, const T *coef
   for (int I = 0; I < 6; ++I) s[I] = out[I];
 }
 
-// Dispatch on the scheme for spectrum indices (i1, i2, i3), i1 in [0, n1/2].
+// The two per-axis table values a Green step needs at axis index i:
+// (sin, cos) for AFB, (Re, Im) of the FB symbol, the plain wavenumber for
+// BASIC.  Kernels load them together with their data, before the transforms,
+// so that the Green step itself reads registers only; the table kinds are
+// chosen arithmetically (no branch has to merge a load result).
+template <typename T> struct AxisVal {
+  T p, q;
+};
+template <typename T> __device__ __forceinline__ AxisVal<T> axis_val(const GreenParams<T> &g, int axis, int i) {
+  const int kp = g.scheme == SCHEME_AFB ? TAB_SH : (g.scheme == SCHEME_FB ? TAB_AR : TAB_K);
+  const int kq = g.scheme == SCHEME_AFB ? TAB_C : (g.scheme == SCHEME_FB ? TAB_AI : TAB_K);
+  return AxisVal<T>{tabv(g, kp, axis, i), tabv(g, kq, axis, i)};
+}
+
+// Dispatch on the scheme for spectrum indices (i1, i2, i3), i1 in [0, n1/2],
+// with the per-axis table values ax[r] = axis_val(g, r, idx[r]).
 template <typename T>
 __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, int i2, int i3,
-                                              cplx<T> (&s)[6]) {
+                                              const AxisVal<T> (&ax)[3], cplx<T> (&s)[6]) {
   const int idx[3] = {i1, i2, i3};
   if (g.scheme == SCHEME_DGO) {
     if (i1 == 0 && i2 == 0 && i3 == 0) {
@@ -210,26 +225,20 @@ __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, i
   if (g.scheme == SCHEME_FB) {
     cplx<T> a[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) a[r] = cplx<T>{tabv(g, TAB_AR, r, idx[r]), tabv(g, TAB_AI, r, idx[r])};
+    for (int r = 0; r < 3; ++r) a[r] = cplx<T>{ax[r].p, ax[r].q};
     return green_fb(g, a, s);
   }
   T k[3];
   if (g.scheme == SCHEME_AFB) {
-    T sh[3], c[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      sh[r] = tabv(g, TAB_SH, r, idx[r]);
-      c[r] = tabv(g, TAB_C, r, idx[r]);
-    }
-    k[0] = sh[0] * c[1] * c[2];
-    k[1] = sh[1] * c[2] * c[0];
-    k[2] = sh[2] * c[0] * c[1];
+    k[0] = ax[0].p * ax[1].q * ax[2].q;
+    k[1] = ax[1].p * ax[2].q * ax[0].q;
+    k[2] = ax[2].p * ax[0].q * ax[1].q;
   } else {
     bool nyq[3];
     bool live = false;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      k[r] = tabv(g, TAB_K, r, idx[r]);
+      k[r] = ax[r].p;
       nyq[r] = (2 * idx[r] == g.n[r]);
       live = live || (!nyq[r] && k[r] != T(0));
     }
@@ -240,6 +249,13 @@ __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, i
     }
   }
   return green_real(g, k, s);
+}
+
+// The same, loading the table values itself.
+template <typename T>
+__device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, int i2, int i3, cplx<T> (&s)[6]) {
+  const AxisVal<T> ax[3] = {axis_val(g, 0, i1), axis_val(g, 1, i2), axis_val(g, 2, i3)};
+  return green_point(g, i1, i2, i3, ax, s);
 }
 
 }  // namespace lsfft

@@ -435,6 +435,10 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
+  const AxisVal<T> axx = axis_val(a.g, 0, i1), axy = axis_val(a.g, 1, valid ? i2 : 0);
+  AxisVal<T> axz[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) axz[e] = axis_val(a.g, 2, t + TPC * e);
   int buf = 0;
   const cplx<T> *twl = stage_twiddles(twl_, a.tw);
 #pragma unroll
@@ -455,7 +459,8 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
     cplx<T> s[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) s[c] = v[c][e];
-    const double r = green_point(a.g, i1, valid ? i2 : 0, t + TPC * e, s);
+    const AxisVal<T> ax[3] = {axx, axy, axz[e]};
+    const double r = green_point(a.g, i1, valid ? i2 : 0, t + TPC * e, ax, s);
     if (valid) res += wgt * r;
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][e] = s[c];
