@@ -241,6 +241,94 @@ def equal_accuracy(n, targets=(1e-5, 1e-6), kmax=500, kstep=10):
     return out
 
 
+def config_report():
+    """Iterations to tolerance, status and wall time for the configurations of
+    the paper's benchmark family: 16^3 BASIC FP64 (tol 1e-8); 64^3 at contrasts
+    10 and 1e3, sharp and smooth interfaces, BASIC / FB / AFB, FP64 and FP32,
+    six unit load cases -> Mandel C_eff (tol 1e-6); 256^3 AFB and DGO at
+    contrasts 1e3 and 1e-3, PCD, eps_12 = 1e-3 (tol 1e-6).  GPU only; FP32
+    C_eff is compared with the FP64 one."""
+    import torch
+
+    from paper_2009_03762_amd import inputs, lsfft
+    r2 = np.sqrt(0.5)
+    units = np.zeros((6, 6))
+    for J in range(6):
+        units[J, J] = 1.0 if J < 3 else r2   # unit Mandel norm, tensor components
+    mandel = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+
+    def cell(n, contrast, interface="sharp"):
+        lam, mu = inputs.cubic_inclusion(n, n // 2, 1.0, contrast, 0.3, interface=interface, eps=1.0)
+        l0, m0 = inputs.reference_medium_mean(1.0, contrast, 0.3)
+        return lam, mu, l0, m0
+
+    def timed(s, Eb, tol, maxit):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve_device(Eb, tol=tol, maxit=maxit)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    out = {}
+    lam, mu, l0, m0 = cell(16, 10.0)
+    s = lsfft.Solver(lam, mu, l0, m0, scheme="basic", prec="f64")
+    r, dt = timed(s, inputs.macro_strain("11", 1e-3), 1e-8, 10000)
+    s.close()
+    out["16^3 basic f64 tol 1e-8"] = {"iters": r["iters"], "status": lsfft.status_string(r["status"]),
+                                      "residual": r["residual"], "ms": dt * 1e3}
+    print("[configs] 16^3 done", file=sys.stderr, flush=True)
+    c2 = {}
+    for contrast in (10.0, 1000.0):
+        for interface in ("sharp", "smooth"):
+            lam, mu, l0, m0 = cell(64, contrast, interface)
+            ceff = {}
+            for scheme in ("basic", "fb", "afb"):
+                for prec in ("f64", "f32"):
+                    s = lsfft.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec)
+                    M = np.zeros((6, 6))
+                    its, sts, tot = [], [], 0.0
+                    for J in range(6):
+                        r, dt = timed(s, units[J], 1e-6, 20000)
+                        M[:, J] = mandel * r["sig_mean"]
+                        its.append(r["iters"])
+                        sts.append(lsfft.status_string(r["status"]))
+                        tot += dt
+                    s.close()
+                    ceff[(scheme, prec)] = M
+                    ent = {"iters": its, "status": sorted(set(sts)), "ms_total": tot * 1e3,
+                           "C1111": M[0, 0], "C1212_mandel": M[5, 5],
+                           "asym": float(np.linalg.norm(M - M.T) / np.linalg.norm(M))}
+                    if prec == "f32":
+                        ent["rel_err_vs_f64"] = float(np.linalg.norm(M - ceff[(scheme, "f64")]) /
+                                                      np.linalg.norm(ceff[(scheme, "f64")]))
+                    c2[f"64^3 contrast {contrast:g} {interface} {scheme} {prec}"] = ent
+            print(f"[configs] 64^3 contrast {contrast:g} {interface} done", file=sys.stderr, flush=True)
+    out["config2"] = c2
+    c3 = {}
+    Eb = inputs.macro_strain("12", 1e-3)
+    for contrast in (1e3, 1e-3):
+        lam, mu, l0, m0 = cell(256, contrast)
+        runs = [("afb f64", dict(scheme="afb", prec="f64")),
+                ("afb f32 (5 fp64 warm-start iterations)", dict(scheme="afb", prec="f32", f64_warmup=5)),
+                ("dgo p=1 M=4 f32", dict(scheme="dgo", prec="f32", dgo_images=4, dgo_weight_power=1)),
+                ("dgo p=2 M=4 f32", dict(scheme="dgo", prec="f32", dgo_images=4, dgo_weight_power=2))]
+        for name, kw in runs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = lsfft.Solver(lam, mu, l0, m0, disc="pcd", **kw)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            r, dt = timed(s, Eb, 1e-6, 3000)
+            s.close()
+            c3[f"256^3 contrast {contrast:g} {name}"] = {
+                "iters": r["iters"], "status": lsfft.status_string(r["status"]), "residual": r["residual"],
+                "ms": dt * 1e3, "create_ms": setup * 1e3,
+                "GVoxel_iter_per_s": 256 ** 3 * max(r["iters"], 1) / dt / 1e9}
+            print(f"[configs] 256^3 {contrast:g} {name} done", file=sys.stderr, flush=True)
+    out["config3"] = c3
+    return out
+
+
 def cpu_baseline(n=128, iters=8):
     """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
     full iterations after setup, single-threaded numpy."""
@@ -300,6 +388,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
     args = ap.parse_args()
@@ -310,6 +400,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.configs:
+        print(json.dumps(config_report()), flush=True)
         return
     res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form) \
         if args.prec in ("f32", "both") else None

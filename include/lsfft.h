@@ -60,8 +60,12 @@ typedef enum { LSFFT_TD = 0, LSFFT_PCD = 1 } lsfft_disc;
 
 typedef enum { LSFFT_BASIC = 0, LSFFT_FB = 1, LSFFT_AFB = 2, LSFFT_DGO = 3 } lsfft_scheme;
 
-/* F64: all arithmetic in FP64.  F32: fields, FFTs and the Green step in FP32;
- * the residual, mean stress and convergence reductions in FP64. */
+/* F64: all arithmetic in FP64.  F32: strain, stress, FFTs and the Green step
+ * in FP32; the displacement of the displacement form, the residual, mean
+ * stress and convergence reductions in FP64.  With a stiffness contrast chi
+ * the FP32 equilibrium residual has a floor of roughly chi x 1e-8 (about 2e-5
+ * at chi = 1e3): a tolerance below it is not reached (LSFFT_ENOTCONV after
+ * maxit), although the fields reach FP64 accuracy well before. */
 typedef enum { LSFFT_F64 = 0, LSFFT_F32 = 1 } lsfft_prec;
 
 typedef enum {
