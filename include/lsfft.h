@@ -160,6 +160,24 @@ lsfft_status lsfft_stress_spectrum(lsfft_solver s, const void *eps_dev, void *si
  * |in(xi) q^b(xi)|^2 (BASIC, FB, AFB; 0 for DGO).  in and out may alias. */
 lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev, double *res_sq);
 
+/* Adjoint sensitivity of an effective-stiffness objective.  For the converged
+ * strains eps_a, eps_b of two solves with macroscopic strains A and B (DEVICE
+ * fields of the solver's precision, 6N, field layout, e.g. from
+ * lsfft_solve_device), J = <eps_a : C : eps_b> = A : C_eff : B.  BASIC, FB
+ * and AFB are self-adjoint (their fixed point minimises a quadratic energy
+ * over compatible fluctuations, Sec. 5.2), so the adjoint field of A is the
+ * primal solution under A and the derivative of J is the partial derivative
+ * at the solution:
+ *   dj_dlambda[x] = tr eps_a tr eps_b / N,  dj_dmu[x] = 2 eps_a : eps_b / N,
+ *   dj_dyoung[x]  = (lambda dJ/dlambda + mu dJ/dmu) / E   (fixed Poisson ratio,
+ *                   E = mu (3 lambda + 2 mu) / (lambda + mu) of voxel x).
+ * Outputs: DEVICE arrays of N values of the solver's precision; any may be
+ * NULL.  Computed in FP64.  The DGO iteration is not self-adjoint: its
+ * sensitivities are not given by this entry point.  EINVAL on NULL handle or
+ * strain fields. */
+lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, const void *eps_b_dev,
+                                      void *dj_dlambda_dev, void *dj_dmu_dev, void *dj_dyoung_dev);
+
 /* Per-kernel event timing for benchmarking.  lsfft_set_timing(s, id) makes
  * every later solve record HIP events around each launch of kernel `id`
  * (0 = x-pass, 1 = forward y-pass, 2 = z-pass + Green, 3 = inverse y-pass,

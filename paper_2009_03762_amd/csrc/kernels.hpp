@@ -584,6 +584,41 @@ __global__ void k_state_init(State *s) {
 }
 
 // ---------------------------------------------------------------- pointwise helpers
+// Sensitivity of J = <eps_a : C : eps_b> (= A : C_eff : B for the converged
+// strains under macroscopic loads A and B) to the moduli of each voxel: the
+// discrete problem minimises a quadratic energy over compatible fluctuations,
+// so the derivative of the minimum is the partial derivative at the minimiser:
+//   dJ/dlambda(x) = tr eps_a tr eps_b / N,   dJ/dmu(x) = 2 eps_a : eps_b / N,
+// and at fixed Poisson ratio dJ/dE(x) = (lambda dJ/dlambda + mu dJ/dmu) / E
+// with E = mu (3 lambda + 2 mu) / (lambda + mu).  FP64 arithmetic; any output
+// may be null.
+template <typename T>
+__global__ void k_stiffness_gradient(const T *__restrict__ ea, const T *__restrict__ eb, const T *__restrict__ lam,
+                                     const T *__restrict__ mu, T *__restrict__ dl, T *__restrict__ dm,
+                                     T *__restrict__ de, long long N) {
+  const double inv = 1.0 / (double)N;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    double tra = 0.0, trb = 0.0, dd = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double a = (double)ea[c * N + i], b = (double)eb[c * N + i];
+      if (c < 3) {
+        tra += a;
+        trb += b;
+      }
+      dd += (c < 3 ? 1.0 : 2.0) * a * b;
+    }
+    const double gl = tra * trb * inv, gm = 2.0 * dd * inv;
+    if (dl) dl[i] = (T)gl;
+    if (dm) dm[i] = (T)gm;
+    if (de) {
+      const double l = (double)lam[i], m = (double)mu[i];
+      const double E = m * (3.0 * l + 2.0 * m) / (l + m);
+      de[i] = (T)((l * gl + m * gm) / E);
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_hooke_out(const T *__restrict__ eps, const T *__restrict__ lam, const T *__restrict__ mu,
                             T *__restrict__ sig, long long N) {

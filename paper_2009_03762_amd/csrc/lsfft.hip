@@ -996,6 +996,25 @@ lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev
                                 : green_impl<double>(s, in_dev, out_dev, res_sq);
 }
 
+lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, const void *eps_b_dev,
+                                      void *dj_dlambda_dev, void *dj_dmu_dev, void *dj_dyoung_dev) {
+  if (!s || !eps_a_dev || !eps_b_dev) return LSFFT_EINVAL;
+  const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
+  if (s->prec == LSFFT_F32)
+    hipLaunchKernelGGL(lsfft::k_stiffness_gradient<float>, dim3(blocks), dim3(256), 0, s->stream,
+                       (const float *)eps_a_dev, (const float *)eps_b_dev, (const float *)s->lam,
+                       (const float *)s->mu, (float *)dj_dlambda_dev, (float *)dj_dmu_dev, (float *)dj_dyoung_dev,
+                       s->d.N);
+  else
+    hipLaunchKernelGGL(lsfft::k_stiffness_gradient<double>, dim3(blocks), dim3(256), 0, s->stream,
+                       (const double *)eps_a_dev, (const double *)eps_b_dev, (const double *)s->lam,
+                       (const double *)s->mu, (double *)dj_dlambda_dev, (double *)dj_dmu_dev,
+                       (double *)dj_dyoung_dev, s->d.N);
+  LSFFT_CHECK(hipGetLastError());
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  return LSFFT_OK;
+}
+
 lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id) {
   if (!s || kernel_id < -1 || kernel_id > 5) return LSFFT_EINVAL;
   s->timing_kernel = kernel_id;

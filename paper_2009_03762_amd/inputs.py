@@ -153,3 +153,27 @@ def mandel_unit_strains():
     out = np.eye(6)
     out[3:, 3:] /= np.sqrt(2.0)
     return out
+
+
+def gaussian_random_field(n, corr_len=8.0, seed=7):
+    """Standardised periodic Gaussian random field: white noise convolved with
+    a Gaussian of standard deviation `corr_len` voxels (applied as the
+    Gaussian's periodic transfer function), then shifted and scaled to zero
+    mean and unit variance.  Shape (n3, n2, n1)."""
+    n1, n2, n3 = _shape(n)
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n3, n2, n1))
+    k3 = 2.0 * np.pi * np.fft.fftfreq(n3)[:, None, None]
+    k2 = 2.0 * np.pi * np.fft.fftfreq(n2)[None, :, None]
+    k1 = 2.0 * np.pi * np.fft.rfftfreq(n1)[None, None, :]
+    filt = np.exp(-0.5 * corr_len ** 2 * (k1 ** 2 + k2 ** 2 + k3 ** 2))
+    g = np.fft.irfftn(np.fft.rfftn(w, axes=(0, 1, 2)) * filt, s=(n3, n2, n1), axes=(0, 1, 2))
+    g -= g.mean()
+    return g / g.std()
+
+
+def lognormal_young(n, corr_len=8.0, seed=7, log10_mean=1.0, log10_std=0.5, clip=(1.0, 100.0)):
+    """Log-normal Young's modulus field E = clip(10^(log10_mean + log10_std g), clip)
+    from `gaussian_random_field`."""
+    g = gaussian_random_field(n, corr_len, seed)
+    return np.clip(10.0 ** (log10_mean + log10_std * g), clip[0], clip[1])

@@ -59,6 +59,7 @@ def _load():
         "lsfft_residual_history": (C.c_int, [h, dp, C.c_int32, C.POINTER(C.c_int32)]),
         "lsfft_stress_spectrum": (C.c_int, [h, C.c_void_p, C.c_void_p]),
         "lsfft_green_apply": (C.c_int, [h, C.c_void_p, C.c_void_p, dp]),
+        "lsfft_stiffness_gradient": (C.c_int, [h, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
         "lsfft_set_timing": (C.c_int, [h, C.c_int32]),
         "lsfft_get_timing": (C.c_int, [h, dp, C.POINTER(C.c_int32)]),
         "lsfft_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -75,7 +76,8 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("lsfft_create", "lsfft_solve", "lsfft_solve_device", "lsfft_residual_history",
-           "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_set_timing", "lsfft_get_timing",
+           "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
+           "lsfft_get_timing",
            "lsfft_kernel_name", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
 
 
@@ -146,10 +148,17 @@ def destroy(handle):
     return _lib.lsfft_destroy(handle)
 
 
+def _ebar(Ebar):
+    Eb = np.ascontiguousarray(Ebar, dtype=np.float64)
+    if Eb.shape != (6,):
+        raise ValueError("Ebar must hold the 6 Voigt tensor components (11, 22, 33, 23, 13, 12)")
+    return Eb
+
+
 def solve(handle, Ebar, tol, maxit, eps=None, sig=None):
     """lsfft_solve with host outputs.  eps / sig: float64 arrays (6, n3, n2, n1) or None.
     Returns (status, sig_mean (6,), iters, residual)."""
-    Eb = np.ascontiguousarray(Ebar, dtype=np.float64)
+    Eb = _ebar(Ebar)
     sm = np.zeros(6)
     it = C.c_int32(0)
     r = C.c_double(0.0)
@@ -166,7 +175,7 @@ def solve(handle, Ebar, tol, maxit, eps=None, sig=None):
 def solve_device(handle, Ebar, tol, maxit, eps_dev=None, sig_dev=None):
     """lsfft_solve_device.  eps_dev / sig_dev: contiguous device tensors of the
     solver precision with 6 N elements, or None."""
-    Eb = np.ascontiguousarray(Ebar, dtype=np.float64)
+    Eb = _ebar(Ebar)
     sm = np.zeros(6)
     it = C.c_int32(0)
     r = C.c_double(0.0)
@@ -204,6 +213,15 @@ def green_apply(handle, in_dev, out_dev):
     if st != OK:
         raise LsfftError(st, "lsfft_green_apply")
     return r.value
+
+
+def stiffness_gradient(handle, eps_a_dev, eps_b_dev, dj_dlambda=None, dj_dmu=None, dj_dyoung=None):
+    """lsfft_stiffness_gradient: device tensors of the solver precision."""
+    ptr = (lambda t: t.data_ptr() if t is not None else None)
+    st = _lib.lsfft_stiffness_gradient(handle, eps_a_dev.data_ptr(), eps_b_dev.data_ptr(), ptr(dj_dlambda),
+                                       ptr(dj_dmu), ptr(dj_dyoung))
+    if st != OK:
+        raise LsfftError(st, "lsfft_stiffness_gradient")
 
 
 def set_timing(handle, kernel_id):

@@ -86,3 +86,10 @@ def test_null_handles(L):
     assert L.destroy(None) == L.OK
     with pytest.raises(L.LsfftError):
         L.set_timing(None, 0)
+
+
+def test_macro_strain_must_have_six_components(L):
+    with pytest.raises(ValueError):
+        L.solve(None, np.zeros(3), 1e-6, 10)
+    with pytest.raises(ValueError):
+        L.solve_device(None, 1.0, 1e-6, 10)
