@@ -121,6 +121,19 @@ typedef struct {
  * device memory until lsfft_destroy. */
 lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out);
 
+/* Create one solver for `count` systems on the same grid, solved together:
+ * every kernel launch covers the whole batch (the system index is the second
+ * grid dimension) and each system stops on its own test.  Typical uses: the
+ * six load cases of an effective stiffness (cfgs[m] equal but for nothing, the
+ * loads differ at solve time), or several cells of equal size (cfgs[m]
+ * differ in lambda, mu, lambda0, mu0).  All cfgs must agree on n, h, disc,
+ * scheme, prec, form, dgo_images, dgo_weight_power, stream and f64_warmup
+ * (EINVAL otherwise); for the DGO they must also share lambda0 and mu0 (one
+ * table).  Memory: count times that of one system.  1 <= count <= 65535.
+ * lsfft_create(cfg, out) is lsfft_create_batch(cfg, 1, out).  The operator
+ * entry points and lsfft_residual_history act on system 0. */
+lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_solver *out);
+
 /* Solve for macroscopic strain Ebar[6] (Voigt tensor components).  Stops at
  * the first k with r_k <= tol (returns LSFFT_OK) or at k = maxit
  * (LSFFT_ENOTCONV).  r_k is the relative equilibrium norm
@@ -140,6 +153,20 @@ lsfft_status lsfft_solve(lsfft_solver s, const double Ebar[6], double tol, int32
 lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit,
                                 void *eps_dev, void *sig_dev, double sig_mean[6],
                                 int32_t *iters, double *residual);
+
+/* Solve every system of a batch handle: Ebar[count][6] (HOST), DEVICE outputs
+ * eps_dev and sig_dev of [count][6][N] values of the solver's precision (either
+ * may be NULL), HOST outputs sig_mean[count][6], iters[count],
+ * residual[count], status[count] (per-system lsfft_status; each may be NULL).
+ * Same stopping test as lsfft_solve, per system.  Returns the largest
+ * per-system status (OK < ENOTCONV < EDIVERGED) or a negative error.
+ * lsfft_solve and lsfft_solve_device return EINVAL on handles with count > 1. */
+lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, int32_t maxit,
+                               void *eps_dev, void *sig_dev, double *sig_mean, int32_t *iters,
+                               double *residual, int32_t *status);
+
+/* Number of systems of a handle (0 for NULL). */
+int32_t lsfft_batch_size(lsfft_solver s);
 
 /* Residual history r_0..r_iters of the last solve, copied to HOST out[0..cap);
  * *count receives iters + 1.  EINVAL if no solve has run. */
@@ -172,9 +199,9 @@ lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev
  *   dj_dyoung[x]  = (lambda dJ/dlambda + mu dJ/dmu) / E   (fixed Poisson ratio,
  *                   E = mu (3 lambda + 2 mu) / (lambda + mu) of voxel x).
  * Outputs: DEVICE arrays of N values of the solver's precision; any may be
- * NULL.  Computed in FP64.  The DGO iteration is not self-adjoint: its
- * sensitivities are not given by this entry point.  EINVAL on NULL handle or
- * strain fields. */
+ * NULL.  Computed in FP64 with the moduli of system 0 of a batch handle.
+ * The DGO iteration is not self-adjoint: its sensitivities are not given by
+ * this entry point.  EINVAL on NULL handle or strain fields. */
 lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, const void *eps_b_dev,
                                       void *dj_dlambda_dev, void *dj_dmu_dev, void *dj_dyoung_dev);
 

@@ -104,16 +104,21 @@ __device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, const 
 // ---------------------------------------------------------------- u update (x-lines)
 template <typename T> struct UArgs {
   Dims d;
-  double *u;          // [3][n3][n2][n1], FP64 whatever T
+  double *u;          // [system][3][n3][n2][n1], FP64 whatever T
   const cplx<T> *spec;
   const cplx<T> *nyq;
   const cplx<T> *tw;  // exp(-2 pi i m / n1)
-  const State *st;
+  const State *st;    // [system]
+  Strides bs;
 };
 
 template <typename T, int L, int E, int WG>
 __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  a.u += sysb * 3 * a.bs.field;
+  a.spec += sysb * a.bs.spec;
+  a.nyq += sysb * a.bs.nyq;
   __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
@@ -171,21 +176,31 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
 // n - {0,1}^3 (all indices periodic).
 template <typename T> struct SArgs {
   Dims d;
-  const double *u;     // FP64 displacement
-  const T *lam;
+  const double *u;     // FP64 displacement [system][3][N]
+  const T *lam;        // [system][N]
   const T *mu;
   cplx<T> *spec;
   cplx<T> *nyq;
   const cplx<T> *tw;   // exp(-2 pi i m / n1)
-  double Eb[6];
-  double hE[3][3];     // h_j Ebar_ij: the macroscopic part of an edge difference
+  const Member<T> *mem;  // Ebar, h_j Ebar_ij of each system
+  Strides bs;
   double ihu[3];       // 1 / h_r for the FP64 gradient
   T ih[3];             // 1 / h_r for the divergence
-  double *partial;     // [gridDim.x][8]: 6 stress sums, sum |f|^2
-  const State *st;
+  double *partial;     // [system][gridDim.x][8]: 6 stress sums, sum |f|^2
+  const State *st;     // [system]
   int Z;               // planes per workgroup
-  int zero_u;          // u is identically zero (first pass): skip its loads
+  int zero_u;          // u is identically zero (first pass): the LDS variant skips its loads
 };
+
+// Offset the per-system pointers of stencil arguments to system b.
+template <typename T> __device__ __forceinline__ void stencil_member(SArgs<T> &a, int b) {
+  a.u += b * 3 * a.bs.field;
+  a.lam += b * a.bs.field;
+  a.mu += b * a.bs.field;
+  a.spec += b * a.bs.spec;
+  a.nyq += b * a.bs.nyq;
+  if (a.partial) a.partial += b * a.bs.part;
+}
 
 template <int SCHEME> struct Stencil;
 
@@ -276,7 +291,12 @@ __device__ __forceinline__ void cell_stress(const double (&Eb)[6], const double 
 
 template <typename T, int N1, int E, int SCHEME, int T2>
 __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  stencil_member(a, sysb);
+  double Ebl[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Ebl[c] = a.mem[sysb].Eb[c];
   constexpr int WG = 256;
   constexpr int L = N1 / 2;
   constexpr int TPC = L / E;
@@ -389,7 +409,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
           Stencil<SCHEME>::grad(cv, ihu, gr[c]);
         }
         double sg[6];
-        cell_stress(a.Eb, gr, lm, m2, sg);
+        cell_stress(Ebl, gr, lm, m2, sg);
 #pragma unroll
         for (int c = 0; c < 6; ++c) Sp[(l * 6 + c) * N1 + x] = (T)sg[c];
         if (l >= 1 && z >= z0) {
@@ -482,7 +502,16 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 #endif
 template <typename T, int N1, int E, int SCHEME, int T2>
 __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  stencil_member(a, sysb);
+  // the system's constants in registers (a reference into global memory
+  // would be reloaded after every store of the march)
+  double hE[3][3];
+#pragma unroll
+  for (int q1 = 0; q1 < 3; ++q1)
+#pragma unroll
+    for (int q2 = 0; q2 < 3; ++q2) hE[q1][q2] = a.mem[sysb].hE[q1][q2];
   constexpr int WG = 256;
   constexpr int L = N1 / 2;
   constexpr int TPC = L / E;
@@ -567,7 +596,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 #pragma unroll
       for (int l = 0; l < NSL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ddy[v][l][c] = (T)((src[v][l + 1][c] - src[v][l][c]) + a.hE[c][1]);
+        for (int c = 0; c < 3; ++c) ddy[v][l][c] = (T)((src[v][l + 1][c] - src[v][l][c]) + hE[c][1]);
 #pragma unroll
     for (int v = 0; v < XV; ++v)
 #pragma unroll
@@ -581,7 +610,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 #pragma unroll
       for (int l = 0; l < NUL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ddx[v][l][c] = (T)((ux_at(l, c, x1) - src[v][l][c]) + a.hE[c][0]);
+        for (int c = 0; c < 3; ++c) ddx[v][l][c] = (T)((ux_at(l, c, x1) - src[v][l][c]) + hE[c][0]);
     }
   };
 
@@ -596,7 +625,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 #pragma unroll
       for (int l = 0; l < NUL; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dz[v][l][c] = (T)((u[Q][v][l][c] - u[P][v][l][c]) + a.hE[c][2]);
+        for (int c = 0; c < 3; ++c) dz[v][l][c] = (T)((u[Q][v][l][c] - u[P][v][l][c]) + hE[c][2]);
     fetch_u(u[P], z + 2);
     fetch_lm(lam[Q], mu[Q], z + 1);
     // The previous step's last reads of Ux (its exchange) and of the sigma
@@ -771,7 +800,11 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 // ---------------------------------------------------------------- z pass, displacement form
 template <typename T, int NZ, int E, int P>
 __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  a.spec += sysb * a.bs.spec;
+  a.nyq += sysb * a.bs.nyq;
+  member_green(a.g, a.mem, sysb);
   __shared__ cplx<T> twl_[NZ];
   constexpr int TPC = NZ / E;
   __shared__ cplx<T> lds[2 * NZ * P];

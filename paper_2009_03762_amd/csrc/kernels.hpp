@@ -44,6 +44,23 @@ struct State {
 
 enum { XMODE_INIT = 0, XMODE_UPDATE = 1, XMODE_DGO = 2, XMODE_EXTERNAL = 3 };
 
+// A solver holds a batch of systems on one grid (the load cases of a cell, or
+// several cells of equal size); every kernel takes its system from
+// blockIdx.y.  Per-system constants live in device memory:
+template <typename T> struct Member {
+  double Eb[6];      // macroscopic strain, Voigt tensor components
+  double hE[3][3];   // h_j Ebar_ij: the macroscopic part of an edge difference
+  T lam0, mu0;       // reference medium C0
+  T c1, c2, beta;    // 1/mu0, (lam0+mu0)/(mu0 (lam0+2 mu0)), (lam0+mu0)/(lam0+2 mu0)
+};
+// Element strides between consecutive systems of the batch.
+struct Strides {
+  long long field;   // one real N-voxel field (eps has 6, u has 3 of them)
+  long long spec;    // complex values of the main spectrum (all components)
+  long long nyq;     // complex values of the x-Nyquist plane (all components)
+  long long part;    // doubles of the block partial sums
+};
+
 template <typename T> struct XArgs {
   Dims d;
   T *eps;
@@ -53,10 +70,10 @@ template <typename T> struct XArgs {
   cplx<T> *spec;
   cplx<T> *nyq;
   const cplx<T> *tw;  // exp(-2 pi i m / n1), m = 0..n1-1
-  T Eb[6];
-  T lam0, mu0;
-  double *partial;    // [gridDim.x][8]
-  const State *st;
+  const Member<T> *mem;
+  Strides bs;
+  double *partial;    // [system][gridDim.x][8]
+  const State *st;    // [system]
   int mode;
   int polarisation;   // transform (C - C0) : eps instead of C : eps
 };
@@ -192,7 +209,19 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long nblocks) {
 // that their latencies overlap.
 template <typename T, int L, int E, int WG>
 __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  a.eps += sysb * 6 * a.bs.field;
+  a.lam += sysb * a.bs.field;
+  a.mu += sysb * a.bs.field;
+  a.spec += sysb * a.bs.spec;
+  a.nyq += sysb * a.bs.nyq;
+  if (a.partial) a.partial += sysb * a.bs.part;
+  // the system's constants in registers
+  T Ebl[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Ebl[c] = (T)a.mem[sysb].Eb[c];
+  const T lam0 = a.mem[sysb].lam0, mu0 = a.mem[sysb].mu0;
   __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
@@ -281,11 +310,11 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
         n0 = o0 + w[c][e].x;
         n1v = o1 + w[c][e].y;
       } else if (a.mode == XMODE_DGO) {
-        n0 = a.Eb[c] + w[c][e].x;
-        n1v = a.Eb[c] + w[c][e].y;
+        n0 = Ebl[c] + w[c][e].x;
+        n1v = Ebl[c] + w[c][e].y;
       } else if (a.mode == XMODE_INIT) {
-        n0 = a.Eb[c];
-        n1v = a.Eb[c];
+        n0 = Ebl[c];
+        n1v = Ebl[c];
       } else {
         n0 = o0;
         n1v = o1;
@@ -302,7 +331,7 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
     for (int h = 0; h < 2; ++h) {
       const T tr = ev[0][h] + ev[1][h] + ev[2][h];
       const T l = lam[e][h], m2 = T(2) * mu[e][h];
-      const T lp = l - a.lam0, mp2 = m2 - T(2) * a.mu0;
+      const T lp = l - lam0, mp2 = m2 - T(2) * mu0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const T sg = (c < 3 ? l * tr : T(0)) + m2 * ev[c][h];
@@ -339,7 +368,8 @@ template <typename T> struct YArgs {
   cplx<T> *spec;
   cplx<T> *nyq;
   const cplx<T> *tw;  // exp(-2 pi i m / n2)
-  const State *st;
+  const State *st;    // [system]
+  Strides bs;
   long long main_blocks;
   int ncomp;          // components transformed (6 strain form, 3 displacement form)
 };
@@ -348,7 +378,10 @@ template <typename T> struct YArgs {
 // n1/2 between y points; Nyquist plane = (c, k3) rows, stride 1.
 template <typename T, int NY, int E, int P, bool FWD>
 __global__ __launch_bounds__(P *(NY / E)) void k_ypass(YArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  a.spec += sysb * a.bs.spec;
+  a.nyq += sysb * a.bs.nyq;
   __shared__ cplx<T> twl_[NY];
   constexpr int TPC = NY / E;
   __shared__ cplx<T> lds[2 * NY * P];
@@ -390,15 +423,33 @@ template <typename T> struct ZArgs {
   cplx<T> *nyq;
   const cplx<T> *tw;  // exp(-2 pi i m / n3)
   GreenParams<T> g;
-  double *partial;    // [gridDim.x]
-  const State *st;
+  const Member<T> *mem;  // reference medium of each system (null: g as given)
+  Strides bs;
+  double *partial;    // [system][gridDim.x]
+  const State *st;    // [system]
   long long main_blocks;
   int forward_only;   // 1: forward transform only (operator entry point)
 };
 
+// The Green parameters of system b: the shared tables and the system's C0.
+template <typename T> __device__ __forceinline__ void member_green(GreenParams<T> &g, const Member<T> *mem, int b) {
+  if (!mem) return;
+  const Member<T> &m = mem[b];
+  g.lam0 = m.lam0;
+  g.mu0 = m.mu0;
+  g.c1 = m.c1;
+  g.c2 = m.c2;
+  g.beta = m.beta;
+}
+
 template <typename T, int NZ, int E, int P>
 __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
-  if (a.st && a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st && a.st[sysb].done) return;
+  a.spec += sysb * a.bs.spec;
+  a.nyq += sysb * a.bs.nyq;
+  if (a.partial) a.partial += sysb * a.bs.part;
+  member_green(a.g, a.mem, sysb);
   __shared__ cplx<T> twl_[NZ];
   constexpr int TPC = NZ / E;
   constexpr int WG = P * TPC;
@@ -487,24 +538,30 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
 constexpr int RSTAGE = 64;
 
 struct ReduceArgs {
-  const double *px;   // x-pass block sums [nx][8] (6 stress sums, |d eps|^2, unused)
+  const double *px;   // x-pass block sums [system][nx][8] (6 stress sums, |d eps|^2, unused)
   int nx;
-  const double *pz;   // z-pass block sums [nz]
+  const double *pz;   // z-pass block sums [system][nz]
   int nz;
-  double *stage;      // [RSTAGE][8]: 6 stress sums, |d eps|^2, residual
-  State *st;
-  double *hist;
+  long long spx, spz; // strides between systems
+  double *stage;      // [system][RSTAGE][8]: 6 stress sums, |d eps|^2, residual
+  State *st;          // [system]
+  double *hist;       // [system][hcap]
+  long long hcap;
+  const double *ebar_norms;  // [system] |Ebar|_F
   int k, maxit;
   double tol;
   int dgo;
   int disp;           // displacement form: residual from sum_x |div sigma|^2 (x-side slot 6)
   double N;
-  double ebar_norm;   // |Ebar|_F
   double div_factor;
 };
 
 __global__ __launch_bounds__(256) void k_reduce_stage(ReduceArgs a) {
-  if (a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st[sysb].done) return;
+  a.px += sysb * a.spx;
+  a.pz += sysb * a.spz;
+  a.stage += (long long)sysb * RSTAGE * 8;
   __shared__ double red[4 * 8];
   const int b = blockIdx.x;
   const long long cx = (a.nx + RSTAGE - 1) / RSTAGE, cz = (a.nz + RSTAGE - 1) / RSTAGE;
@@ -520,7 +577,12 @@ __global__ __launch_bounds__(256) void k_reduce_stage(ReduceArgs a) {
 }
 
 __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
-  if (a.st->done) return;
+  const int sysb = blockIdx.y;
+  if (a.st[sysb].done) return;
+  a.stage += (long long)sysb * RSTAGE * 8;
+  a.st += sysb;
+  a.hist += sysb * a.hcap;
+  const double ebar_norm = a.ebar_norms[sysb];
   __shared__ double red[8];
   double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < RSTAGE; i += 64)
@@ -536,7 +598,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   }
   double r;
   if (a.dgo) {
-    r = (a.k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * a.ebar_norm);
+    r = (a.k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * ebar_norm);
   } else {
     const double num = a.disp ? sqrt(a.N * vals[6]) : sqrt(vals[7]);
     const double den = a.N * sqrt(sn);
@@ -571,8 +633,10 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   }
 }
 
-__global__ void k_state_init(State *s) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_state_init(State *st, int count) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < count) {
+    State *s = st + b;
     s->done = 0;
     s->status = 1;
     s->iters = 0;

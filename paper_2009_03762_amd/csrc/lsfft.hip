@@ -148,7 +148,14 @@ template <typename T> std::vector<T> axis_tables(const int n[3], const double h[
 struct lsfft_solver_s {
   int n[3];
   double h[3];
-  double lam0, mu0;
+  double lam0, mu0;       // reference medium of system 0 (operator entry points)
+  int B = 1;              // systems in the batch
+  int launch_b = 1;       // systems covered by the launches being issued
+  std::vector<double> lam0v, mu0v;  // reference medium of every system
+  void *mem = nullptr;    // lsfft::Member<T>[B]
+  double *enorm = nullptr;  // |Ebar|_F of every system
+  lsfft::Strides bs{};
+  long long spx = 0, spz = 0;  // doubles between systems in px / pz
   int disc, scheme, prec, M, pw;
   hipStream_t stream;
   Dims d;
@@ -209,7 +216,7 @@ template <typename T> struct Launch {
     switch (s->d.L) {
 #define XCASE(Lv)                                                                                        \
   case Lv:                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid), dim3(XWG), 0, s->stream, a); \
+    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
     return hipGetLastError();
       LSFFT_X_LENGTHS(XCASE)
 #undef XCASE
@@ -237,7 +244,7 @@ template <typename T> struct Launch {
 #define YCASE(Nv)                                                                                     \
   case Nv: {                                                                                          \
     constexpr int E = ey_of(Nv), P = pcols<T>(Nv, E);                                                 \
-    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P, FWD>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P, FWD>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
     return hipGetLastError();                                                                          \
   }
       LSFFT_YZ_LENGTHS(YCASE)
@@ -262,7 +269,7 @@ template <typename T> struct Launch {
 #define ZCASE(Nv)                                                                                   \
   case Nv: {                                                                                        \
     constexpr int E = ez_of(Nv), P = pcols_z<T>(Nv, E);                                             \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
     return hipGetLastError();                                                                        \
   }
       LSFFT_YZ_LENGTHS(ZCASE)
@@ -297,7 +304,7 @@ template <typename T> struct Launch {
     switch (s->d.L) {
 #define UCASE(Lv)                                                                                         \
   case Lv:                                                                                                \
-    hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid), dim3(XWG), 0, s->stream, a); \
+    hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
     return hipGetLastError();
       LSFFT_X_LENGTHS(UCASE)
 #undef UCASE
@@ -310,11 +317,11 @@ template <typename T> struct Launch {
 #define SCASE(Lv)                                                                                      \
   case 2 * Lv:                                                                                         \
     if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
-      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid), dim3(256), \
+      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), \
                          0, s->stream, a);                                                             \
       return hipGetLastError();                                                                        \
     } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
-      hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid), dim3(256), 0, \
+      hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), 0, \
                          s->stream, a);                                                                \
       return hipGetLastError();                                                                        \
     } else {                                                                                           \
@@ -334,7 +341,7 @@ template <typename T> struct Launch {
 #define ZUCASE(Nv)                                                                                    \
   case Nv: {                                                                                          \
     constexpr int E = ezu_of(Nv), P = pcols_zu<T>(Nv, E);                                             \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P>), dim3(grid), dim3(P * (Nv / E)), 0, s->stream, a); \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
     return hipGetLastError();                                                                          \
   }
       LSFFT_YZ_LENGTHS(ZUCASE)
@@ -396,8 +403,7 @@ struct Timed {
   }
 };
 
-template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, const double Eb[6], int mode, const void *eps_in,
-                                             bool with_partial) {
+template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, int mode, const void *eps_in, bool with_partial) {
   lsfft::XArgs<T> a;
   a.d = s->d;
   a.eps = (T *)s->eps;
@@ -407,9 +413,9 @@ template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, const double Eb[6], 
   a.spec = (cplx<T> *)s->spec;
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
-  for (int c = 0; c < 6; ++c) a.Eb[c] = (T)(Eb ? Eb[c] : 0.0);
-  a.lam0 = (T)s->lam0;
-  a.mu0 = (T)s->mu0;
+  a.mem = (const lsfft::Member<T> *)s->mem;
+  a.bs = s->bs;
+  a.bs.part = s->spx;
   a.partial = with_partial ? s->px : nullptr;
   a.st = with_partial ? s->st : nullptr;
   a.mode = mode;
@@ -425,6 +431,7 @@ template <typename T> lsfft::YArgs<T> yargs(lsfft_solver s, bool flag, int ncomp
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twy;
   a.st = flag ? s->st : nullptr;
+  a.bs = s->bs;
   const int py = Launch<T>::ycols(s->n[1]);
   a.main_blocks = ((long long)ncomp * s->n[2] * s->d.L + py - 1) / py;
   return a;
@@ -442,6 +449,9 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twz;
   a.g = green_params<T>(s);
+  a.mem = (const lsfft::Member<T> *)s->mem;
+  a.bs = s->bs;
+  a.bs.part = s->spz;
   a.partial = flag ? s->pz : nullptr;
   a.st = flag ? s->st : nullptr;
   a.main_blocks = s->z_main_blocks;
@@ -449,7 +459,7 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
   return a;
 }
 
-template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, const double Eb[6], int zero_u) {
+template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   lsfft::SArgs<T> a;
   a.d = s->d;
   a.u = (const double *)s->u;
@@ -458,12 +468,12 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, const double Eb[6], 
   a.spec = (cplx<T> *)s->spec;
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
-  for (int c = 0; c < 6; ++c) a.Eb[c] = Eb[c];
-  static const int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  a.mem = (const lsfft::Member<T> *)s->mem;
+  a.bs = s->bs;
+  a.bs.part = s->spx;
   for (int r = 0; r < 3; ++r) {
     a.ihu[r] = 1.0 / s->h[r];
     a.ih[r] = (T)(1.0 / s->h[r]);
-    for (int i = 0; i < 3; ++i) a.hE[i][r] = s->h[r] * Eb[vo[i][r]];
   }
   a.partial = s->px;
   a.st = s->st;
@@ -480,76 +490,119 @@ template <typename T> lsfft::UArgs<T> uargs(lsfft_solver s) {
   a.nyq = (const cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
   a.st = s->st;
+  a.bs = s->bs;
   return a;
 }
 
-template <typename T> hipError_t strain_from_u(lsfft_solver s, const double Eb[6]) {
+// eps of every system from its displacement; Eb: [B][6]
+template <typename T> hipError_t strain_from_u(lsfft_solver s, const double *Eb) {
   const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
   const double ih0 = 1.0 / s->h[0], ih1 = 1.0 / s->h[1], ih2 = 1.0 / s->h[2];
-  if (s->scheme == LSFFT_FB)
-    hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_FB>), dim3(blocks), dim3(256), 0, s->stream,
-                       (const double *)s->u, (T *)s->eps, s->d, Eb[0], Eb[1], Eb[2], Eb[3], Eb[4], Eb[5], ih0,
-                       ih1, ih2);
-  else
-    hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_AFB>), dim3(blocks), dim3(256), 0, s->stream,
-                       (const double *)s->u, (T *)s->eps, s->d, Eb[0], Eb[1], Eb[2], Eb[3], Eb[4], Eb[5], ih0,
-                       ih1, ih2);
-  return hipGetLastError();
+  for (int b = 0; b < s->B; ++b) {
+    const double *u = (const double *)s->u + (long long)b * 3 * s->d.N;
+    T *eps = (T *)s->eps + (long long)b * 6 * s->d.N;
+    const double *e = Eb + 6 * b;
+    if (s->scheme == LSFFT_FB)
+      hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_FB>), dim3(blocks), dim3(256), 0, s->stream, u,
+                         eps, s->d, e[0], e[1], e[2], e[3], e[4], e[5], ih0, ih1, ih2);
+    else
+      hipLaunchKernelGGL((lsfft::k_strain_from_u<T, lsfft::SCHEME_AFB>), dim3(blocks), dim3(256), 0, s->stream, u,
+                         eps, s->d, e[0], e[1], e[2], e[3], e[4], e[5], ih0, ih1, ih2);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
-// Iterations k_begin .. k_end-1 of a solve (maxit, tol as in lsfft_solve).
+// Per-system constants (macroscopic strain Eb[B][6], reference medium) to the device.
+template <typename T> lsfft_status upload_members(lsfft_solver s, const double *Eb) {
+  std::vector<lsfft::Member<T>> m(s->B);
+  std::vector<double> en(s->B);
+  static const int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  for (int b = 0; b < s->B; ++b) {
+    const double *e = Eb ? Eb + 6 * b : nullptr;
+    double nrm = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      m[b].Eb[c] = e ? e[c] : 0.0;
+      nrm += (c < 3 ? 1.0 : 2.0) * m[b].Eb[c] * m[b].Eb[c];
+    }
+    en[b] = std::sqrt(nrm);
+    for (int i = 0; i < 3; ++i)
+      for (int r = 0; r < 3; ++r) m[b].hE[i][r] = s->h[r] * m[b].Eb[vo[i][r]];
+    const double l0 = s->lam0v[b], m0 = s->mu0v[b];
+    m[b].lam0 = (T)l0;
+    m[b].mu0 = (T)m0;
+    m[b].c1 = (T)(1.0 / m0);
+    m[b].c2 = (T)((l0 + m0) / (m0 * (l0 + 2.0 * m0)));
+    m[b].beta = (T)((l0 + m0) / (l0 + 2.0 * m0));
+  }
+  LSFFT_CHECK(hipMemcpyAsync(s->mem, m.data(), sizeof(lsfft::Member<T>) * s->B, hipMemcpyHostToDevice, s->stream));
+  LSFFT_CHECK(hipMemcpyAsync(s->enorm, en.data(), sizeof(double) * s->B, hipMemcpyHostToDevice, s->stream));
+  // the host vectors go out of scope: wait for the copies
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  return LSFFT_OK;
+}
+
+bool all_done(const lsfft_solver s) {
+  for (int b = 0; b < s->B; ++b)
+    if (!s->st_host[b].done) return false;
+  return true;
+}
+
+// Iterations k_begin .. k_end-1 of a solve (maxit, tol as in lsfft_solve) of
+// every system of the batch, whose constants upload_members has set.
 // fresh: start from u = 0 / eps = Ebar with a new device state; otherwise the
 // state, history and u left by an earlier phase are continued (displacement
 // form), after re-evaluating the stencil on that u in this precision.
-// Returns LSFFT_OK when the iterations ran, even if the state is not done.
+// Returns LSFFT_OK when the iterations ran, even if not every system is done.
 template <typename T>
-lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit, int k_begin, int k_end,
-                       bool fresh) {
+lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k_end, bool fresh) {
   using L = Launch<T>;
-  double en = 0.0;
-  for (int c = 0; c < 6; ++c) en += (c < 3 ? 1.0 : 2.0) * Eb[c] * Eb[c];
-  en = std::sqrt(en);
   const bool dgo = (s->scheme == LSFFT_DGO);
   const bool disp = s->disp != 0;
   const int ncomp = disp ? 3 : 6;
+  s->launch_b = s->B;
   if (fresh) {
-    hipLaunchKernelGGL(lsfft::k_state_init, dim3(1), dim3(1), 0, s->stream, s->st);
+    hipLaunchKernelGGL(lsfft::k_state_init, dim3((s->B + 63) / 64), dim3(64), 0, s->stream, s->st, s->B);
     LSFFT_CHECK(hipGetLastError());
   }
   if (disp) {
     if (fresh) {
-      const long long nu = 3 * s->d.N;
+      const long long nu = 3 * s->d.N * s->B;
       hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
                          dim3(256), 0, s->stream, (double *)s->u, nu);
       LSFFT_CHECK(hipGetLastError());
     }
     Timed tm(s, 0);
-    LSFFT_CHECK(L::stencil(s, sargs<T>(s, Eb, fresh ? 1 : 0), s->nsb));
+    LSFFT_CHECK(L::stencil(s, sargs<T>(s, fresh ? 1 : 0), s->nsb));
   } else {
     Timed tm(s, 0);
-    LSFFT_CHECK(L::xpass(s, xargs<T>(s, Eb, lsfft::XMODE_INIT, nullptr, true), s->nxb));
+    LSFFT_CHECK(L::xpass(s, xargs<T>(s, lsfft::XMODE_INIT, nullptr, true), s->nxb));
   }
   const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
   const int nyg = ygrid<T>(s, ncomp);
   lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
   if (disp) za.main_blocks = s->zu_main_blocks;
-  const lsfft::XArgs<T> xa = xargs<T>(s, Eb, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
-  const lsfft::SArgs<T> sa = sargs<T>(s, Eb, 0);
+  const lsfft::XArgs<T> xa = xargs<T>(s, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
+  const lsfft::SArgs<T> sa = sargs<T>(s, 0);
   const lsfft::UArgs<T> ua = uargs<T>(s);
   lsfft::ReduceArgs ra;
   ra.px = s->px;
   ra.nx = disp ? s->nsb : s->nxb;
   ra.pz = s->pz;
   ra.nz = disp ? 0 : s->nzb;
+  ra.spx = s->spx;
+  ra.spz = s->spz;
   ra.stage = s->pstage;
   ra.st = s->st;
   ra.hist = s->hist;
+  ra.hcap = s->hist_cap;
+  ra.ebar_norms = s->enorm;
   ra.maxit = maxit;
   ra.tol = tol;
   ra.dgo = dgo ? 1 : 0;
   ra.disp = disp ? 1 : 0;
   ra.N = (double)s->d.N;
-  ra.ebar_norm = en;
   ra.div_factor = 1e6;
   int k = k_begin;
   int chunk = (tol == 0.0) ? k_end - k_begin : 2;
@@ -567,9 +620,9 @@ lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit
       ra.k = k;
       {
         Timed tm(s, 5);
-        hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE), dim3(256), 0, s->stream, ra);
+        hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE, s->B), dim3(256), 0, s->stream, ra);
         LSFFT_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1), dim3(64), 0, s->stream, ra);
+        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1, s->B), dim3(64), 0, s->stream, ra);
         LSFFT_CHECK(hipGetLastError());
       }
       {
@@ -582,7 +635,7 @@ lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit
           LSFFT_CHECK(L::uxpass(s, ua, s->nub));
         }
         // the last iteration of a phase leaves the stencil to the next one
-        // (at k = maxit the state is done and the stencil would return at once)
+        // (at k = maxit every system is done and the stencil would return at once)
         if (k + 1 < k_end) {
           Timed tm(s, 0);
           LSFFT_CHECK(L::stencil(s, sa, s->nsb));
@@ -592,24 +645,31 @@ lsfft_status run_phase(lsfft_solver s, const double Eb[6], double tol, int maxit
         LSFFT_CHECK(L::xpass(s, xa, s->nxb));
       }
     }
-    LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State), hipMemcpyDeviceToHost, s->stream));
+    LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State) * s->B, hipMemcpyDeviceToHost, s->stream));
     LSFFT_CHECK(hipStreamSynchronize(s->stream));
-    if (s->st_host->done || k >= k_end) break;
+    if (all_done(s) || k >= k_end) break;
     chunk = std::min(chunk * 2, 64);
   }
   return LSFFT_OK;
 }
 
+// Eb: [B][6].  Returns the largest status over the systems (OK < ENOTCONV <
+// EDIVERGED) or a negative error.
 template <typename T>
-lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit) {
+lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) {
   if (maxit + 1 > s->hist_cap) {
     if (s->hist) (void)hipFree(s->hist);
     s->hist = nullptr;
     int cap = maxit + 1 < 1024 ? 1024 : maxit + 1;
-    if (hipMalloc(&s->hist, sizeof(double) * cap) != hipSuccess) return LSFFT_ENOMEM;
+    if (hipMalloc(&s->hist, sizeof(double) * cap * (size_t)s->B) != hipSuccess) {
+      s->hist_cap = 0;
+      return LSFFT_ENOMEM;
+    }
     s->hist_cap = cap;
   }
   s->ev_used = 0;
+  lsfft_status us = upload_members<T>(s, Eb);
+  if (us != LSFFT_OK) return us;
   int k0 = 0;
   if (s->twin && s->warm > 0) {
     // FP64 iterations 0 .. k0-1 on the shared u, state and history
@@ -617,19 +677,21 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
     t->hist = s->hist;
     t->hist_cap = s->hist_cap;
     t->timing_kernel = -1;
+    us = upload_members<double>(t, Eb);
+    if (us != LSFFT_OK) return us;
     k0 = std::min(s->warm, maxit + 1);
-    lsfft_status ps = run_phase<double>(t, Eb, tol, maxit, 0, k0, true);
+    lsfft_status ps = run_phase<double>(t, tol, maxit, 0, k0, true);
     if (ps != LSFFT_OK) return ps;
   }
-  if (k0 == 0 || (!s->st_host->done && k0 <= maxit)) {
-    lsfft_status ps = run_phase<T>(s, Eb, tol, maxit, k0, maxit + 1, k0 == 0);
+  if (k0 == 0 || (!all_done(s) && k0 <= maxit)) {
+    lsfft_status ps = run_phase<T>(s, tol, maxit, k0, maxit + 1, k0 == 0);
     if (ps != LSFFT_OK) return ps;
   }
-  if (!s->st_host->done) return LSFFT_EDEVICE;
+  if (!all_done(s)) return LSFFT_EDEVICE;
   if (s->disp) {
     LSFFT_CHECK(strain_from_u<T>(s, Eb));
   }
-  s->last_iters = s->st_host->iters;
+  s->last_iters = s->st_host[0].iters;
   if (s->timing_kernel >= 0 && s->ev_used >= 2) {
     double tot = 0.0;
     int cnt = 0;
@@ -643,14 +705,19 @@ lsfft_status run_solve(lsfft_solver s, const double Eb[6], double tol, int maxit
     s->timing_mean = cnt ? tot / cnt : 0.0;
     s->timing_count = cnt;
   }
-  return (lsfft_status)s->st_host->status;
+  int worst = 0;
+  for (int b = 0; b < s->B; ++b) worst = std::max(worst, s->st_host[b].status);
+  return (lsfft_status)worst;
 }
 
+// Outputs of every system: eps_out / sig_out hold [B][6][N] values (host
+// doubles or device T); either may be null.
 template <typename T> lsfft_status finish_outputs(lsfft_solver s, void *eps_out, void *sig_out, bool host) {
-  const size_t bytes = 6 * (size_t)s->d.N * sizeof(T);
+  const size_t n6 = 6 * (size_t)s->d.N;
+  const size_t bytes = n6 * (size_t)s->B * sizeof(T);
   if (eps_out) {
     if (host) {
-      std::vector<T> tmp(6 * (size_t)s->d.N);
+      std::vector<T> tmp(n6 * s->B);
       LSFFT_CHECK(hipMemcpyAsync(tmp.data(), s->eps, bytes, hipMemcpyDeviceToHost, s->stream));
       LSFFT_CHECK(hipStreamSynchronize(s->stream));
       double *o = (double *)eps_out;
@@ -661,18 +728,20 @@ template <typename T> lsfft_status finish_outputs(lsfft_solver s, void *eps_out,
   }
   if (sig_out) {
     T *dst = nullptr;
-    bool tmp_dev = host;
     if (host) {
       LSFFT_CHECK(hipMalloc(&dst, bytes));
     } else {
       dst = (T *)sig_out;
     }
     const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
-    hipLaunchKernelGGL(lsfft::k_hooke_out<T>, dim3(blocks), dim3(256), 0, s->stream, (const T *)s->eps,
-                       (const T *)s->lam, (const T *)s->mu, dst, s->d.N);
-    LSFFT_CHECK(hipGetLastError());
-    if (tmp_dev) {
-      std::vector<T> tmp(6 * (size_t)s->d.N);
+    for (int b = 0; b < s->B; ++b) {
+      const long long off = (long long)b * s->d.N;
+      hipLaunchKernelGGL(lsfft::k_hooke_out<T>, dim3(blocks), dim3(256), 0, s->stream, (const T *)s->eps + 6 * off,
+                         (const T *)s->lam + off, (const T *)s->mu + off, dst + 6 * off, s->d.N);
+      LSFFT_CHECK(hipGetLastError());
+    }
+    if (host) {
+      std::vector<T> tmp(n6 * s->B);
       LSFFT_CHECK(hipMemcpyAsync(tmp.data(), dst, bytes, hipMemcpyDeviceToHost, s->stream));
       LSFFT_CHECK(hipStreamSynchronize(s->stream));
       (void)hipFree(dst);
@@ -690,15 +759,17 @@ bool finite_all(const double *p, long long n) {
   return true;
 }
 
-template <typename T> lsfft_status upload_moduli(lsfft_solver s, const double *lam, const double *mu) {
+template <typename T> lsfft_status upload_moduli(lsfft_solver s, const lsfft_config *cfg) {
   const size_t N = (size_t)s->d.N;
   std::vector<T> a(N), b(N);
-  for (size_t i = 0; i < N; ++i) {
-    a[i] = (T)lam[i];
-    b[i] = (T)mu[i];
+  for (int m = 0; m < s->B; ++m) {
+    for (size_t i = 0; i < N; ++i) {
+      a[i] = (T)cfg[m].lambda[i];
+      b[i] = (T)cfg[m].mu[i];
+    }
+    LSFFT_CHECK(hipMemcpy((T *)s->lam + m * N, a.data(), N * sizeof(T), hipMemcpyHostToDevice));
+    LSFFT_CHECK(hipMemcpy((T *)s->mu + m * N, b.data(), N * sizeof(T), hipMemcpyHostToDevice));
   }
-  LSFFT_CHECK(hipMemcpy(s->lam, a.data(), N * sizeof(T), hipMemcpyHostToDevice));
-  LSFFT_CHECK(hipMemcpy(s->mu, b.data(), N * sizeof(T), hipMemcpyHostToDevice));
   return LSFFT_OK;
 }
 
@@ -750,8 +821,8 @@ void release(lsfft_solver s) {
     s->st_host = nullptr;
     s->hist = nullptr;
   }
-  void *ptrs[] = {s->eps, s->lam, s->mu, s->spec, s->nyq, s->tab, s->twx, s->twy, s->twz, s->u,
-                  s->dgo_main, s->dgo_nyq, s->px, s->pz, s->pg, s->pstage, s->st, s->hist};
+  void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
+                  s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -760,7 +831,8 @@ void release(lsfft_solver s) {
 }
 
 template <typename T> lsfft_status stress_spectrum_impl(lsfft_solver s, const void *eps_dev, void *out) {
-  LSFFT_CHECK(Launch<T>::xpass(s, xargs<T>(s, nullptr, lsfft::XMODE_EXTERNAL, eps_dev, false), s->nxb));
+  s->launch_b = 1;  // the operator entry points act on system 0
+  LSFFT_CHECK(Launch<T>::xpass(s, xargs<T>(s, lsfft::XMODE_EXTERNAL, eps_dev, false), s->nxb));
   LSFFT_CHECK(Launch<T>::template ypass<true>(s, yargs<T>(s, false), s->nyb));
   LSFFT_CHECK(Launch<T>::zpass(s, zargs<T>(s, false, 1), s->nzb));
   const long long total = 6LL * s->d.rows * (s->d.L + 1);
@@ -815,9 +887,10 @@ const char *lsfft_kernel_name(int32_t id) {
   return (id >= 0 && id < 6) ? names[id] : "none";
 }
 
-lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
-  if (!cfg || !out || !cfg->lambda || !cfg->mu) return LSFFT_EINVAL;
+lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_solver *out) {
+  if (!cfgs || !out || count < 1 || count > 65535) return LSFFT_EINVAL;
   *out = nullptr;
+  const lsfft_config *cfg = cfgs;
   for (int r = 0; r < 3; ++r) {
     if (!supported_len(cfg->n[r])) return LSFFT_EINVAL;
     if (!(cfg->h[r] >= 0.0) || !std::isfinite(cfg->h[r])) return LSFFT_EINVAL;
@@ -832,18 +905,37 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
     if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
     if (cfg->dgo_weight_power != 1 && cfg->dgo_weight_power != 2) return LSFFT_EINVAL;
   }
-  if (!ok_moduli(cfg->lambda0, cfg->mu0)) return LSFFT_EINVAL;
   const long long N = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
-  for (long long i = 0; i < N; ++i)
-    if (!ok_moduli(cfg->lambda[i], cfg->mu[i])) return LSFFT_EINVAL;
+  for (int m = 0; m < count; ++m) {
+    const lsfft_config *c = cfgs + m;
+    if (!c->lambda || !c->mu) return LSFFT_EINVAL;
+    // every system shares the grid and the solver options
+    for (int r = 0; r < 3; ++r)
+      if (c->n[r] != cfg->n[r] || c->h[r] != cfg->h[r]) return LSFFT_EINVAL;
+    if (c->disc != cfg->disc || c->scheme != cfg->scheme || c->prec != cfg->prec || c->form != cfg->form ||
+        c->dgo_images != cfg->dgo_images || c->dgo_weight_power != cfg->dgo_weight_power ||
+        c->stream != cfg->stream || c->f64_warmup != cfg->f64_warmup)
+      return LSFFT_EINVAL;
+    if (!ok_moduli(c->lambda0, c->mu0)) return LSFFT_EINVAL;
+    // the DGO table depends on C0: one table, one reference medium
+    if (cfg->scheme == LSFFT_DGO && (c->lambda0 != cfg->lambda0 || c->mu0 != cfg->mu0)) return LSFFT_EINVAL;
+    for (long long i = 0; i < N; ++i)
+      if (!ok_moduli(c->lambda[i], c->mu[i])) return LSFFT_EINVAL;
+  }
 
   lsfft_solver s = new lsfft_solver_s();
   for (int r = 0; r < 3; ++r) {
     s->n[r] = cfg->n[r];
     s->h[r] = cfg->h[r] > 0.0 ? cfg->h[r] : 1.0;
   }
+  s->B = count;
+  s->launch_b = count;
   s->lam0 = cfg->lambda0;
   s->mu0 = cfg->mu0;
+  for (int m = 0; m < count; ++m) {
+    s->lam0v.push_back(cfgs[m].lambda0);
+    s->mu0v.push_back(cfgs[m].mu0);
+  }
   s->disc = cfg->disc;
   s->scheme = cfg->scheme;
   s->prec = cfg->prec;
@@ -858,24 +950,31 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   s->d.rows = (long long)s->n[1] * s->n[2];
   s->d.comp_main = s->d.rows * s->d.L;
   s->d.comp_nyq = s->d.rows;
+  s->bs.field = N;
+  s->bs.spec = 6 * s->d.comp_main;
+  s->bs.nyq = 6 * s->d.comp_nyq;
 
   const size_t es = esize(s);
   const size_t cs = 2 * es;
+  const size_t B = (size_t)count;
   lsfft_status st = LSFFT_OK;
   auto fail = [&](lsfft_status e) {
     release(s);
     delete s;
     return e;
   };
-  if (hipMalloc(&s->eps, 6 * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->lam, (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->mu, (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->spec, 6 * (size_t)s->d.comp_main * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->nyq, 6 * (size_t)s->d.comp_nyq * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->st, sizeof(State)) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipHostMalloc(&s->st_host, sizeof(State), 0) != hipSuccess) return fail(LSFFT_ENOMEM);
-  st = (s->prec == LSFFT_F32) ? upload_moduli<float>(s, cfg->lambda, cfg->mu)
-                              : upload_moduli<double>(s, cfg->lambda, cfg->mu);
+  if (hipMalloc(&s->eps, B * 6 * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->lam, B * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->mu, B * (size_t)N * es) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->spec, B * 6 * (size_t)s->d.comp_main * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->nyq, B * 6 * (size_t)s->d.comp_nyq * cs) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->st, B * sizeof(State)) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipHostMalloc(&s->st_host, B * sizeof(State), 0) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->mem, B * (s->prec == LSFFT_F32 ? sizeof(lsfft::Member<float>) : sizeof(lsfft::Member<double>))) !=
+      hipSuccess)
+    return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->enorm, B * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+  st = (s->prec == LSFFT_F32) ? upload_moduli<float>(s, cfgs) : upload_moduli<double>(s, cfgs);
   if (st != LSFFT_OK) return fail(st);
   st = (s->prec == LSFFT_F32) ? upload_tables<float>(s) : upload_tables<double>(s);
   if (st != LSFFT_OK) return fail(st);
@@ -885,16 +984,17 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
     s->disp = (cfg->form == 1) ? 0 : (fits ? 1 : 0);
   }
   if (s->disp) {
-    if (hipMalloc(&s->u, 3 * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->u, B * 3 * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
     // y-blocks: a power-of-two n1 < 256 packs 256/n1 independent y-groups per workgroup
     const int n1 = s->n[0];
     const bool pow2 = stencil_reg_kernel(n1);
     const int G = (pow2 && n1 < 256) ? 256 / n1 : 1;
     const int ny = (s->n[1] + G * ST2 - 1) / (G * ST2);
-    // planes per stencil workgroup: as many as keep >= 1024 workgroups, at least 2
+    // planes per stencil workgroup: as many as keep >= 1024 workgroups (over
+    // the whole batch), at least 2
     int Z = 2;
     for (int c : {32, 16, 8, 4}) {
-      if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) >= 1024) {
+      if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) * count >= 1024) {
         Z = c;
         break;
       }
@@ -907,23 +1007,29 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
     s->zu_main_blocks = ((long long)s->n[1] * s->d.L + pzu - 1) / pzu;
     s->nzub = (int)(s->zu_main_blocks + ((long long)s->n[1] + pzu - 1) / pzu);
   }
-  if (hipMalloc(&s->px, sizeof(double) * 8 * (size_t)std::max(s->nxb, s->nsb)) != hipSuccess)
-    return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->pz, sizeof(double) * (size_t)s->nzb) != hipSuccess) return fail(LSFFT_ENOMEM);
-  if (hipMalloc(&s->pstage, sizeof(double) * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
+  s->spx = 8LL * std::max(s->nxb, s->nsb);
+  s->spz = std::max(s->nzb, 1);
+  if (hipMalloc(&s->px, sizeof(double) * B * (size_t)s->spx) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->pz, sizeof(double) * B * (size_t)s->spz) != hipSuccess) return fail(LSFFT_ENOMEM);
+  if (hipMalloc(&s->pstage, sizeof(double) * B * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
   s->ngb = 1024;
   if (hipMalloc(&s->pg, sizeof(double) * (size_t)s->ngb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  // reference media of the systems for the operator entry points and the DGO
+  st = (s->prec == LSFFT_F32) ? upload_members<float>(s, nullptr) : upload_members<double>(s, nullptr);
+  if (st != LSFFT_OK) return fail(st);
   if (s->scheme == LSFFT_DGO) {
     st = (s->prec == LSFFT_F32) ? build_dgo<float>(s) : build_dgo<double>(s);
     if (st != LSFFT_OK) return fail(st);
   }
   if (cfg->f64_warmup > 0 && s->prec == LSFFT_F32 && s->disp && stencil_fits<double>(s->n[0])) {
-    lsfft_config c2 = *cfg;
-    c2.prec = LSFFT_F64;
-    c2.form = 2;
-    c2.f64_warmup = 0;
+    std::vector<lsfft_config> c2(cfgs, cfgs + count);
+    for (auto &c : c2) {
+      c.prec = LSFFT_F64;
+      c.form = 2;
+      c.f64_warmup = 0;
+    }
     lsfft_solver t = nullptr;
-    st = lsfft_create(&c2, &t);
+    st = lsfft_create_batch(c2.data(), count, &t);
     if (st != LSFFT_OK) return fail(st);
     (void)hipFree(t->u);
     (void)hipFree(t->st);
@@ -939,15 +1045,20 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) {
   return LSFFT_OK;
 }
 
+lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out) { return lsfft_create_batch(cfg, 1, out); }
+
 static lsfft_status check_solve_args(lsfft_solver s, const double *Eb, double tol, int32_t maxit) {
   if (!s || !Eb) return LSFFT_EINVAL;
   if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return LSFFT_EINVAL;
-  if (!finite_all(Eb, 6)) return LSFFT_EINVAL;
+  if (!finite_all(Eb, 6LL * s->B)) return LSFFT_EINVAL;
   return LSFFT_OK;
 }
 
-static lsfft_status solve_common(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, void *eps,
-                                 void *sig, double sig_mean[6], int32_t *iters, double *residual, bool host) {
+// Eb [B][6]; outputs of every system: eps, sig [B][6][N], sig_mean [B][6],
+// iters, residual, status [B] (each may be null).
+static lsfft_status solve_common(lsfft_solver s, const double *Ebar, double tol, int32_t maxit, void *eps,
+                                 void *sig, double *sig_mean, int32_t *iters, double *residual, int32_t *status,
+                                 bool host) {
   lsfft_status st = check_solve_args(s, Ebar, tol, maxit);
   if (st != LSFFT_OK) return st;
   lsfft_status rs = (s->prec == LSFFT_F32) ? run_solve<float>(s, Ebar, tol, maxit)
@@ -956,22 +1067,35 @@ static lsfft_status solve_common(lsfft_solver s, const double Ebar[6], double to
   lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, eps, sig, host)
                                            : finish_outputs<double>(s, eps, sig, host);
   if (os != LSFFT_OK) return os;
-  if (sig_mean)
-    for (int c = 0; c < 6; ++c) sig_mean[c] = s->st_host->sig_mean[c];
-  if (iters) *iters = s->st_host->iters;
-  if (residual) *residual = s->st_host->r;
+  for (int b = 0; b < s->B; ++b) {
+    const State &x = s->st_host[b];
+    if (sig_mean)
+      for (int c = 0; c < 6; ++c) sig_mean[6 * b + c] = x.sig_mean[c];
+    if (iters) iters[b] = x.iters;
+    if (residual) residual[b] = x.r;
+    if (status) status[b] = x.status;
+  }
   return rs;
 }
 
 lsfft_status lsfft_solve(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, double *eps, double *sig,
                          double sig_mean[6], int32_t *iters, double *residual) {
-  return solve_common(s, Ebar, tol, maxit, eps, sig, sig_mean, iters, residual, true);
+  if (s && s->B != 1) return LSFFT_EINVAL;
+  return solve_common(s, Ebar, tol, maxit, eps, sig, sig_mean, iters, residual, nullptr, true);
 }
 
 lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit, void *eps_dev,
                                 void *sig_dev, double sig_mean[6], int32_t *iters, double *residual) {
-  return solve_common(s, Ebar, tol, maxit, eps_dev, sig_dev, sig_mean, iters, residual, false);
+  if (s && s->B != 1) return LSFFT_EINVAL;
+  return solve_common(s, Ebar, tol, maxit, eps_dev, sig_dev, sig_mean, iters, residual, nullptr, false);
 }
+
+lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, int32_t maxit, void *eps_dev,
+                               void *sig_dev, double *sig_mean, int32_t *iters, double *residual, int32_t *status) {
+  return solve_common(s, Ebar, tol, maxit, eps_dev, sig_dev, sig_mean, iters, residual, status, false);
+}
+
+int32_t lsfft_batch_size(lsfft_solver s) { return s ? s->B : 0; }
 
 lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count) {
   if (!s || !out || cap < 0 || s->last_iters < 0) return LSFFT_EINVAL;

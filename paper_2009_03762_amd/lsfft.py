@@ -53,6 +53,10 @@ def _load():
     h = C.c_void_p
     sig = {
         "lsfft_create": (C.c_int, [C.POINTER(Config), C.POINTER(h)]),
+        "lsfft_create_batch": (C.c_int, [C.POINTER(Config), C.c_int32, C.POINTER(h)]),
+        "lsfft_solve_batch": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
+                                        C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
+        "lsfft_batch_size": (C.c_int32, [h]),
         "lsfft_solve": (C.c_int, [h, dp, C.c_double, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), dp]),
         "lsfft_solve_device": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                          C.POINTER(C.c_int32), dp]),
@@ -75,7 +79,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTS = ("lsfft_create", "lsfft_solve", "lsfft_solve_device", "lsfft_residual_history",
+EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_device", "lsfft_solve_batch",
+           "lsfft_batch_size", "lsfft_residual_history",
            "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
            "lsfft_get_timing",
            "lsfft_kernel_name", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
@@ -114,11 +119,7 @@ def _stream_handle(stream):
 FORMS = {"auto": 0, "strain": 1, "displacement": 2}
 
 
-def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
-    """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
-    lam = np.ascontiguousarray(lam, dtype=np.float64)
-    mu = np.ascontiguousarray(mu, dtype=np.float64)
+def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form, f64_warmup):
     if lam.ndim != 3 or lam.shape != mu.shape:
         raise ValueError("lam and mu must be 3D arrays of equal shape (n3, n2, n1)")
     n3, n2, n1 = lam.shape
@@ -137,11 +138,65 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
     cfg.stream = _stream_handle(stream)
     cfg.form = FORMS[form] if isinstance(form, str) else int(form)
     cfg.f64_warmup = int(f64_warmup)
+    return cfg
+
+
+def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
+    """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    cfg = _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
+                  f64_warmup)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:
         raise LsfftError(st, "lsfft_create")
     return handle
+
+
+def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0), dgo_images=4,
+                 dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
+    """lsfft_create_batch.  systems: sequence of (lam, mu, lambda0, mu0) with
+    float64 host arrays of one shape (n3, n2, n1)."""
+    arrays = []
+    cfgs = (Config * len(systems))()
+    for m, (lam, mu, l0, m0) in enumerate(systems):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        arrays.append((lam, mu))   # keep the buffers alive through the call
+        cfgs[m] = _config(lam, mu, l0, m0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
+                          f64_warmup)
+    handle = C.c_void_p()
+    st = _lib.lsfft_create_batch(cfgs, len(systems), C.byref(handle))
+    if st != OK:
+        raise LsfftError(st, "lsfft_create_batch")
+    return handle
+
+
+def batch_size(handle):
+    return int(_lib.lsfft_batch_size(handle))
+
+
+def solve_batch(handle, Ebars, tol, maxit, eps_dev=None, sig_dev=None):
+    """lsfft_solve_batch.  Ebars: (count, 6) Voigt tensor components.  eps_dev /
+    sig_dev: contiguous device tensors of the solver precision with count * 6 N
+    elements, or None.  Returns (status, sig_mean (count, 6), iters, residual,
+    per-system status)."""
+    count = batch_size(handle)
+    Eb = np.ascontiguousarray(Ebars, dtype=np.float64)
+    if Eb.shape != (count, 6):
+        raise ValueError(f"Ebars must have shape ({count}, 6)")
+    sm = np.zeros((count, 6))
+    it = (C.c_int32 * count)()
+    r = np.zeros(count)
+    sts = (C.c_int32 * count)()
+    pe = eps_dev.data_ptr() if eps_dev is not None else None
+    ps = sig_dev.data_ptr() if sig_dev is not None else None
+    st = _lib.lsfft_solve_batch(handle, _dptr(Eb), float(tol), int(maxit), pe, ps, _dptr(sm), it, _dptr(r), sts)
+    if st < 0:
+        raise LsfftError(st, "lsfft_solve_batch")
+    return st, sm, np.array(list(it)), r, np.array(list(sts))
 
 
 def destroy(handle):

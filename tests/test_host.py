@@ -93,3 +93,18 @@ def test_macro_strain_must_have_six_components(L):
         L.solve(None, np.zeros(3), 1e-6, 10)
     with pytest.raises(ValueError):
         L.solve_device(None, 1.0, 1e-6, 10)
+
+
+def test_batch_configs_must_agree(L):
+    lam, mu = _mat((8, 8, 8))
+    lam2, mu2 = _mat((8, 8, 16))
+    with pytest.raises(L.LsfftError) as e:
+        L.create_batch([(lam, mu, 1.0, 1.0), (lam2, mu2, 1.0, 1.0)])
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.LsfftError) as e:   # the DGO table needs one reference medium
+        L.create_batch([(lam, mu, 1.0, 1.0), (lam, mu, 1.1, 1.0)], scheme="dgo", disc="pcd")
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.LsfftError) as e:
+        L.create_batch([])
+    assert e.value.status == L.EINVAL
+    assert L.batch_size(None) == 0
