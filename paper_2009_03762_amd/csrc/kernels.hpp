@@ -36,7 +36,7 @@ struct State {
   int done;
   int status;
   int iters;
-  int pad;
+  int k;        // index of the next iteration to test (advanced by k_reduce)
   double r0;
   double r;
   double sig_mean[6];
@@ -548,7 +548,7 @@ struct ReduceArgs {
   double *hist;       // [system][hcap]
   long long hcap;
   const double *ebar_norms;  // [system] |Ebar|_F
-  int k, maxit;
+  int maxit;
   double tol;
   int dgo;
   int disp;           // displacement form: residual from sum_x |div sigma|^2 (x-side slot 6)
@@ -590,6 +590,9 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   block_sum<64>(vals, 8, red);
   if (threadIdx.x != 0) return;
   State &s = *a.st;
+  // the iteration index lives on the device, so that a captured sequence of
+  // iterations can be replayed unchanged
+  const int k = s.k;
   double mean[6];
   double sn = 0.0;
   for (int c = 0; c < 6; ++c) {
@@ -598,38 +601,40 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   }
   double r;
   if (a.dgo) {
-    r = (a.k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * ebar_norm);
+    r = (k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * ebar_norm);
   } else {
     const double num = a.disp ? sqrt(a.N * vals[6]) : sqrt(vals[7]);
     const double den = a.N * sqrt(sn);
     r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : __builtin_huge_val());
   }
-  a.hist[a.k] = r;
+  a.hist[k] = r;
   s.r = r;
   for (int c = 0; c < 6; ++c) s.sig_mean[c] = mean[c];
-  s.iters = a.k;
+  s.iters = k;
   const int first = a.dgo ? 1 : 0;
-  if (a.k == first) s.r0 = r;
+  if (k == first) s.r0 = r;
   int done = 0, status = 1;
   const bool finite = (r == r) && (r < __builtin_huge_val());
-  if (a.dgo && a.k == 0) {
-    if (a.k == a.maxit) { done = 1; status = 1; }
+  if (a.dgo && k == 0) {
+    if (k == a.maxit) { done = 1; status = 1; }
   } else if (r <= a.tol) {
     done = 1;
     status = 0;
-  } else if (!a.dgo && a.k == a.maxit) {
+  } else if (!a.dgo && k == a.maxit) {
     done = 1;
     status = 1;
   } else if (!finite || r > a.div_factor * fmax(s.r0, 1e-300)) {
     done = 1;
     status = 2;
-  } else if (a.dgo && a.k == a.maxit) {
+  } else if (a.dgo && k == a.maxit) {
     done = 1;
     status = 1;
   }
   if (done) {
     s.status = status;
     s.done = 1;
+  } else {
+    s.k = k + 1;
   }
 }
 
@@ -640,7 +645,7 @@ __global__ void k_state_init(State *st, int count) {
     s->done = 0;
     s->status = 1;
     s->iters = 0;
-    s->pad = 0;
+    s->k = 0;
     s->r0 = 0.0;
     s->r = 0.0;
     for (int c = 0; c < 6; ++c) s->sig_mean[c] = 0.0;

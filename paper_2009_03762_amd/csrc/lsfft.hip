@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
@@ -187,6 +188,15 @@ struct lsfft_solver_s {
   lsfft_solver_s *twin = nullptr;
   int warm = 0;
   int borrowed = 0;  // u, st, st_host and hist belong to another solver
+  // Replay of captured iteration chunks: an internal stream (default
+  // priority) that waits on `stream`, and the executable graph of GRAPH_CHUNK
+  // iterations for the (tol, maxit) it was captured with.
+  int use_graphs = 1;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gevent = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_tol = -1.0;
+  int g_maxit = -1;
 };
 
 namespace {
@@ -549,6 +559,45 @@ bool all_done(const lsfft_solver s) {
   return true;
 }
 
+constexpr int GRAPH_CHUNK = 8;
+
+// Capture GRAPH_CHUNK iterations (enqueued by `iteration`) on the internal
+// stream and keep the executable graph; captured again when tol or maxit
+// change.  The captured launches are kernels only.
+template <typename F> lsfft_status ensure_graph(lsfft_solver s, double tol, int maxit, F &&iteration) {
+  if (!s->gstream) {
+    LSFFT_CHECK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+    LSFFT_CHECK(hipEventCreateWithFlags(&s->gevent, hipEventDisableTiming));
+  }
+  if (s->gexec && s->g_tol == tol && s->g_maxit == maxit) return LSFFT_OK;
+  if (s->gexec) {
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  hipStream_t user = s->stream;
+  s->stream = s->gstream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal);
+  for (int j = 0; j < GRAPH_CHUNK && e == hipSuccess; ++j) e = iteration(false);
+  hipError_t e2 = hipStreamEndCapture(s->gstream, &g);
+  s->stream = user;
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    fprintf(stderr, "lsfft: graph capture failed: %s\n", hipGetErrorString(e != hipSuccess ? e : e2));
+    return LSFFT_EDEVICE;
+  }
+  e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    s->gexec = nullptr;
+    fprintf(stderr, "lsfft: graph instantiation failed: %s\n", hipGetErrorString(e));
+    return LSFFT_EDEVICE;
+  }
+  s->g_tol = tol;
+  s->g_maxit = maxit;
+  return LSFFT_OK;
+}
+
 // Iterations k_begin .. k_end-1 of a solve (maxit, tol as in lsfft_solve) of
 // every system of the batch, whose constants upload_members has set.
 // fresh: start from u = 0 / eps = Ebar with a new device state; otherwise the
@@ -604,49 +653,77 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   ra.disp = disp ? 1 : 0;
   ra.N = (double)s->d.N;
   ra.div_factor = 1e6;
+  // One iteration of every system: forward y, z-pass with the Green step,
+  // reduction and stopping test, inverse y, then the x side (displacement
+  // update and stencil, or x-pass).  `last` omits the trailing stencil (the
+  // next phase evaluates it in its own precision).
+  auto iteration = [&](bool last) -> hipError_t {
+    hipError_t e;
+    {
+      Timed tm(s, 1);
+      if ((e = L::template ypass<true>(s, ya, nyg)) != hipSuccess) return e;
+    }
+    {
+      Timed tm(s, 2);
+      if ((e = disp ? L::zpass_u(s, za, s->nzub) : L::zpass(s, za, s->nzb)) != hipSuccess) return e;
+    }
+    {
+      Timed tm(s, 5);
+      hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE, s->B), dim3(256), 0, s->stream, ra);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(lsfft::k_reduce, dim3(1, s->B), dim3(64), 0, s->stream, ra);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+      Timed tm(s, 3);
+      if ((e = L::template ypass<false>(s, ya, nyg)) != hipSuccess) return e;
+    }
+    if (disp) {
+      {
+        Timed tm(s, 4);
+        if ((e = L::uxpass(s, ua, s->nub)) != hipSuccess) return e;
+      }
+      if (!last) {
+        Timed tm(s, 0);
+        if ((e = L::stencil(s, sa, s->nsb)) != hipSuccess) return e;
+      }
+    } else {
+      Timed tm(s, 0);
+      if ((e = L::xpass(s, xa, s->nxb)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  auto read_state = [&](hipStream_t st) -> lsfft_status {
+    LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State) * s->B, hipMemcpyDeviceToHost, st));
+    LSFFT_CHECK(hipStreamSynchronize(st));
+    return LSFFT_OK;
+  };
   int k = k_begin;
+  // The final phase of a solve replays captured chunks of iterations (its
+  // iterations run to the stopping test, so a chunk may overrun: kernels of
+  // a finished system return at once).  Kernel timing needs the eager path.
+  const bool graphs = s->use_graphs && k_end == maxit + 1 && s->timing_kernel < 0 && k_end - k >= GRAPH_CHUNK;
+  if (graphs) {
+    lsfft_status gs = ensure_graph(s, tol, maxit, iteration);
+    if (gs != LSFFT_OK) return gs;
+    LSFFT_CHECK(hipEventRecord(s->gevent, s->stream));
+    LSFFT_CHECK(hipStreamWaitEvent(s->gstream, s->gevent, 0));
+    int per_sync = (tol == 0.0) ? (k_end - k + GRAPH_CHUNK - 1) / GRAPH_CHUNK : 1;
+    for (;;) {
+      for (int j = 0; j < per_sync && k < k_end; ++j, k += GRAPH_CHUNK) LSFFT_CHECK(hipGraphLaunch(s->gexec, s->gstream));
+      lsfft_status rs = read_state(s->gstream);
+      if (rs != LSFFT_OK) return rs;
+      if (all_done(s) || k >= k_end) break;
+      per_sync = std::min(per_sync * 2, 8);
+    }
+    return LSFFT_OK;
+  }
   int chunk = (tol == 0.0) ? k_end - k_begin : 2;
   for (;;) {
     const int nenq = std::min(chunk, k_end - k);
-    for (int j = 0; j < nenq; ++j, ++k) {
-      {
-        Timed tm(s, 1);
-        LSFFT_CHECK(L::template ypass<true>(s, ya, nyg));
-      }
-      {
-        Timed tm(s, 2);
-        LSFFT_CHECK(disp ? L::zpass_u(s, za, s->nzub) : L::zpass(s, za, s->nzb));
-      }
-      ra.k = k;
-      {
-        Timed tm(s, 5);
-        hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE, s->B), dim3(256), 0, s->stream, ra);
-        LSFFT_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(lsfft::k_reduce, dim3(1, s->B), dim3(64), 0, s->stream, ra);
-        LSFFT_CHECK(hipGetLastError());
-      }
-      {
-        Timed tm(s, 3);
-        LSFFT_CHECK(L::template ypass<false>(s, ya, nyg));
-      }
-      if (disp) {
-        {
-          Timed tm(s, 4);
-          LSFFT_CHECK(L::uxpass(s, ua, s->nub));
-        }
-        // the last iteration of a phase leaves the stencil to the next one
-        // (at k = maxit every system is done and the stencil would return at once)
-        if (k + 1 < k_end) {
-          Timed tm(s, 0);
-          LSFFT_CHECK(L::stencil(s, sa, s->nsb));
-        }
-      } else {
-        Timed tm(s, 0);
-        LSFFT_CHECK(L::xpass(s, xa, s->nxb));
-      }
-    }
-    LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State) * s->B, hipMemcpyDeviceToHost, s->stream));
-    LSFFT_CHECK(hipStreamSynchronize(s->stream));
+    for (int j = 0; j < nenq; ++j, ++k) LSFFT_CHECK(iteration(k + 1 == k_end));
+    lsfft_status rs = read_state(s->stream);
+    if (rs != LSFFT_OK) return rs;
     if (all_done(s) || k >= k_end) break;
     chunk = std::min(chunk * 2, 64);
   }
@@ -810,6 +887,12 @@ template <typename T> lsfft_status build_dgo(lsfft_solver s) {
 }
 
 void release(lsfft_solver s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->gevent) (void)hipEventDestroy(s->gevent);
+  if (s->gstream) (void)hipStreamDestroy(s->gstream);
+  s->gexec = nullptr;
+  s->gevent = nullptr;
+  s->gstream = nullptr;
   if (s->twin) {
     release(s->twin);
     delete s->twin;
@@ -930,6 +1013,10 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   }
   s->B = count;
   s->launch_b = count;
+  {
+    const char *ng = std::getenv("LSFFT_NO_GRAPHS");
+    s->use_graphs = (ng && ng[0] && ng[0] != '0') ? 0 : 1;
+  }
   s->lam0 = cfg->lambda0;
   s->mu0 = cfg->mu0;
   for (int m = 0; m < count; ++m) {

@@ -137,3 +137,33 @@ def test_single_entry_points_reject_batch_handles(L):
         L.solve(h, np.zeros(6), 1e-6, 5)
     assert e.value.status == L.EINVAL
     L.destroy(h)
+
+
+@pytest.mark.parametrize("prec,form", [("f64", "displacement"), ("f32", "strain")])
+def test_graph_replay_matches_eager(L, prec, form, monkeypatch):
+    """Solves replaying captured iteration chunks give the same bits as eager
+    launches, on repeated solves of one handle with other work in between."""
+    shape = (16, 16, 16)
+    systems = _cells(shape, (10.0, 30.0))
+    Ebs = np.array([[1e-3, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 1e-3]])
+    res = {}
+    for mode in ("graphs", "eager"):
+        if mode == "eager":
+            monkeypatch.setenv("LSFFT_NO_GRAPHS", "1")
+        else:
+            monkeypatch.delenv("LSFFT_NO_GRAPHS", raising=False)
+        h = L.create_batch(systems, scheme="afb", prec=prec, form=form)
+        outs = []
+        for rep in range(3):
+            eps = torch.zeros((2, 6) + shape, dtype=_dt(prec), device="cuda")
+            tol = 1e-9 if rep != 1 else 0.0
+            st, sm, it, r, sts = L.solve_batch(h, Ebs * (1 + rep), tol, 60 + 5 * rep, eps)
+            torch.cuda.synchronize()
+            junk = torch.randn(1 << 20, device="cuda").sum().item()  # eager work between replays
+            outs.append((it.copy(), sm.copy(), eps.cpu().numpy()))
+        L.destroy(h)
+        res[mode] = outs
+    for (ia, sa_, ea), (ib, sb, eb) in zip(res["graphs"], res["eager"]):
+        assert np.array_equal(ia, ib)
+        assert np.array_equal(sa_, sb)
+        assert np.array_equal(ea, eb)
