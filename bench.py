@@ -19,7 +19,10 @@ solver's stream inside the timed region.  "equal_accuracy" gives, for the
 FP64 path and the FP32 paths (displacement form, the same with five FP64
 warm-start iterations, strain form), the iterations and wall time needed to bring
 the strain field within a relative L2 error of 1e-5 and 1e-6 of a tight FP64
-solution, and the FP32 speedups at equal accuracy.
+solution, and the FP32 speedups at equal accuracy.  "batched_ceff" times the
+effective stiffness (six load cases) of random cells of five sizes (12 by
+default, `--batched-cells 48` for the full set) as plain FP64 solves, as
+batched FP64 solves, and as batched FP32 solves.
 """
 from __future__ import annotations
 
@@ -241,6 +244,88 @@ def equal_accuracy(n, targets=(1e-5, 1e-6), kmax=500, kstep=10):
     return out
 
 
+def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
+    """Effective stiffness (six unit load cases) of `ncells` random cells:
+    sizes drawn from {32, 48, 64, 96, 128}^3, Poisson(20) spheres of radius
+    U[3, 8] voxels, log10 E uniform in [0, 3] per sphere, matrix E = 1,
+    nu = 0.3, C0 = mean of the Lame moduli of the extreme E, AFB.  Three
+    paths, solve time only (handles created beforehand):
+      plain   FP64, one solve per load case and cell (tol);
+      batched FP64, one batch handle per cell size holding every cell and load
+              case, replayed iteration graphs (tol);
+      batched FP32 with five FP64 warm-start iterations, run for the largest
+              FP64 iteration count of its size group (the FP32 residual
+              cannot certify tol at these contrasts);
+    with the error of each path's C_eff against the plain FP64 one."""
+    import torch
+
+    from paper_2009_03762_amd import inputs, lsfft
+    rng = np.random.default_rng(seed0)
+    sizes = [32, 48, 64, 96, 128]
+    cells = []
+    for b in range(ncells):
+        n = int(rng.choice(sizes))
+        E = inputs.poisson_spheres(n, seed0 + b)
+        lam, mu = inputs.lame_from_young(E, 0.3)
+        lo, hi = inputs.lame_from_young(E.min(), 0.3), inputs.lame_from_young(E.max(), 0.3)
+        cells.append((n, lam, mu, 0.5 * float(lo[0] + hi[0]), 0.5 * float(lo[1] + hi[1])))
+    units = inputs.mandel_unit_strains()
+    mandel = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+    maxit = 20000
+
+    def sync_time(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    # plain FP64
+    ref, iters64, t_plain, vox_it = [], [], 0.0, 0
+    for (n, lam, mu, l0, m0) in cells:
+        s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", prec="f64")
+        M = np.zeros((6, 6))
+        its = []
+        for J in range(6):
+            r, dt = sync_time(lambda: s.solve_device(units[J], tol=tol, maxit=maxit))
+            t_plain += dt
+            M[:, J] = mandel * r["sig_mean"]
+            its.append(r["iters"])
+            vox_it += n ** 3 * r["iters"]
+        s.close()
+        ref.append(M)
+        iters64.append(its)
+    print(f"[bench] batched: plain FP64 done ({t_plain:.2f} s)", file=sys.stderr, flush=True)
+    groups = {}
+    for i, c in enumerate(cells):
+        groups.setdefault(c[0], []).append(i)
+    out = {"cells": ncells, "sizes": {str(n): len(ix) for n, ix in sorted(groups.items())},
+           "plain_f64": {"seconds": t_plain, "GVoxel_iter_per_s": vox_it / t_plain / 1e9,
+                         "iters_mean": float(np.mean(iters64)), "iters_max": int(np.max(iters64))}}
+    for name, prec, warm in (("batched_f64", "f64", 0), ("batched_f32_warm5", "f32", 5)):
+        t_tot, err, vit = 0.0, 0.0, 0
+        for n, ix in sorted(groups.items()):
+            systems = [(cells[i][1], cells[i][2], cells[i][3], cells[i][4]) for i in ix for J in range(6)]
+            h = lsfft.create_batch(systems, scheme="afb", prec=prec, f64_warmup=warm)
+            Ebs = np.tile(units, (len(ix), 1))
+            if prec == "f64":
+                (st, sm, it, r, sts), dt = sync_time(lambda: lsfft.solve_batch(h, Ebs, tol, maxit))
+            else:
+                K = int(max(max(iters64[i]) for i in ix))
+                (st, sm, it, r, sts), dt = sync_time(lambda: lsfft.solve_batch(h, Ebs, 0.0, K))
+            lsfft.destroy(h)
+            t_tot += dt
+            vit += n ** 3 * int(np.sum(it))
+            for q, i in enumerate(ix):
+                M = np.stack([mandel * sm[6 * q + J] for J in range(6)], axis=1)
+                err = max(err, float(np.linalg.norm(M - ref[i]) / np.linalg.norm(ref[i])))
+        out[name] = {"seconds": t_tot, "GVoxel_iter_per_s": vit / t_tot / 1e9, "speedup_over_plain_f64": t_plain / t_tot,
+                     "max_rel_err_ceff_vs_plain_f64": err}
+        print(f"[bench] batched: {name} done ({t_tot:.2f} s)", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return out
+
+
 def config_report():
     """Iterations to tolerance, status and wall time for the configurations of
     the paper's benchmark family: 16^3 BASIC FP64 (tol 1e-8); 64^3 at contrasts
@@ -388,6 +473,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-cells", type=int, default=12,
+                    help="cells of the batched effective-stiffness measurement (48 for the full set)")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
@@ -439,6 +527,8 @@ def main():
         line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
     if not args.no_accuracy:
         line["equal_accuracy"] = equal_accuracy(args.size)
+    if not args.no_batched and args.batched_cells > 0:
+        line["batched_ceff"] = batched_ceff(args.batched_cells)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

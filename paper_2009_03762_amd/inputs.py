@@ -177,3 +177,31 @@ def lognormal_young(n, corr_len=8.0, seed=7, log10_mean=1.0, log10_std=0.5, clip
     from `gaussian_random_field`."""
     g = gaussian_random_field(n, corr_len, seed)
     return np.clip(10.0 ** (log10_mean + log10_std * g), clip[0], clip[1])
+
+
+def poisson_spheres(n, seed, mean_count=20, radius=(3.0, 8.0), log10_E=(0.0, 3.0), E_matrix=1.0):
+    """Young's modulus field of a periodic cell with Poisson(mean_count)
+    spheres: centres uniform in the cell, radii uniform in `radius` voxels,
+    per-sphere log10 E uniform in `log10_E`, matrix E_matrix; a voxel belongs
+    to a sphere when the periodic (minimum-image) distance of its centre to
+    the sphere centre is at most the radius; overlaps keep the largest E.
+    Shape (n3, n2, n1)."""
+    n1, n2, n3 = _shape(n)
+    rng = np.random.default_rng(seed)
+    count = rng.poisson(mean_count)
+    E = np.full((n3, n2, n1), float(E_matrix))
+    x1 = np.arange(n1) + 0.5
+    x2 = np.arange(n2) + 0.5
+    x3 = np.arange(n3) + 0.5
+    for _ in range(count):
+        c = rng.uniform(0.0, 1.0, 3) * np.array([n1, n2, n3])
+        r = rng.uniform(*radius)
+        Ei = 10.0 ** rng.uniform(*log10_E)
+
+        def d(x, c0, n0):
+            t = np.abs(x - c0)
+            return np.minimum(t, n0 - t)
+        dist2 = (d(x3, c[2], n3)[:, None, None] ** 2 + d(x2, c[1], n2)[None, :, None] ** 2 +
+                 d(x1, c[0], n1)[None, None, :] ** 2)
+        E = np.where(dist2 <= r * r, np.maximum(E, Ei), E)
+    return E
