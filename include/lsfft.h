@@ -58,7 +58,15 @@ typedef struct lsfft_solver_s *lsfft_solver;
  * flag is recorded and gates DGO, which is defined for PCD only. */
 typedef enum { LSFFT_TD = 0, LSFFT_PCD = 1 } lsfft_disc;
 
-typedef enum { LSFFT_BASIC = 0, LSFFT_FB = 1, LSFFT_AFB = 2, LSFFT_DGO = 3 } lsfft_scheme;
+/* BASIC, FB, AFB, DGO: see above.  CD: central-difference gradient
+ * q^CD_r = i sin(2 pi kappa_r/n_r)/h_r (eq. (14)) with the conjugate divergence;
+ * ACD: the averaged central difference of Sec. 5.3 (eq. (43)),
+ * q_r = q^CD_r cos(2 pi kappa_s/n_s) cos(2 pi kappa_t/n_t), conjugate pair.
+ * CD and ACD use the strain form (form 2 is EINVAL).  Where a wavevector
+ * vanishes exactly (CD: every index 0 or Nyquist; ACD also wherever two of the
+ * cosines vanish, e.g. two indices at n/4) the Green function is 0 (Sec. 3.1
+ * after the TD algorithm). */
+typedef enum { LSFFT_BASIC = 0, LSFFT_FB = 1, LSFFT_AFB = 2, LSFFT_DGO = 3, LSFFT_CD = 4, LSFFT_ACD = 5 } lsfft_scheme;
 
 /* F64: all arithmetic in FP64.  F32: strain, stress, FFTs and the Green step
  * in FP32; the displacement of the displacement form, the residual, mean

@@ -11,6 +11,10 @@
 //       AFB:   k_r = (2/h_r) sin(pi kappa_r/n_r) cos(pi kappa_s/n_s) cos(pi kappa_t/n_t),
 //              the real vector with q^AhC = i k and q^AFD = Phi i k (Sec. 5.3 eq. (43)),
 //              so the phase Phi cancels from the strain update of eq. (34);
+//       CD:    k_r = sin(2 pi kappa_r/n_r)/h_r, q^CD = i k of eq. (14) with the
+//              conjugate divergence;
+//       ACD:   k_r = sin(2 pi kappa_r/n_r)/h_r cos(2 pi kappa_s/n_s) cos(2 pi kappa_t/n_t),
+//              the averaged central difference of Sec. 5.3 eq. (43), conjugate pair;
 //   FB: q^a = a_r = (e^{i 2 pi kappa_r/n_r} - 1)/h_r, q^b = conj(a) (eq. (45)):
 //       increment = -sym( K^{-1} (sigma_hat conj(a)) (x) a ),
 //       K = mu0 |a|^2 I + mu0 a (x) conj(a) + lam0 conj(a) (x) a  (= -G^{-1}, eq. (34));
@@ -25,10 +29,14 @@
 
 namespace lsfft {
 
-enum { SCHEME_BASIC = 0, SCHEME_FB = 1, SCHEME_AFB = 2, SCHEME_DGO = 3 };
+enum { SCHEME_BASIC = 0, SCHEME_FB = 1, SCHEME_AFB = 2, SCHEME_DGO = 3, SCHEME_CD = 4, SCHEME_ACD = 5 };
 
-// Table kinds, laid out tab[kind * (n1 + n2 + n3) + off[axis] + i].
-enum { TAB_K = 0, TAB_SH = 1, TAB_C = 2, TAB_AR = 3, TAB_AI = 4, TAB_KINDS = 5 };
+// Table kinds, laid out tab[kind * (n1 + n2 + n3) + off[axis] + i]:
+// TAB_K 2 pi kappa/(n h); TAB_SH (2/h) sin(pi kappa/n); TAB_C cos(pi kappa/n);
+// TAB_AR, TAB_AI real and imaginary parts of (e^{2 pi i kappa/n} - 1)/h (the
+// imaginary part is also the central-difference wavenumber sin(2 pi kappa/n)/h);
+// TAB_C2 cos(2 pi kappa/n).  Zeros are exact.
+enum { TAB_K = 0, TAB_SH = 1, TAB_C = 2, TAB_AR = 3, TAB_AI = 4, TAB_C2 = 5, TAB_KINDS = 6 };
 
 template <typename T> struct GreenParams {
   int scheme;
@@ -195,8 +203,12 @@ template <typename T> struct AxisVal {
   T p, q;
 };
 template <typename T> __device__ __forceinline__ AxisVal<T> axis_val(const GreenParams<T> &g, int axis, int i) {
-  const int kp = g.scheme == SCHEME_AFB ? TAB_SH : (g.scheme == SCHEME_FB ? TAB_AR : TAB_K);
-  const int kq = g.scheme == SCHEME_AFB ? TAB_C : (g.scheme == SCHEME_FB ? TAB_AI : TAB_K);
+  const int kp = g.scheme == SCHEME_AFB ? TAB_SH
+               : g.scheme == SCHEME_FB  ? TAB_AR
+               : (g.scheme == SCHEME_CD || g.scheme == SCHEME_ACD) ? TAB_AI : TAB_K;
+  const int kq = g.scheme == SCHEME_AFB ? TAB_C
+               : (g.scheme == SCHEME_FB || g.scheme == SCHEME_CD) ? TAB_AI
+               : g.scheme == SCHEME_ACD ? TAB_C2 : TAB_K;
   return AxisVal<T>{tabv(g, kp, axis, i), tabv(g, kq, axis, i)};
 }
 
@@ -229,10 +241,14 @@ __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, i
     return green_fb(g, a, s);
   }
   T k[3];
-  if (g.scheme == SCHEME_AFB) {
+  if (g.scheme == SCHEME_AFB || g.scheme == SCHEME_ACD) {
+    // a per-axis difference times the averaging factors of the other axes
     k[0] = ax[0].p * ax[1].q * ax[2].q;
     k[1] = ax[1].p * ax[2].q * ax[0].q;
     k[2] = ax[2].p * ax[0].q * ax[1].q;
+  } else if (g.scheme == SCHEME_CD) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) k[r] = ax[r].p;
   } else {
     bool nyq[3];
     bool live = false;

@@ -139,6 +139,7 @@ template <typename T> std::vector<T> axis_tables(const int n[3], const double h[
       tab[lsfft::TAB_C * S + off[r] + i] = (T)ch;
       tab[lsfft::TAB_AR * S + off[r] + i] = (T)((c2 - 1.0L) / hr);
       tab[lsfft::TAB_AI * S + off[r] + i] = (T)(s2 / hr);
+      tab[lsfft::TAB_C2 * S + off[r] + i] = (T)c2;
     }
   }
   return tab;
@@ -979,7 +980,8 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     if (!(cfg->h[r] >= 0.0) || !std::isfinite(cfg->h[r])) return LSFFT_EINVAL;
   }
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
-  if (cfg->scheme < LSFFT_BASIC || cfg->scheme > LSFFT_DGO) return LSFFT_EINVAL;
+  if (cfg->scheme < LSFFT_BASIC || cfg->scheme > LSFFT_ACD) return LSFFT_EINVAL;
+  if ((cfg->scheme == LSFFT_CD || cfg->scheme == LSFFT_ACD) && cfg->form == 2) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
   if (cfg->form < 0 || cfg->form > 2) return LSFFT_EINVAL;
   if (cfg->f64_warmup < 0) return LSFFT_EINVAL;

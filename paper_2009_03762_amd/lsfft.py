@@ -17,9 +17,9 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsfft.s
 
 OK, ENOTCONV, EDIVERGED, EINVAL, ENOMEM, EDEVICE = 0, 1, 2, -1, -2, -3
 TD, PCD = 0, 1
-BASIC, FB, AFB, DGO = 0, 1, 2, 3
+BASIC, FB, AFB, DGO, CD, ACD = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
-SCHEMES = {"basic": BASIC, "fb": FB, "afb": AFB, "dgo": DGO}
+SCHEMES = {"basic": BASIC, "fb": FB, "afb": AFB, "dgo": DGO, "cd": CD, "acd": ACD}
 PRECS = {"f64": F64, "f32": F32}
 DISCS = {"td": TD, "pcd": PCD}
 KERNELS = {"xpass": 0, "ypass_fwd": 1, "zpass": 2, "ypass_inv": 3, "uxpass": 4, "reduce": 5}

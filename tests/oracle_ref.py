@@ -8,7 +8,7 @@ import numpy as np
 
 from oracle import fdd, fourier, green, solve3d
 
-SCHEME_NAMES = {"basic": "basic", "fb": "FB", "afb": "AFB"}
+SCHEME_NAMES = {"basic": "basic", "fb": "FB", "afb": "AFB", "cd": "CD", "acd": "ACD"}
 
 
 def hooke_voigt(lam, mu, eps):

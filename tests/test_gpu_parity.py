@@ -57,7 +57,7 @@ def test_stress_spectrum(L, shape, prec):
     assert rel(got, ref) < tol
 
 
-@pytest.mark.parametrize("scheme", ["basic", "fb", "afb"])
+@pytest.mark.parametrize("scheme", ["basic", "fb", "afb", "cd", "acd"])
 @pytest.mark.parametrize("shape", [(16, 16, 16), (24, 8, 12)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_green_apply(L, scheme, shape, prec):
@@ -112,15 +112,19 @@ SOLVE_CASES = [
     ("afb", (32, 24, 8)),
     ("fb", (12, 16, 48)),
     ("basic", (24, 8, 12)),
+    ("cd", (16, 12, 8)),
+    ("acd", (16, 16, 16)),
+    ("acd", (24, 8, 12)),
 ]
+NAMES = {"basic": "basic", "fb": "FB", "afb": "AFB", "cd": "CD", "acd": "ACD"}
 
 
 @pytest.mark.parametrize("scheme,shape", SOLVE_CASES)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("form", ["strain", "auto"])
 def test_fixed_iterations_match_oracle(L, scheme, shape, prec, form):
-    if form == "auto" and scheme == "basic":
-        pytest.skip("the basic scheme has a single (strain) form")
+    if form == "auto" and scheme in ("basic", "cd", "acd"):
+        pytest.skip("this scheme has a single (strain) form")
     print(f"\n[fixed_iter] scheme={scheme} shape={shape} prec={prec} form={form}", flush=True)
     K = 12
     n1, n2, n3 = shape
@@ -130,8 +134,7 @@ def test_fixed_iterations_match_oracle(L, scheme, shape, prec, form):
     Eb = np.array([1e-3, 2e-4, -1e-4, 3e-4, -2e-4, 5e-4])
     s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec, form=form)
     out = s.solve(Eb, tol=0.0, maxit=K)
-    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
-                            tol=0.0, maxit=K)
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K)
     assert out["iters"] == K and out["status"] == L.ENOTCONV
     tol = 1e-12 if prec == "f64" else 1e-5
     assert rel(out["eps"], ref.eps) < tol
@@ -144,7 +147,8 @@ def test_fixed_iterations_match_oracle(L, scheme, shape, prec, form):
 
 
 @pytest.mark.parametrize("scheme,form", [("basic", "auto"), ("fb", "strain"), ("fb", "displacement"),
-                                         ("afb", "strain"), ("afb", "displacement")])
+                                         ("afb", "strain"), ("afb", "displacement"), ("cd", "auto"),
+                                         ("acd", "auto")])
 def test_converged_matches_oracle_fp64(L, scheme, form):
     shape = (16, 16, 16)
     print(f"\n[converged] scheme={scheme} form={form}", flush=True)
@@ -153,8 +157,7 @@ def test_converged_matches_oracle_fp64(L, scheme, form):
     Eb = inputs.macro_strain("11", 1e-3)
     s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f64", form=form)
     out = s.solve(Eb, tol=1e-8, maxit=2000)
-    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme={"basic": "basic", "fb": "FB", "afb": "AFB"}[scheme],
-                            tol=1e-8, maxit=2000)
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme=NAMES[scheme], tol=1e-8, maxit=2000)
     assert out["status"] == L.OK and ref.status == solve3d.OK
     assert out["iters"] == ref.iters
     assert rel(out["eps"], ref.eps) < 1e-11
@@ -186,7 +189,7 @@ def test_homogeneous_is_exact(L):
     lam = np.full((8, 16, 16), 2.0)
     mu = np.full((8, 16, 16), 1.5)
     Eb = np.array([1e-3, 2e-4, -3e-4, 1e-4, 5e-5, 2e-4])
-    for scheme in ("basic", "fb", "afb"):
+    for scheme in ("basic", "fb", "afb", "cd", "acd"):
         s = L.Solver(lam, mu, 1.0, 1.0, scheme=scheme, prec="f64")
         out = s.solve(Eb, tol=1e-12, maxit=10)
         assert out["status"] == L.OK and out["iters"] == 0
