@@ -120,7 +120,7 @@ def measured_traffic(kernel, prec, n):
     return ent["read_bytes"] + ent["write_bytes"]
 
 
-def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
+def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement", autotune=True):
     import torch
 
     from paper_2009_03762_amd import lsfft
@@ -129,6 +129,15 @@ def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
     torch.cuda.synchronize()
     s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec, form=form)
     print(f"[bench] {prec}: solver created for {n}^3 ({form} form)", file=sys.stderr, flush=True)
+    tuned = None
+    if autotune:
+        t0 = time.perf_counter()
+        sched, ms0, ms1 = lsfft.autotune(s.handle, 16)
+        tuned = {"schedule": sched, "default_ms_per_iter": ms0, "tuned_ms_per_iter": ms1,
+                 "tune_seconds": time.perf_counter() - t0}
+        print(f"[bench] {prec}: schedule {sched}: {ms0:.4f} -> {ms1:.4f} ms/iter", file=sys.stderr, flush=True)
+    else:
+        tuned = {"schedule": lsfft.get_schedule(s.handle)}
     s.solve_device(Eb, tol=0.0, maxit=warmup)
     torch.cuda.synchronize()
     names = KERNEL_NAMES[form]
@@ -180,6 +189,7 @@ def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement"):
         "bytes_per_voxel_iteration": bytes_per_iteration(n, esize, form) / N,
         "form": form,
         "kernels": kernels,
+        "autotune": tuned,
     }
     s.close()
     torch.cuda.synchronize()
@@ -302,11 +312,16 @@ def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
     out = {"cells": ncells, "sizes": {str(n): len(ix) for n, ix in sorted(groups.items())},
            "plain_f64": {"seconds": t_plain, "GVoxel_iter_per_s": vox_it / t_plain / 1e9,
                          "iters_mean": float(np.mean(iters64)), "iters_max": int(np.max(iters64))}}
-    for name, prec, warm in (("batched_f64", "f64", 0), ("batched_f32_warm5", "f32", 5)):
-        t_tot, err, vit = 0.0, 0.0, 0
+    for name, prec, warm, tune in (("batched_f64", "f64", 0, False), ("batched_f32_warm5", "f32", 5, False),
+                                   ("batched_f32_warm5_tuned", "f32", 5, True)):
+        t_tot, err, vit, t_tune, scheds = 0.0, 0.0, 0, 0.0, {}
         for n, ix in sorted(groups.items()):
             systems = [(cells[i][1], cells[i][2], cells[i][3], cells[i][4]) for i in ix for J in range(6)]
             h = lsfft.create_batch(systems, scheme="afb", prec=prec, f64_warmup=warm)
+            if tune:
+                (sch, ms0, ms1), dt = sync_time(lambda: lsfft.autotune(h, 16))
+                t_tune += dt
+                scheds[str(n)] = {"schedule": sch, "default_ms_per_iter": ms0, "tuned_ms_per_iter": ms1}
             Ebs = np.tile(units, (len(ix), 1))
             if prec == "f64":
                 (st, sm, it, r, sts), dt = sync_time(lambda: lsfft.solve_batch(h, Ebs, tol, maxit))
@@ -321,6 +336,9 @@ def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
                 err = max(err, float(np.linalg.norm(M - ref[i]) / np.linalg.norm(ref[i])))
         out[name] = {"seconds": t_tot, "GVoxel_iter_per_s": vit / t_tot / 1e9, "speedup_over_plain_f64": t_plain / t_tot,
                      "max_rel_err_ceff_vs_plain_f64": err}
+        if tune:
+            out[name]["tune_seconds"] = t_tune
+            out[name]["schedules"] = scheds
         print(f"[bench] batched: {name} done ({t_tot:.2f} s)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     return out
@@ -480,6 +498,8 @@ def main():
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch schedule instead of the tuned one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the solver is a "
@@ -492,9 +512,10 @@ def main():
     if args.configs:
         print(json.dumps(config_report()), flush=True)
         return
-    res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form) \
+    tune = not args.no_autotune
+    res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form, tune) \
         if args.prec in ("f32", "both") else None
-    res64 = run_gpu("f64", args.size, args.steps, args.warmup, not args.no_breakdown, args.form) \
+    res64 = run_gpu("f64", args.size, args.steps, args.warmup, not args.no_breakdown, args.form, tune) \
         if args.prec in ("f64", "both") else None
     head = res32 if res32 is not None else res64
     line = {
@@ -519,11 +540,12 @@ def main():
         "whole_iteration_frac_fixed_balg": head["whole_iteration_frac_fixed_balg"],
         "bytes_per_voxel_iteration": head["bytes_per_voxel_iteration"],
         "kernels": head["kernels"],
+        "autotune": head["autotune"],
     }
     if res32 is not None and res64 is not None:
         line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
                                                "whole_iteration_frac_fixed_balg",
-                                               "bytes_per_voxel_iteration", "kernels")}
+                                               "bytes_per_voxel_iteration", "kernels", "autotune")}
         line["fp32_speedup_over_fp64"] = res32["value"] / res64["value"]
     if not args.no_accuracy:
         line["equal_accuracy"] = equal_accuracy(args.size)

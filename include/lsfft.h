@@ -176,6 +176,48 @@ lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, i
 /* Number of systems of a handle (0 for NULL). */
 int32_t lsfft_batch_size(lsfft_solver s);
 
+/* Launch schedule of the passes of one iteration.  It decides how the work
+ * is cut into workgroups and in which order they run, not the formulas:
+ * results under two schedules agree to rounding (the reductions of mean
+ * stress and residual add their per-workgroup partial sums in another
+ * order).  Each handle has its own schedule; the FP64 warm-start iterations
+ * (f64_warmup) keep their default one. */
+typedef struct {
+  int32_t stencil_planes; /* z-planes per stencil workgroup in the displacement
+                             form: an even divisor of n3 (2 .. 32 are offered
+                             by lsfft_autotune); 0 in the strain form       */
+  int32_t y_cols;         /* pencils (consecutive x columns) per y-pass
+                             workgroup: the default or its alternative, one
+                             of two values fixed by n2 and the precision    */
+  int32_t z_cols;         /* the same for the z pass (the pass holding the
+                             Green step)                                    */
+  int32_t xcd_order;      /* bit 0 stencil, bit 1 y pass, bit 2 z pass: deal
+                             consecutive tiles to the same XCD (shared L2)
+                             instead of round-robin over the 8 XCDs         */
+} lsfft_schedule;
+
+/* The handle's current schedule.  EINVAL on NULL arguments. */
+lsfft_status lsfft_get_schedule(lsfft_solver s, lsfft_schedule *out);
+
+/* Replace the handle's schedule (e.g. one found by lsfft_autotune on an
+ * earlier run of the same grid and precision).  EINVAL, with the schedule
+ * unchanged, when a field is not one this grid offers. */
+lsfft_status lsfft_set_schedule(lsfft_solver s, const lsfft_schedule *sch);
+
+/* Schedule tuner.  Times whole iterations of every system of the handle
+ * (its own moduli, a unit axial macroscopic strain, the stopping test off,
+ * `iterations` rounded up to whole captured chunks of 8, best of 3 runs
+ * after one untimed run) and searches the knobs one at a time: stencil
+ * planes, y and z column tiles, then each XCD-order bit, keeping a change
+ * that is faster by more than 1 %.  Leaves the best schedule in force and
+ * returns it in *best, with the milliseconds per iteration of the schedule
+ * in force on entry (*start_ms) and of the best one (*best_ms); any output
+ * may be NULL.  Overwrites the handle's fields and residual history (a
+ * later solve starts afresh).  Takes about 40 x iterations iteration times.
+ * EINVAL: NULL handle, iterations < 1 or > 4096. */
+lsfft_status lsfft_autotune(lsfft_solver s, int32_t iterations, lsfft_schedule *best, double *start_ms,
+                            double *best_ms);
+
 /* Residual history r_0..r_iters of the last solve, copied to HOST out[0..cap);
  * *count receives iters + 1.  EINVAL if no solve has run. */
 lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count);

@@ -1,5 +1,8 @@
 """Build the HIP library liblsfft.so in-tree for gfx950.
 
+The host side and the FP32 and FP64 pass kernels are three translation units,
+compiled in parallel and linked into one shared library.
+
 Usage: python -m paper_2009_03762_amd.build [--quick] [--verbose]
 """
 from __future__ import annotations
@@ -8,13 +11,15 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblsfft.so")
-SOURCES = [os.path.join(PKG, "csrc", "lsfft.hip")]
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("fft.hpp", "green.hpp", "kernels.hpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("lsfft.hip", "launch_f32.hip", "launch_f64.hip")]
+HEADERS = [os.path.join(PKG, "csrc", f) for f in ("fft.hpp", "green.hpp", "kernels.hpp", "disp.hpp", "reduce.hpp",
+                                                  "solver.hpp", "launch.hpp")]
 ARCH = os.environ.get("LSFFT_ARCH", "gfx950")
 
 
@@ -25,26 +30,48 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def command(out=LIB, quick=False):
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions stay disabled in every HIP build of this library
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-o", out] + SOURCES
+def compile_flags(quick=False):
+    flags = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+             # packed FP32 instructions stay disabled in every HIP build of this library
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include")]
     if quick:
-        cmd.insert(1, "-DLSFFT_QUICK_BUILD")
-    return cmd
+        flags.append("-DLSFFT_QUICK_BUILD")
+    return flags
+
+
+def commands(objdir, out=LIB, quick=False):
+    """(compile commands, one per source; the link command)."""
+    objs = [os.path.join(objdir, os.path.splitext(os.path.basename(s))[0] + ".o") for s in SOURCES]
+    comp = [compile_flags(quick) + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + objs
+    return comp, link
 
 
 def build(quick=False, verbose=False, out=LIB):
     t0 = time.time()
     tmp = out + ".tmp"
-    cmd = command(tmp, quick)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building liblsfft.so")
+    with tempfile.TemporaryDirectory(prefix="lsfft_build_") as objdir:
+        comp, link = commands(objdir, tmp, quick)
+        procs = []
+        for cmd in comp:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        failed = False
+        for cmd, p in zip(comp, procs):
+            log, _ = p.communicate()
+            if p.returncode != 0:
+                failed = True
+                sys.stderr.write(log)
+        if failed:
+            raise RuntimeError("hipcc failed compiling liblsfft.so")
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking liblsfft.so")
     os.replace(tmp, out)
     if verbose:
         print(f"built {out} in {time.time() - t0:.1f}s", flush=True)

@@ -189,6 +189,7 @@ template <typename T> struct SArgs {
   double *partial;     // [system][gridDim.x][8]: 6 stress sums, sum |f|^2
   const State *st;     // [system]
   int Z;               // planes per workgroup
+  int xcd;             // 1: XCD-aware order of the tiles
   int zero_u;          // u is identically zero (first pass): the LDS variant skips its loads
 };
 
@@ -204,15 +205,11 @@ template <typename T> __device__ __forceinline__ void stencil_member(SArgs<T> &a
 
 template <int SCHEME> struct Stencil;
 
-// Tile of a stencil workgroup: y-blocks fastest, then z-blocks.  Each XCD
-// takes a contiguous range of tiles, so workgroups marching neighbouring
-// y-blocks side by side share their halo lines in that XCD's L2.
-#ifndef LSFFT_STENCIL_XCD
-#define LSFFT_STENCIL_XCD 1
-#endif
-__device__ __forceinline__ int stencil_tile() {
-  return LSFFT_STENCIL_XCD ? (int)xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-}
+// Tile of a stencil workgroup: y-blocks fastest, then z-blocks.  In the
+// XCD-aware order each XCD takes a contiguous range of tiles, so workgroups
+// marching neighbouring y-blocks side by side share their halo lines in that
+// XCD's L2.
+__device__ __forceinline__ int stencil_tile(int xcd) { return (int)tile_of(blockIdx.x, gridDim.x, xcd); }
 
 // Average forward difference over the cell, eq. (36) carried to 3D.
 template <> struct Stencil<SCHEME_AFB> {
@@ -315,7 +312,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
   const int ny_blocks = n2 / T2;
-  const int tile = stencil_tile();
+  const int tile = stencil_tile(a.xcd);
   const int y0 = (tile % ny_blocks) * T2;
   const int z0 = (tile / ny_blocks) * a.Z;
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
@@ -535,7 +532,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
   const int ny_blocks = (n2 + G * T2 - 1) / (G * T2);
-  const int tile = stencil_tile();
+  const int tile = stencil_tile(a.xcd);
   for (int i = tid; i < N1; i += WG) twl[i] = a.tw[i];
   const int g = tid / NX, xt = tid % NX;
   const int yg0 = (tile % ny_blocks) * G * T2 + g * T2;
@@ -816,7 +813,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
   int i1, i2;
   bool valid;
   if ((long long)blockIdx.x < a.main_blocks) {
-    const long long col = xcd_tile(blockIdx.x, a.main_blocks) * P + p;
+    const long long col = tile_of(blockIdx.x, a.main_blocks, a.xcd) * P + p;
     valid = col < (long long)a.d.n2 * L;
     i2 = (int)(col / L);
     i1 = (int)(col % L);

@@ -1,0 +1,127 @@
+// Definitions of the pass-kernel launches, instantiated once per precision
+// by launch_f32.hip and launch_f64.hip.
+#pragma once
+#include "solver.hpp"
+
+namespace lsfft_host {
+
+template <typename T>
+hipError_t Launch<T>::xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid) {
+  switch (s->d.L) {
+#define XCASE(Lv)                                                                                        \
+case Lv:                                                                                               \
+  hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
+  return hipGetLastError();
+    LSFFT_X_LENGTHS(XCASE)
+#undef XCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T> template <bool FWD>
+hipError_t Launch<T>::ypass(lsfft_solver s, const lsfft::YArgs<T> &a, int grid) {
+  switch (s->d.n2) {
+#define YCASE(Nv)                                                                                      \
+case Nv: {                                                                                           \
+  constexpr int E = ey_of(Nv), P0 = pcols<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                        \
+  if (s->yv)                                                                                         \
+    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P1, FWD>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, \
+                       s->stream, a);                                                                \
+  else                                                                                               \
+    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P0, FWD>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, \
+                       s->stream, a);                                                                \
+  return hipGetLastError();                                                                          \
+}
+    LSFFT_YZ_LENGTHS(YCASE)
+#undef YCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t Launch<T>::zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+  switch (s->d.n3) {
+#define ZCASE(Nv)                                                                                      \
+case Nv: {                                                                                           \
+  constexpr int E = ez_of(Nv), P0 = pcols_z<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                      \
+  if (s->zv)                                                                                         \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, s->stream, \
+                       a);                                                                           \
+  else                                                                                               \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, s->stream, \
+                       a);                                                                           \
+  return hipGetLastError();                                                                          \
+}
+    LSFFT_YZ_LENGTHS(ZCASE)
+#undef ZCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t Launch<T>::uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid) {
+  switch (s->d.L) {
+#define UCASE(Lv)                                                                                         \
+case Lv:                                                                                                \
+  hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
+  return hipGetLastError();
+    LSFFT_X_LENGTHS(UCASE)
+#undef UCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T> template <int SCH>
+hipError_t Launch<T>::stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
+  switch (s->n[0]) {
+#define SCASE(Lv)                                                                                      \
+case 2 * Lv:                                                                                         \
+  if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
+    hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), \
+                       0, s->stream, a);                                                             \
+    return hipGetLastError();                                                                        \
+  } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
+    hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), 0, \
+                       s->stream, a);                                                                \
+    return hipGetLastError();                                                                        \
+  } else {                                                                                           \
+    return hipErrorInvalidValue;                                                                     \
+  }
+    LSFFT_X_LENGTHS(SCASE)
+#undef SCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t Launch<T>::stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
+  return s->scheme == LSFFT_FB ? stencil_s<lsfft::SCHEME_FB>(s, a, grid) : stencil_s<lsfft::SCHEME_AFB>(s, a, grid);
+}
+
+template <typename T>
+hipError_t Launch<T>::zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+  switch (s->d.n3) {
+#define ZUCASE(Nv)                                                                                     \
+case Nv: {                                                                                           \
+  constexpr int E = ezu_of(Nv), P0 = pcols_zu<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                    \
+  if (s->zv)                                                                                         \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0,    \
+                       s->stream, a);                                                                \
+  else                                                                                               \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P0>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0,    \
+                       s->stream, a);                                                                \
+  return hipGetLastError();                                                                          \
+}
+    LSFFT_YZ_LENGTHS(ZUCASE)
+#undef ZUCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lsfft_host

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/lsfft.h: validation, device
-// buffers, per-axis tables, kernel dispatch over the supported transform
-// lengths, and the fixed-point loop with a device-side stop flag.
+// buffers, per-axis tables, the launch schedule and its tuner, and the
+// fixed-point loop with a device-side stop flag.  The pass kernels are
+// launched through Launch<T> (launch_f32.hip, launch_f64.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -9,77 +10,15 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
-#include "../../include/lsfft.h"
-#include "disp.hpp"
+#include "solver.hpp"
+#include "reduce.hpp"
 
-using lsfft::cplx;
-using lsfft::Dims;
-using lsfft::State;
+using namespace lsfft_host;
 
 namespace {
-
-// ------------------------------------------------------------------ sizes
-// Points per thread for each transform: y and z use radix-8/4/2 passes with 8
-// points per thread, x uses 4 (its six strain and six spectrum components are
-// all held in registers); lengths with a factor 3 use 6 (x, z) or 12 (y).
-#ifndef LSFFT_XE
-#define LSFFT_XE 4
-#endif
-#ifndef LSFFT_ZE
-#define LSFFT_ZE 8
-#endif
-#ifndef LSFFT_ZSEG
-#define LSFFT_ZSEG 64
-#endif
-constexpr int e_pow2(int L) { return L < 8 ? L : 8; }
-constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : (L < LSFFT_XE ? L : LSFFT_XE); }
-constexpr int ey_of(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : e_pow2(n); }
-constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZE ? n : LSFFT_ZE); }
-// Columns per workgroup: at least `seg` bytes of each row (coalescing), at
-// least 256 threads per workgroup.
-template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
-  const int tpc = n / E;
-  const int pmin = seg / (int)sizeof(cplx<T>);
-  const int p = 256 / tpc;
-  return p > pmin ? p : pmin;
-}
-template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n, E, 128); }
-template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
-// z-pass of the displacement form (three components)
-#ifndef LSFFT_ZUE
-#define LSFFT_ZUE LSFFT_ZE
-#endif
-#ifndef LSFFT_ZUSEG
-#define LSFFT_ZUSEG LSFFT_ZSEG
-#endif
-constexpr int ezu_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZUE ? n : LSFFT_ZUE); }
-template <typename T> constexpr int pcols_zu(int n, int E) {
-  return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
-}
-constexpr int XWG = 256;
-// Stencil kernel: its 2 x 3 x-transforms must fit in 256 threads (<= 32 threads each).
-constexpr int es_of(int L) {
-  return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
-}
-#ifndef LSFFT_ST2
-#define LSFFT_ST2 2
-#endif
-constexpr int ST2 = LSFFT_ST2;
-constexpr bool stencil_reg_kernel(int n1) { return (n1 & (n1 - 1)) == 0 && n1 >= 8; }
-// LDS of the stencil kernels (n1 values per line): the register-resident one
-// holds one FP64 u plane (T2+2 lines x 3) per y-group, two sigma planes
-// (T2+1 lines x 6), the f lines (T2 x 3) and the x twiddles; the other one
-// two u planes.
-template <typename T> constexpr long long stencil_lds(int n1) {
-  const long long G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
-  const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
-  const long long twiddles = stencil_reg_kernel(n1) ? 2LL * n1 * (long long)sizeof(T) : 0;
-  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + twiddles +
-         256;
-}
-template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
 
 // The transform lengths the kernels are instantiated for: 2^a or 3 * 2^a.
 bool supported_len(int n) {
@@ -147,58 +86,6 @@ template <typename T> std::vector<T> axis_tables(const int n[3], const double h[
 
 }  // namespace
 
-struct lsfft_solver_s {
-  int n[3];
-  double h[3];
-  double lam0, mu0;       // reference medium of system 0 (operator entry points)
-  int B = 1;              // systems in the batch
-  int launch_b = 1;       // systems covered by the launches being issued
-  std::vector<double> lam0v, mu0v;  // reference medium of every system
-  void *mem = nullptr;    // lsfft::Member<T>[B]
-  double *enorm = nullptr;  // |Ebar|_F of every system
-  lsfft::Strides bs{};
-  long long spx = 0, spz = 0;  // doubles between systems in px / pz
-  int disc, scheme, prec, M, pw;
-  hipStream_t stream;
-  Dims d;
-  void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
-  void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
-  void *dgo_main = nullptr, *dgo_nyq = nullptr;
-  void *u = nullptr;      // displacement (FB, AFB): [3][n3][n2][n1], FP64 in both precisions
-  int disp = 0;           // 1: displacement-form path with real-space stencils
-  int sZ = 0, nsb = 0, nub = 0;
-  double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
-  int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
-  long long y_main_blocks = 0, z_main_blocks = 0;
-  long long zu_main_blocks = 0;  // displacement-form z-pass grid
-  int nzub = 0;
-  State *st = nullptr;
-  State *st_host = nullptr;
-  double *hist = nullptr;
-  int hist_cap = 0;
-  int last_iters = -1;
-  int tabS = 0, off[3] = {0, 0, 0};
-  int timing_kernel = -1;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  double timing_mean = 0.0;
-  int timing_count = 0;
-  // FP64 warm start of an F32 displacement-form solver: a second solver in
-  // F64 that borrows u, the device state and the residual history of this
-  // one and runs its first `warm` iterations.
-  lsfft_solver_s *twin = nullptr;
-  int warm = 0;
-  int borrowed = 0;  // u, st, st_host and hist belong to another solver
-  // Replay of captured iteration chunks: an internal stream (default
-  // priority) that waits on `stream`, and the executable graph of GRAPH_CHUNK
-  // iterations for the (tol, maxit) it was captured with.
-  int use_graphs = 1;
-  hipStream_t gstream = nullptr;
-  hipEvent_t gevent = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double g_tol = -1.0;
-  int g_maxit = -1;
-};
 
 namespace {
 
@@ -212,156 +99,6 @@ namespace {
     }                                                      \
   } while (0)
 
-// Lengths handled by the dispatch switches.  Every supported n_r = 2^a 3^b in
-// [4, 512] appears for y / z; x uses n1/2.
-#ifdef LSFFT_QUICK_BUILD
-#define LSFFT_YZ_LENGTHS(X) X(8) X(16) X(64) X(256)
-#define LSFFT_X_LENGTHS(X) X(4) X(8) X(32) X(128)
-#else
-#define LSFFT_YZ_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
-#define LSFFT_X_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
-#endif
-
-template <typename T> struct Launch {
-  static hipError_t xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid) {
-    switch (s->d.L) {
-#define XCASE(Lv)                                                                                        \
-  case Lv:                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
-    return hipGetLastError();
-      LSFFT_X_LENGTHS(XCASE)
-#undef XCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  static int xgrid(int L, long long rows) {
-    int tpc = 1;
-    switch (L) {
-#define XG(Lv) \
-  case Lv:     \
-    tpc = Lv / ex_of(Lv); \
-    break;
-      LSFFT_X_LENGTHS(XG)
-#undef XG
-      default:
-        return 0;
-    }
-    const int P = XWG / tpc;
-    return (int)((rows + P - 1) / P);
-  }
-  template <bool FWD> static hipError_t ypass(lsfft_solver s, const lsfft::YArgs<T> &a, int grid) {
-    switch (s->d.n2) {
-#define YCASE(Nv)                                                                                     \
-  case Nv: {                                                                                          \
-    constexpr int E = ey_of(Nv), P = pcols<T>(Nv, E);                                                 \
-    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P, FWD>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
-    return hipGetLastError();                                                                          \
-  }
-      LSFFT_YZ_LENGTHS(YCASE)
-#undef YCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  static int ycols(int n) {
-    switch (n) {
-#define YC(Nv) \
-  case Nv:     \
-    return pcols<T>(Nv, ey_of(Nv));
-      LSFFT_YZ_LENGTHS(YC)
-#undef YC
-      default:
-        return 0;
-    }
-  }
-  static hipError_t zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
-    switch (s->d.n3) {
-#define ZCASE(Nv)                                                                                   \
-  case Nv: {                                                                                        \
-    constexpr int E = ez_of(Nv), P = pcols_z<T>(Nv, E);                                             \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
-    return hipGetLastError();                                                                        \
-  }
-      LSFFT_YZ_LENGTHS(ZCASE)
-#undef ZCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  static int zucols(int n) {
-    switch (n) {
-#define ZUC(Nv) \
-  case Nv:      \
-    return pcols_zu<T>(Nv, ezu_of(Nv));
-      LSFFT_YZ_LENGTHS(ZUC)
-#undef ZUC
-      default:
-        return 0;
-    }
-  }
-  static int zcols(int n) {
-    switch (n) {
-#define ZC(Nv) \
-  case Nv:     \
-    return pcols_z<T>(Nv, ez_of(Nv));
-      LSFFT_YZ_LENGTHS(ZC)
-#undef ZC
-      default:
-        return 0;
-    }
-  }
-  static hipError_t uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid) {
-    switch (s->d.L) {
-#define UCASE(Lv)                                                                                         \
-  case Lv:                                                                                                \
-    hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
-    return hipGetLastError();
-      LSFFT_X_LENGTHS(UCASE)
-#undef UCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  template <int SCH> static hipError_t stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
-    switch (s->n[0]) {
-#define SCASE(Lv)                                                                                      \
-  case 2 * Lv:                                                                                         \
-    if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
-      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), \
-                         0, s->stream, a);                                                             \
-      return hipGetLastError();                                                                        \
-    } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
-      hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, ST2>), dim3(grid, s->launch_b), dim3(256), 0, \
-                         s->stream, a);                                                                \
-      return hipGetLastError();                                                                        \
-    } else {                                                                                           \
-      return hipErrorInvalidValue;                                                                     \
-    }
-      LSFFT_X_LENGTHS(SCASE)
-#undef SCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  static hipError_t stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid) {
-    return s->scheme == LSFFT_FB ? stencil_s<lsfft::SCHEME_FB>(s, a, grid) : stencil_s<lsfft::SCHEME_AFB>(s, a, grid);
-  }
-  static hipError_t zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
-    switch (s->d.n3) {
-#define ZUCASE(Nv)                                                                                    \
-  case Nv: {                                                                                          \
-    constexpr int E = ezu_of(Nv), P = pcols_zu<T>(Nv, E);                                             \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P>), dim3(grid, s->launch_b), dim3(P * (Nv / E)), 0, s->stream, a); \
-    return hipGetLastError();                                                                          \
-  }
-      LSFFT_YZ_LENGTHS(ZUCASE)
-#undef ZUCASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-};
 
 template <typename T> lsfft::GreenParams<T> green_params(lsfft_solver s) {
   lsfft::GreenParams<T> g;
@@ -443,13 +180,14 @@ template <typename T> lsfft::YArgs<T> yargs(lsfft_solver s, bool flag, int ncomp
   a.tw = (const cplx<T> *)s->twy;
   a.st = flag ? s->st : nullptr;
   a.bs = s->bs;
-  const int py = Launch<T>::ycols(s->n[1]);
+  const int py = Launch<T>::ycols(s->n[1], s->yv);
   a.main_blocks = ((long long)ncomp * s->n[2] * s->d.L + py - 1) / py;
+  a.xcd = (s->xcd >> 1) & 1;
   return a;
 }
 
 template <typename T> int ygrid(lsfft_solver s, int ncomp) {
-  const int py = Launch<T>::ycols(s->n[1]);
+  const int py = Launch<T>::ycols(s->n[1], s->yv);
   return (int)(((long long)ncomp * s->n[2] * s->d.L + py - 1) / py + ((long long)ncomp * s->n[2] + py - 1) / py);
 }
 
@@ -467,6 +205,7 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
   a.st = flag ? s->st : nullptr;
   a.main_blocks = s->z_main_blocks;
   a.forward_only = forward_only;
+  a.xcd = (s->xcd >> 2) & 1;
   return a;
 }
 
@@ -489,6 +228,7 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   a.partial = s->px;
   a.st = s->st;
   a.Z = s->sZ;
+  a.xcd = s->xcd & 1;
   a.zero_u = zero_u;
   return a;
 }
@@ -649,11 +389,11 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   ra.hcap = s->hist_cap;
   ra.ebar_norms = s->enorm;
   ra.maxit = maxit;
-  ra.tol = tol;
+  ra.tol = s->tuning ? -1.0 : tol;
   ra.dgo = dgo ? 1 : 0;
   ra.disp = disp ? 1 : 0;
   ra.N = (double)s->d.N;
-  ra.div_factor = 1e6;
+  ra.div_factor = s->tuning ? __builtin_huge_val() : 1e6;
   // One iteration of every system: forward y, z-pass with the Green step,
   // reduction and stopping test, inverse y, then the x side (displacement
   // update and stencil, or x-pass).  `last` omits the trailing stencil (the
@@ -709,7 +449,7 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
     if (gs != LSFFT_OK) return gs;
     LSFFT_CHECK(hipEventRecord(s->gevent, s->stream));
     LSFFT_CHECK(hipStreamWaitEvent(s->gstream, s->gevent, 0));
-    int per_sync = (tol == 0.0) ? (k_end - k + GRAPH_CHUNK - 1) / GRAPH_CHUNK : 1;
+    int per_sync = (tol == 0.0 || s->tuning) ? (k_end - k + GRAPH_CHUNK - 1) / GRAPH_CHUNK : 1;
     for (;;) {
       for (int j = 0; j < per_sync && k < k_end; ++j, k += GRAPH_CHUNK) LSFFT_CHECK(hipGraphLaunch(s->gexec, s->gstream));
       lsfft_status rs = read_state(s->gstream);
@@ -719,7 +459,7 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
     }
     return LSFFT_OK;
   }
-  int chunk = (tol == 0.0) ? k_end - k_begin : 2;
+  int chunk = (tol == 0.0 || s->tuning) ? k_end - k_begin : 2;
   for (;;) {
     const int nenq = std::min(chunk, k_end - k);
     for (int j = 0; j < nenq; ++j, ++k) LSFFT_CHECK(iteration(k + 1 == k_end));
@@ -733,8 +473,8 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
 
 // Eb: [B][6].  Returns the largest status over the systems (OK < ENOTCONV <
 // EDIVERGED) or a negative error.
-template <typename T>
-lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) {
+// Room for the residuals of iterations 0 .. maxit of every system.
+lsfft_status ensure_hist(lsfft_solver s, int maxit) {
   if (maxit + 1 > s->hist_cap) {
     if (s->hist) (void)hipFree(s->hist);
     s->hist = nullptr;
@@ -745,6 +485,22 @@ lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) 
     }
     s->hist_cap = cap;
   }
+  return LSFFT_OK;
+}
+
+// Drop the captured iteration chunk (the schedule or the stopping rule it
+// was captured with has changed).
+void drop_graph(lsfft_solver s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  s->gexec = nullptr;
+  s->g_tol = -1.0;
+  s->g_maxit = -1;
+}
+
+template <typename T>
+lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) {
+  lsfft_status hs = ensure_hist(s, maxit);
+  if (hs != LSFFT_OK) return hs;
   s->ev_used = 0;
   lsfft_status us = upload_members<T>(s, Eb);
   if (us != LSFFT_OK) return us;
@@ -851,6 +607,49 @@ template <typename T> lsfft_status upload_moduli(lsfft_solver s, const lsfft_con
   return LSFFT_OK;
 }
 
+// y-blocks of a stencil plane: a power-of-two n1 < 256 packs 256/n1
+// independent y-groups per workgroup.
+int stencil_yblocks(const lsfft_solver s) {
+  const int n1 = s->n[0];
+  const int G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
+  return (s->n[1] + G * ST2 - 1) / (G * ST2);
+}
+
+// Grids of the passes for the solver's schedule: planes per stencil
+// workgroup and the column-tile variants of the y and z passes.
+template <typename T> lsfft_status set_grids(lsfft_solver s) {
+  const int py = Launch<T>::ycols(s->n[1], s->yv);
+  const int pzc = Launch<T>::zcols(s->n[2], s->zv);
+  if (py <= 0 || pzc <= 0) return LSFFT_EINVAL;
+  s->y_main_blocks = (6LL * s->n[2] * s->d.L + py - 1) / py;
+  s->nyb = (int)(s->y_main_blocks + (6LL * s->n[2] + py - 1) / py);
+  s->z_main_blocks = ((long long)s->n[1] * s->d.L + pzc - 1) / pzc;
+  s->nzb = (int)(s->z_main_blocks + ((long long)s->n[1] + pzc - 1) / pzc);
+  if (s->disp) {
+    if (s->sZ < 2 || s->n[2] % s->sZ) return LSFFT_EINVAL;
+    s->nsb = stencil_yblocks(s) * (s->n[2] / s->sZ);
+    s->nub = s->nxb;
+    const int pzu = Launch<T>::zucols(s->n[2], s->zv);
+    if (pzu <= 0) return LSFFT_EINVAL;
+    s->zu_main_blocks = ((long long)s->n[1] * s->d.L + pzu - 1) / pzu;
+    s->nzub = (int)(s->zu_main_blocks + ((long long)s->n[1] + pzu - 1) / pzu);
+  }
+  return LSFFT_OK;
+}
+
+// Partial-sum slots per system that any schedule needs: x-pass or stencil
+// workgroups (8 values each; two planes per stencil workgroup at least) and
+// z-pass workgroups (one value each).
+template <typename T> void partial_slots(const lsfft_solver s, long long &spx, long long &spz) {
+  const long long nsb_max = s->disp ? (long long)stencil_yblocks(s) * (s->n[2] / 2) : 0;
+  spx = 8LL * std::max<long long>(s->nxb, nsb_max);
+  spz = 1;
+  for (int v = 0; v < 2; ++v) {
+    const int pzc = Launch<T>::zcols(s->n[2], v);
+    spz = std::max<long long>(spz, ((long long)s->n[1] * s->d.L + pzc - 1) / pzc + ((long long)s->n[1] + pzc - 1) / pzc);
+  }
+}
+
 template <typename T> lsfft_status upload_tables(lsfft_solver s) {
   std::vector<T> tab = axis_tables<T>(s->n, s->h, s->off, s->tabS);
   LSFFT_CHECK(hipMalloc(&s->tab, tab.size() * sizeof(T)));
@@ -865,14 +664,8 @@ template <typename T> lsfft_status upload_tables(lsfft_solver s) {
   LSFFT_CHECK(hipMemcpy(s->twy, wy.data(), wy.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
   LSFFT_CHECK(hipMemcpy(s->twz, wz.data(), wz.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
   s->nxb = Launch<T>::xgrid(s->d.L, s->d.rows);
-  const int py = Launch<T>::ycols(s->n[1]);
-  s->y_main_blocks = (6LL * s->n[2] * s->d.L + py - 1) / py;
-  s->nyb = (int)(s->y_main_blocks + (6LL * s->n[2] + py - 1) / py);
-  const int pzc = Launch<T>::zcols(s->n[2]);
-  s->z_main_blocks = ((long long)s->n[1] * s->d.L + pzc - 1) / pzc;
-  s->nzb = (int)(s->z_main_blocks + ((long long)s->n[1] + pzc - 1) / pzc);
-  if (s->nxb <= 0 || py <= 0 || pzc <= 0) return LSFFT_EINVAL;
-  return LSFFT_OK;
+  if (s->nxb <= 0) return LSFFT_EINVAL;
+  return set_grids<T>(s);
 }
 
 template <typename T> lsfft_status build_dgo(lsfft_solver s) {
@@ -946,6 +739,137 @@ template <typename T> lsfft_status green_impl(lsfft_solver s, const void *in, vo
 }
 
 bool ok_moduli(double l, double m) { return std::isfinite(l) && std::isfinite(m) && m > 0.0 && 3.0 * l + 2.0 * m > 0.0; }
+
+// ------------------------------------------------------------------ schedule
+template <typename T> void get_schedule(const lsfft_solver s, lsfft_schedule *out) {
+  out->stencil_planes = s->disp ? s->sZ : 0;
+  out->y_cols = Launch<T>::ycols(s->n[1], s->yv);
+  out->z_cols = s->disp ? Launch<T>::zucols(s->n[2], s->zv) : Launch<T>::zcols(s->n[2], s->zv);
+  out->xcd_order = s->xcd;
+}
+
+// Apply a schedule after checking it against the ones this grid offers.
+template <typename T> lsfft_status set_schedule(lsfft_solver s, const lsfft_schedule *in) {
+  int yv = -1, zv = -1;
+  for (int v = 1; v >= 0; --v) {
+    if (in->y_cols == Launch<T>::ycols(s->n[1], v)) yv = v;
+    const int zc = s->disp ? Launch<T>::zucols(s->n[2], v) : Launch<T>::zcols(s->n[2], v);
+    if (in->z_cols == zc) zv = v;
+  }
+  if (yv < 0 || zv < 0 || in->xcd_order < 0 || in->xcd_order > 7) return LSFFT_EINVAL;
+  int z = 0;
+  if (s->disp) {
+    z = in->stencil_planes;
+    if (z < 2 || z > s->n[2] || (z & 1) || s->n[2] % z) return LSFFT_EINVAL;
+  } else if (in->stencil_planes != 0) {
+    return LSFFT_EINVAL;
+  }
+  const int oz = s->sZ, oy = s->yv, ov = s->zv;
+  if (s->disp) s->sZ = z;
+  s->yv = yv;
+  s->zv = zv;
+  lsfft_status st = set_grids<T>(s);
+  if (st != LSFFT_OK) {
+    s->sZ = oz;
+    s->yv = oy;
+    s->zv = ov;
+    (void)set_grids<T>(s);
+    return st;
+  }
+  s->xcd = in->xcd_order;
+  drop_graph(s);
+  return LSFFT_OK;
+}
+
+// Milliseconds per iteration of the whole batch under the current schedule:
+// the best of `reps` timed runs of `chunks` captured chunks of iterations
+// (after one untimed run), on a unit axial macroscopic strain, with the
+// stopping test off.
+template <typename T> lsfft_status time_schedule(lsfft_solver s, int chunks, int reps, double &ms) {
+  const int iters = chunks * GRAPH_CHUNK;
+  double best = __builtin_huge_val();
+  for (int r = 0; r <= reps; ++r) {
+    LSFFT_CHECK(hipStreamSynchronize(s->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    lsfft_status ps = run_phase<T>(s, 0.0, iters - 1, 0, iters, true);
+    if (ps != LSFFT_OK) return ps;
+    LSFFT_CHECK(hipStreamSynchronize(s->stream));
+    const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (r > 0) best = std::min(best, el / iters);
+  }
+  ms = best;
+  return LSFFT_OK;
+}
+
+// Coordinate search over the schedule knobs: stencil planes per workgroup,
+// the two column tiles of the y and z passes, then each XCD-order bit; a
+// change is kept when it is faster by more than 1 %.
+template <typename T>
+lsfft_status autotune(lsfft_solver s, int iterations, lsfft_schedule *best, double *start_ms, double *best_ms) {
+  const int chunks = std::max(1, (iterations + GRAPH_CHUNK - 1) / GRAPH_CHUNK);
+  const int reps = 3;
+  lsfft_status st = ensure_hist(s, chunks * GRAPH_CHUNK);
+  if (st != LSFFT_OK) return st;
+  std::vector<double> eb(6 * (size_t)s->B, 0.0);
+  for (int b = 0; b < s->B; ++b) eb[6 * b] = 1.0;
+  st = upload_members<T>(s, eb.data());
+  if (st != LSFFT_OK) return st;
+  const int timing = s->timing_kernel;
+  s->timing_kernel = -1;
+  s->tuning = 1;
+  drop_graph(s);
+  lsfft_schedule cur;
+  get_schedule<T>(s, &cur);
+  double tcur = 0.0;
+  st = time_schedule<T>(s, chunks, reps, tcur);
+  const double t0 = tcur;
+  auto trial = [&](const lsfft_schedule &c) -> lsfft_status {
+    lsfft_status e = set_schedule<T>(s, &c);
+    if (e != LSFFT_OK) return e;
+    double t = 0.0;
+    e = time_schedule<T>(s, chunks, reps, t);
+    if (e != LSFFT_OK) return e;
+    if (t < 0.99 * tcur) {
+      cur = c;
+      tcur = t;
+    }
+    return LSFFT_OK;
+  };
+  if (st == LSFFT_OK && s->disp) {
+    const int z0 = cur.stencil_planes;
+    for (int z = 2; z <= 32 && st == LSFFT_OK; z *= 2) {
+      if (z == z0 || s->n[2] % z) continue;
+      lsfft_schedule c = cur;
+      c.stencil_planes = z;
+      st = trial(c);
+    }
+  }
+  for (int v = 0; v < 2 && st == LSFFT_OK; ++v) {
+    lsfft_schedule c = cur;
+    c.y_cols = Launch<T>::ycols(s->n[1], v);
+    if (c.y_cols != cur.y_cols) st = trial(c);
+  }
+  for (int v = 0; v < 2 && st == LSFFT_OK; ++v) {
+    lsfft_schedule c = cur;
+    c.z_cols = s->disp ? Launch<T>::zucols(s->n[2], v) : Launch<T>::zcols(s->n[2], v);
+    if (c.z_cols != cur.z_cols) st = trial(c);
+  }
+  for (int bit = 0; bit < 3 && st == LSFFT_OK; ++bit) {
+    if (bit == 0 && !s->disp) continue;
+    lsfft_schedule c = cur;
+    c.xcd_order = cur.xcd_order ^ (1 << bit);
+    st = trial(c);
+  }
+  s->tuning = 0;
+  s->timing_kernel = timing;
+  lsfft_status fs = set_schedule<T>(s, &cur);
+  if (st == LSFFT_OK) st = fs;
+  if (st != LSFFT_OK) return st;
+  if (best) *best = cur;
+  if (start_ms) *start_ms = t0;
+  if (best_ms) *best_ms = tcur;
+  return LSFFT_OK;
+}
 
 }  // namespace
 
@@ -1074,13 +998,9 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   }
   if (s->disp) {
     if (hipMalloc(&s->u, B * 3 * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
-    // y-blocks: a power-of-two n1 < 256 packs 256/n1 independent y-groups per workgroup
-    const int n1 = s->n[0];
-    const bool pow2 = stencil_reg_kernel(n1);
-    const int G = (pow2 && n1 < 256) ? 256 / n1 : 1;
-    const int ny = (s->n[1] + G * ST2 - 1) / (G * ST2);
     // planes per stencil workgroup: as many as keep >= 1024 workgroups (over
     // the whole batch), at least 2
+    const int ny = stencil_yblocks(s);
     int Z = 2;
     for (int c : {32, 16, 8, 4}) {
       if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) * count >= 1024) {
@@ -1089,15 +1009,13 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
       }
     }
     s->sZ = Z;
-    s->nsb = ny * (s->n[2] / Z);
-    s->nub = s->nxb;
-    const int pzu = (s->prec == LSFFT_F32) ? Launch<float>::zucols(s->n[2]) : Launch<double>::zucols(s->n[2]);
-    if (pzu <= 0) return fail(LSFFT_EINVAL);
-    s->zu_main_blocks = ((long long)s->n[1] * s->d.L + pzu - 1) / pzu;
-    s->nzub = (int)(s->zu_main_blocks + ((long long)s->n[1] + pzu - 1) / pzu);
   }
-  s->spx = 8LL * std::max(s->nxb, s->nsb);
-  s->spz = std::max(s->nzb, 1);
+  st = (s->prec == LSFFT_F32) ? set_grids<float>(s) : set_grids<double>(s);
+  if (st != LSFFT_OK) return fail(st);
+  if (s->prec == LSFFT_F32)
+    partial_slots<float>(s, s->spx, s->spz);
+  else
+    partial_slots<double>(s, s->spx, s->spz);
   if (hipMalloc(&s->px, sizeof(double) * B * (size_t)s->spx) != hipSuccess) return fail(LSFFT_ENOMEM);
   if (hipMalloc(&s->pz, sizeof(double) * B * (size_t)s->spz) != hipSuccess) return fail(LSFFT_ENOMEM);
   if (hipMalloc(&s->pstage, sizeof(double) * B * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
@@ -1185,6 +1103,27 @@ lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, i
 }
 
 int32_t lsfft_batch_size(lsfft_solver s) { return s ? s->B : 0; }
+
+lsfft_status lsfft_get_schedule(lsfft_solver s, lsfft_schedule *out) {
+  if (!s || !out) return LSFFT_EINVAL;
+  if (s->prec == LSFFT_F32)
+    get_schedule<float>(s, out);
+  else
+    get_schedule<double>(s, out);
+  return LSFFT_OK;
+}
+
+lsfft_status lsfft_set_schedule(lsfft_solver s, const lsfft_schedule *sch) {
+  if (!s || !sch) return LSFFT_EINVAL;
+  return (s->prec == LSFFT_F32) ? set_schedule<float>(s, sch) : set_schedule<double>(s, sch);
+}
+
+lsfft_status lsfft_autotune(lsfft_solver s, int32_t iterations, lsfft_schedule *best, double *start_ms,
+                            double *best_ms) {
+  if (!s || iterations < 1 || iterations > 4096) return LSFFT_EINVAL;
+  return (s->prec == LSFFT_F32) ? autotune<float>(s, iterations, best, start_ms, best_ms)
+                                : autotune<double>(s, iterations, best, start_ms, best_ms);
+}
 
 lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count) {
   if (!s || !out || cap < 0 || s->last_iters < 0) return LSFFT_EINVAL;

@@ -1,0 +1,229 @@
+// Internal header of the host library: launch-shape constants, the solver
+// object behind the opaque lsfft_solver handle, and the kernel dispatch over
+// the supported transform lengths (defined per precision in launch_f32.hip
+// and launch_f64.hip, which build in parallel).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/lsfft.h"
+#include "disp.hpp"
+
+using lsfft::cplx;
+using lsfft::Dims;
+using lsfft::State;
+
+namespace lsfft_host {
+
+// ------------------------------------------------------------------ sizes
+// Points per thread for each transform: y and z use radix-8/4/2 passes with 8
+// points per thread, x uses 4 (its six strain and six spectrum components are
+// all held in registers); lengths with a factor 3 use 6 (x, z) or 12 (y).
+#ifndef LSFFT_XE
+#define LSFFT_XE 4
+#endif
+#ifndef LSFFT_ZE
+#define LSFFT_ZE 8
+#endif
+#ifndef LSFFT_ZSEG
+#define LSFFT_ZSEG 64
+#endif
+constexpr int e_pow2(int L) { return L < 8 ? L : 8; }
+constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : (L < LSFFT_XE ? L : LSFFT_XE); }
+constexpr int ey_of(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : e_pow2(n); }
+constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZE ? n : LSFFT_ZE); }
+// Columns per workgroup: at least `seg` bytes of each row (coalescing), at
+// least 256 threads per workgroup.
+template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
+  const int tpc = n / E;
+  const int pmin = seg / (int)sizeof(cplx<T>);
+  const int p = 256 / tpc;
+  return p > pmin ? p : pmin;
+}
+template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n, E, 128); }
+template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
+// z-pass of the displacement form (three components)
+#ifndef LSFFT_ZUE
+#define LSFFT_ZUE LSFFT_ZE
+#endif
+#ifndef LSFFT_ZUSEG
+#define LSFFT_ZUSEG LSFFT_ZSEG
+#endif
+constexpr int ezu_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZUE ? n : LSFFT_ZUE); }
+template <typename T> constexpr int pcols_zu(int n, int E) {
+  return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
+}
+// The alternative column tile of a y / z pass offered to the schedule tuner:
+// twice the columns while the workgroup stays within 512 threads and 80 KB of
+// LDS (two transposition buffers and the twiddles), else half of them while
+// it keeps at least 64 threads; P itself when neither holds.
+template <typename T> constexpr int palt(int n, int E, int P) {
+  const int tpc = n / E;
+  const long long lds2 = (2LL * n * (2 * P) + n) * (long long)sizeof(cplx<T>);
+  if (2 * P * tpc <= 512 && lds2 <= 80 * 1024) return 2 * P;
+  if (P % 2 == 0 && (P / 2) * tpc >= 64) return P / 2;
+  return P;
+}
+constexpr int XWG = 256;
+// Stencil kernel: its 2 x 3 x-transforms must fit in 256 threads (<= 32 threads each).
+constexpr int es_of(int L) {
+  return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
+}
+#ifndef LSFFT_ST2
+#define LSFFT_ST2 2
+#endif
+constexpr int ST2 = LSFFT_ST2;
+constexpr bool stencil_reg_kernel(int n1) { return (n1 & (n1 - 1)) == 0 && n1 >= 8; }
+// LDS of the stencil kernels (n1 values per line): the register-resident one
+// holds one FP64 u plane (T2+2 lines x 3) per y-group, two sigma planes
+// (T2+1 lines x 6), the f lines (T2 x 3) and the x twiddles; the other one
+// two u planes.
+template <typename T> constexpr long long stencil_lds(int n1) {
+  const long long G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
+  const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
+  const long long twiddles = stencil_reg_kernel(n1) ? 2LL * n1 * (long long)sizeof(T) : 0;
+  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + twiddles +
+         256;
+}
+template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
+
+// Lengths handled by the dispatch switches.  Every supported n_r = 2^a 3^b in
+// [4, 512] appears for y / z; x uses n1/2.
+#ifdef LSFFT_QUICK_BUILD
+#define LSFFT_YZ_LENGTHS(X) X(8) X(16) X(64) X(256)
+#define LSFFT_X_LENGTHS(X) X(4) X(8) X(32) X(128)
+#else
+#define LSFFT_YZ_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define LSFFT_X_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#endif
+
+}  // namespace lsfft_host
+
+struct lsfft_solver_s {
+  int n[3];
+  double h[3];
+  double lam0, mu0;       // reference medium of system 0 (operator entry points)
+  int B = 1;              // systems in the batch
+  int launch_b = 1;       // systems covered by the launches being issued
+  std::vector<double> lam0v, mu0v;  // reference medium of every system
+  void *mem = nullptr;    // lsfft::Member<T>[B]
+  double *enorm = nullptr;  // |Ebar|_F of every system
+  lsfft::Strides bs{};
+  long long spx = 0, spz = 0;  // doubles between systems in px / pz
+  int disc, scheme, prec, M, pw;
+  hipStream_t stream;
+  Dims d;
+  void *eps = nullptr, *lam = nullptr, *mu = nullptr, *spec = nullptr, *nyq = nullptr;
+  void *tab = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
+  void *dgo_main = nullptr, *dgo_nyq = nullptr;
+  void *u = nullptr;      // displacement (FB, AFB): [3][n3][n2][n1], FP64 in both precisions
+  int disp = 0;           // 1: displacement-form path with real-space stencils
+  int sZ = 0, nsb = 0, nub = 0;
+  double *px = nullptr, *pz = nullptr, *pg = nullptr, *pstage = nullptr;
+  int nxb = 0, nzb = 0, nyb = 0, ngb = 0;
+  long long y_main_blocks = 0, z_main_blocks = 0;
+  long long zu_main_blocks = 0;  // displacement-form z-pass grid
+  int nzub = 0;
+  State *st = nullptr;
+  State *st_host = nullptr;
+  double *hist = nullptr;
+  int hist_cap = 0;
+  int last_iters = -1;
+  int tabS = 0, off[3] = {0, 0, 0};
+  int timing_kernel = -1;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double timing_mean = 0.0;
+  int timing_count = 0;
+  // FP64 warm start of an F32 displacement-form solver: a second solver in
+  // F64 that borrows u, the device state and the residual history of this
+  // one and runs its first `warm` iterations.
+  lsfft_solver_s *twin = nullptr;
+  int warm = 0;
+  int borrowed = 0;  // u, st, st_host and hist belong to another solver
+  // Replay of captured iteration chunks: an internal stream (default
+  // priority) that waits on `stream`, and the executable graph of GRAPH_CHUNK
+  // iterations for the (tol, maxit) it was captured with.
+  int use_graphs = 1;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gevent = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_tol = -1.0;
+  int g_maxit = -1;
+  // Schedule: column-tile variant of the y pass (yv) and of the z passes
+  // (zv), XCD-aware tile order (bit 0 stencil, bit 1 y pass, bit 2 z pass);
+  // the stencil's planes per workgroup are sZ above.
+  int yv = 0, zv = 0, xcd = 7;
+  // Set while the schedule tuner times iterations: no stopping test.
+  int tuning = 0;
+};
+
+namespace lsfft_host {
+
+// Workgroup counts and tile widths of the passes (no kernels referenced).
+template <typename T> struct Tiles {
+  static int xgrid(int L, long long rows) {
+    int tpc = 1;
+    switch (L) {
+#define XG(Lv) \
+  case Lv:     \
+    tpc = Lv / ex_of(Lv); \
+    break;
+      LSFFT_X_LENGTHS(XG)
+#undef XG
+      default:
+        return 0;
+    }
+    const int P = XWG / tpc;
+    return (int)((rows + P - 1) / P);
+  }
+  // columns per y-pass workgroup of tile variant v
+  static int ycols(int n, int v) {
+    switch (n) {
+#define YC(Nv) \
+  case Nv:     \
+    return v ? palt<T>(Nv, ey_of(Nv), pcols<T>(Nv, ey_of(Nv))) : pcols<T>(Nv, ey_of(Nv));
+      LSFFT_YZ_LENGTHS(YC)
+#undef YC
+      default:
+        return 0;
+    }
+  }
+  static int zucols(int n, int v) {
+    switch (n) {
+#define ZUC(Nv) \
+  case Nv:      \
+    return v ? palt<T>(Nv, ezu_of(Nv), pcols_zu<T>(Nv, ezu_of(Nv))) : pcols_zu<T>(Nv, ezu_of(Nv));
+      LSFFT_YZ_LENGTHS(ZUC)
+#undef ZUC
+      default:
+        return 0;
+    }
+  }
+  static int zcols(int n, int v) {
+    switch (n) {
+#define ZC(Nv) \
+  case Nv:     \
+    return v ? palt<T>(Nv, ez_of(Nv), pcols_z<T>(Nv, ez_of(Nv))) : pcols_z<T>(Nv, ez_of(Nv));
+      LSFFT_YZ_LENGTHS(ZC)
+#undef ZC
+      default:
+        return 0;
+    }
+  }
+};
+
+// Launches of the pass kernels for the current grid and schedule of a
+// solver; hipErrorInvalidValue for a length without an instantiation.
+template <typename T> struct Launch : Tiles<T> {
+  static hipError_t xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid);
+  template <bool FWD> static hipError_t ypass(lsfft_solver s, const lsfft::YArgs<T> &a, int grid);
+  static hipError_t zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
+  static hipError_t uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid);
+  template <int SCH> static hipError_t stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int grid);
+  static hipError_t stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid);
+  static hipError_t zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
+};
+
+}  // namespace lsfft_host

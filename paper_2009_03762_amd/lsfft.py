@@ -44,6 +44,19 @@ class Config(C.Structure):
     ]
 
 
+class Schedule(C.Structure):
+    """lsfft_schedule: how one iteration's passes are cut into workgroups."""
+    _fields_ = [
+        ("stencil_planes", C.c_int32),
+        ("y_cols", C.c_int32),
+        ("z_cols", C.c_int32),
+        ("xcd_order", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
@@ -57,6 +70,9 @@ def _load():
         "lsfft_solve_batch": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                         C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
         "lsfft_batch_size": (C.c_int32, [h]),
+        "lsfft_get_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
+        "lsfft_set_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
+        "lsfft_autotune": (C.c_int, [h, C.c_int32, C.POINTER(Schedule), dp, dp]),
         "lsfft_solve": (C.c_int, [h, dp, C.c_double, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), dp]),
         "lsfft_solve_device": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                          C.POINTER(C.c_int32), dp]),
@@ -80,7 +96,8 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_device", "lsfft_solve_batch",
-           "lsfft_batch_size", "lsfft_residual_history",
+           "lsfft_batch_size", "lsfft_get_schedule", "lsfft_set_schedule", "lsfft_autotune",
+           "lsfft_residual_history",
            "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
            "lsfft_get_timing",
            "lsfft_kernel_name", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
@@ -176,6 +193,35 @@ def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0)
 
 def batch_size(handle):
     return int(_lib.lsfft_batch_size(handle))
+
+
+def get_schedule(handle):
+    """lsfft_get_schedule, as a dict."""
+    sch = Schedule()
+    st = _lib.lsfft_get_schedule(handle, C.byref(sch))
+    if st != OK:
+        raise LsfftError(st, "lsfft_get_schedule")
+    return sch.as_dict()
+
+
+def set_schedule(handle, schedule):
+    """lsfft_set_schedule from a dict with the four lsfft_schedule fields."""
+    sch = Schedule(**{k: int(schedule[k]) for k, _ in Schedule._fields_})
+    st = _lib.lsfft_set_schedule(handle, C.byref(sch))
+    if st != OK:
+        raise LsfftError(st, "lsfft_set_schedule")
+
+
+def autotune(handle, iterations=16):
+    """lsfft_autotune.  Returns (best schedule dict, ms per iteration of the
+    schedule in force on entry, ms per iteration of the best)."""
+    sch = Schedule()
+    t0 = C.c_double(0.0)
+    t1 = C.c_double(0.0)
+    st = _lib.lsfft_autotune(handle, int(iterations), C.byref(sch), C.byref(t0), C.byref(t1))
+    if st != OK:
+        raise LsfftError(st, "lsfft_autotune")
+    return sch.as_dict(), t0.value, t1.value
 
 
 def solve_batch(handle, Ebars, tol, maxit, eps_dev=None, sig_dev=None):
