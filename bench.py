@@ -103,9 +103,11 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, prec, n):
+def measured_traffic(kernel, key, n, schedule):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    record, if it was taken on the current kernel sources and this workload."""
+    record (key: "f32" displacement form, "f32_strain" strain form), if it was
+    taken on the current kernel sources, this workload and this launch
+    schedule."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
@@ -114,7 +116,9 @@ def measured_traffic(kernel, prec, n):
         return None
     if rec.get("source_sha") != source_sha() or n != 256:
         return None
-    ent = rec.get("kernels", {}).get(kernel, {}).get(prec)
+    if rec.get("schedule", {}).get(key) != schedule:
+        return None
+    ent = rec.get("kernels", {}).get(kernel, {}).get(key)
     if not ent:
         return None
     return ent["read_bytes"] + ent["write_bytes"]
@@ -177,7 +181,8 @@ def run_gpu(prec, n, steps, warmup, breakdown=True, form="displacement", autotun
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": measured_traffic(dominant, prec, n),
+            "traffic": measured_traffic(dominant, prec if form == "displacement" else prec + "_strain", n,
+                                        tuned["schedule"]),
             "bytes_per_launch": ab,
             "mean_launch_ms": dom_ms,
             "launches_timed": dom_cnt,
