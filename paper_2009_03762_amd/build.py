@@ -30,29 +30,30 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def compile_flags(quick=False):
+def compile_flags(quick=False, extra=()):
     flags = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
              # packed FP32 instructions stay disabled in every HIP build of this library
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include")]
     if quick:
         flags.append("-DLSFFT_QUICK_BUILD")
-    return flags
+    return flags + list(extra)
 
 
-def commands(objdir, out=LIB, quick=False):
-    """(compile commands, one per source; the link command)."""
+def commands(objdir, out=LIB, quick=False, extra=()):
+    """(compile commands, one per source; the link command).  `extra`: further
+    compiler flags for every unit (e.g. -D overrides of the tile constants)."""
     objs = [os.path.join(objdir, os.path.splitext(os.path.basename(s))[0] + ".o") for s in SOURCES]
-    comp = [compile_flags(quick) + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    comp = [compile_flags(quick, extra) + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
     link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + objs
     return comp, link
 
 
-def build(quick=False, verbose=False, out=LIB):
+def build(quick=False, verbose=False, out=LIB, extra=()):
     t0 = time.time()
     tmp = out + ".tmp"
     with tempfile.TemporaryDirectory(prefix="lsfft_build_") as objdir:
-        comp, link = commands(objdir, tmp, quick)
+        comp, link = commands(objdir, tmp, quick, extra)
         procs = []
         for cmd in comp:
             if verbose:

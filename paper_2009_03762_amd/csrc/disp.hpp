@@ -36,11 +36,15 @@
 namespace lsfft {
 
 // Delta u_hat = K^{-1} f_hat * scale at one frequency, with the per-axis
-// table values ax[r] = axis_val(g, r, index_r).
-template <typename T>
+// table values ax[r] = axis_val(g, r, index_r).  The scheme (FB or AFB) is a
+// template parameter: the FB inverse of a Hermitian 3 x 3 needs far more
+// registers than the AFB closed form, and a kernel is sized for its
+// heaviest path.
+template <int SCH, typename T>
 __device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, const AxisVal<T> (&ax)[3],
                                                  cplx<T> (&f)[3]) {
-  if (g.scheme == SCHEME_FB) {
+  static_assert(SCH == SCHEME_FB || SCH == SCHEME_AFB, "displacement form: FB or AFB");
+  if constexpr (SCH == SCHEME_FB) {
     cplx<T> a[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) a[r] = cplx<T>{ax[r].p, ax[r].q};
@@ -795,8 +799,11 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 }
 
 // ---------------------------------------------------------------- z pass, displacement form
-template <typename T, int NZ, int E, int P>
-__global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
+#ifndef LSFFT_ZU_WAVES
+#define LSFFT_ZU_WAVES 1
+#endif
+template <typename T, int NZ, int E, int P, int SCH>
+__global__ __launch_bounds__(P *(NZ / E), LSFFT_ZU_WAVES) void k_zpass_u(ZArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
   a.spec += sysb * a.bs.spec;
@@ -836,18 +843,27 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass_u(ZArgs<T> a) {
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
   const AxisVal<T> axx = axis_val(a.g, 0, i1), axy = axis_val(a.g, 1, valid ? i2 : 0);
+#if LSFFT_LDS_AXIS
+  __shared__ AxisVal<T> axl[NZ];
+  stage_axis(axl, a.g, 2);
+#else
   AxisVal<T> axz[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) axz[e] = axis_val(a.g, 2, t + TPC * e);
+#endif
   int buf = 0;
-  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);  // its barrier publishes axl too
 #pragma unroll
   for (int c = 0; c < 3; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, twl, 1, buf);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     cplx<T> f[3] = {v[0][e], v[1][e], v[2][e]};
+#if LSFFT_LDS_AXIS
+    const AxisVal<T> ax[3] = {axx, axy, axl[t + TPC * e]};
+#else
     const AxisVal<T> ax[3] = {axx, axy, axz[e]};
-    green_disp_point(a.g, ax, f);
+#endif
+    green_disp_point<SCH>(a.g, ax, f);
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c][e] = f[c];
   }

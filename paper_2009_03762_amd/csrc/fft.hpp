@@ -195,7 +195,11 @@ __device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds,
 #endif
 template <typename T, int NT>
 __device__ __forceinline__ const cplx<T> *stage_twiddles(cplx<T> (&dst)[NT], const cplx<T> *__restrict__ src) {
-  if constexpr (!LSFFT_LDS_TW) return src;
+  // the barrier also publishes whatever else the workgroup staged before it
+  if constexpr (!LSFFT_LDS_TW) {
+    __syncthreads();
+    return src;
+  }
   for (int i = threadIdx.x; i < NT; i += blockDim.x) dst[i] = src[i];
   __syncthreads();
   return dst;

@@ -212,6 +212,17 @@ template <typename T> __device__ __forceinline__ AxisVal<T> axis_val(const Green
   return AxisVal<T>{tabv(g, kp, axis, i), tabv(g, kq, axis, i)};
 }
 
+// The values of every index of `axis` staged in LDS by the workgroup; a
+// barrier of the caller publishes them.  Read back at each transform point
+// instead of being held in registers from the start of the kernel.
+#ifndef LSFFT_LDS_AXIS
+#define LSFFT_LDS_AXIS 1
+#endif
+template <typename T, int NA>
+__device__ __forceinline__ void stage_axis(AxisVal<T> (&dst)[NA], const GreenParams<T> &g, int axis) {
+  for (int i = threadIdx.x; i < NA; i += blockDim.x) dst[i] = axis_val(g, axis, i);
+}
+
 // Dispatch on the scheme for spectrum indices (i1, i2, i3), i1 in [0, n1/2],
 // with the per-axis table values ax[r] = axis_val(g, r, idx[r]).
 template <typename T>

@@ -493,11 +493,16 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
   const AxisVal<T> axx = axis_val(a.g, 0, i1), axy = axis_val(a.g, 1, valid ? i2 : 0);
+#if LSFFT_LDS_AXIS
+  __shared__ AxisVal<T> axl[NZ];
+  stage_axis(axl, a.g, 2);
+#else
   AxisVal<T> axz[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) axz[e] = axis_val(a.g, 2, t + TPC * e);
+#endif
   int buf = 0;
-  const cplx<T> *twl = stage_twiddles(twl_, a.tw);
+  const cplx<T> *twl = stage_twiddles(twl_, a.tw);  // its barrier publishes axl too
 #pragma unroll
   for (int c = 0; c < 6; ++c) fft_pencil<T, NZ, E, true>(v[c], t, lds + p, P, twl, 1, buf);
   if (a.forward_only) {
@@ -516,7 +521,11 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
     cplx<T> s[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) s[c] = v[c][e];
+#if LSFFT_LDS_AXIS
+    const AxisVal<T> ax[3] = {axx, axy, axl[t + TPC * e]};
+#else
     const AxisVal<T> ax[3] = {axx, axy, axz[e]};
+#endif
     const double r = green_point(a.g, i1, valid ? i2 : 0, t + TPC * e, ax, s);
     if (valid) res += wgt * r;
 #pragma unroll

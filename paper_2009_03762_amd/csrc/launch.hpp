@@ -103,17 +103,17 @@ hipError_t Launch<T>::stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid
   return s->scheme == LSFFT_FB ? stencil_s<lsfft::SCHEME_FB>(s, a, grid) : stencil_s<lsfft::SCHEME_AFB>(s, a, grid);
 }
 
-template <typename T>
-hipError_t Launch<T>::zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+template <typename T> template <int SCH>
+hipError_t Launch<T>::zpass_u_s(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
   switch (s->d.n3) {
 #define ZUCASE(Nv)                                                                                     \
 case Nv: {                                                                                           \
-  constexpr int E = ezu_of(Nv), P0 = pcols_zu<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                    \
+  constexpr int E = ezu_of<T>(Nv), P0 = pcols_zu<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                    \
   if (s->zv)                                                                                         \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0,    \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P1, SCH>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, \
                        s->stream, a);                                                                \
   else                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P0>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0,    \
+    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P0, SCH>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, \
                        s->stream, a);                                                                \
   return hipGetLastError();                                                                          \
 }
@@ -122,6 +122,11 @@ case Nv: {                                                                      
     default:
       return hipErrorInvalidValue;
   }
+}
+
+template <typename T>
+hipError_t Launch<T>::zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
+  return s->scheme == LSFFT_FB ? zpass_u_s<lsfft::SCHEME_FB>(s, a, grid) : zpass_u_s<lsfft::SCHEME_AFB>(s, a, grid);
 }
 
 }  // namespace lsfft_host

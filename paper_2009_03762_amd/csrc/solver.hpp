@@ -45,12 +45,18 @@ template <typename T> constexpr int pcols(int n, int E) { return pcols_seg<T>(n,
 template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(n, E, LSFFT_ZSEG * (int)sizeof(T) / 4); }
 // z-pass of the displacement form (three components)
 #ifndef LSFFT_ZUE
-#define LSFFT_ZUE LSFFT_ZE
+#define LSFFT_ZUE 8
 #endif
 #ifndef LSFFT_ZUSEG
 #define LSFFT_ZUSEG LSFFT_ZSEG
 #endif
-constexpr int ezu_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZUE ? n : LSFFT_ZUE); }
+#ifndef LSFFT_ZUE64
+#define LSFFT_ZUE64 LSFFT_ZUE
+#endif
+template <typename T> constexpr int ezu_of(int n) {
+  const int e = sizeof(T) == 8 ? LSFFT_ZUE64 : LSFFT_ZUE;
+  return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < e ? n : e);
+}
 template <typename T> constexpr int pcols_zu(int n, int E) {
   return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
 }
@@ -194,7 +200,7 @@ template <typename T> struct Tiles {
     switch (n) {
 #define ZUC(Nv) \
   case Nv:      \
-    return v ? palt<T>(Nv, ezu_of(Nv), pcols_zu<T>(Nv, ezu_of(Nv))) : pcols_zu<T>(Nv, ezu_of(Nv));
+    return v ? palt<T>(Nv, ezu_of<T>(Nv), pcols_zu<T>(Nv, ezu_of<T>(Nv))) : pcols_zu<T>(Nv, ezu_of<T>(Nv));
       LSFFT_YZ_LENGTHS(ZUC)
 #undef ZUC
       default:
@@ -223,6 +229,7 @@ template <typename T> struct Launch : Tiles<T> {
   static hipError_t uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid);
   template <int SCH> static hipError_t stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int grid);
   static hipError_t stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid);
+  template <int SCH> static hipError_t zpass_u_s(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
   static hipError_t zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
 };
 
