@@ -8,6 +8,14 @@
       S = (Ebar11 + <lambda/(lambda+2mu)> (Ebar22 + Ebar33)) / <1/(lambda+2mu)>.
   Every scheme's wavevector is parallel to e1 at the frequencies such a field
   excites, so this is also the exact discrete solution of each scheme.
+* `laminate_strain_eig`: the same with a layer eigenstrain E_*(x1) and the
+  law T = C [E - E_*] (Sec. 7): T e1 uniform, E22, E33, E23 = Ebar's;
+      E1j = E_*1j + S1j / (2 mu),  S1j = (Ebar1j - <E_*1j>) / <1/(2 mu)>  (j = 2, 3);
+      E11 = (S - lambda (Ebar22 + Ebar33) + lambda tr E_* + 2 mu E_*11) / (lambda + 2 mu),
+      S = (Ebar11 + <(lambda (Ebar22 + Ebar33) - lambda tr E_* - 2 mu E_*11) / (lambda + 2 mu)>)
+          / <1/(lambda + 2 mu)>.
+  The forcing excites the same frequencies, so it is again the exact discrete
+  solution of each scheme.
 * `voigt_mandel`, `reuss_mandel`: <C> and <C^{-1}>^{-1} in Mandel form.
 * `hs_lower_bulk`: Hashin-Shtrikman lower bound on the bulk modulus of a
   two-phase isotropic mixture.
@@ -30,6 +38,26 @@ def laminate_strain(lam1, mu1, Ebar):
     out[3] = E[3]
     out[4] = E[4] / (mu1 * np.mean(1.0 / mu1))
     out[5] = E[5] / (mu1 * np.mean(1.0 / mu1))
+    return out
+
+
+def laminate_strain_eig(lam1, mu1, Ebar, estar1):
+    """Exact strain (6, n1) of a laminate with layer moduli lam1(x1), mu1(x1)
+    and layer eigenstrain estar1 (6, n1), Voigt tensor components."""
+    E = np.asarray(Ebar, dtype=np.float64)
+    es = np.asarray(estar1, dtype=np.float64)
+    M = lam1 + 2.0 * mu1
+    tr = es[0] + es[1] + es[2]
+    g = lam1 * (E[1] + E[2]) - lam1 * tr - 2.0 * mu1 * es[0]
+    S = (E[0] + np.mean(g / M)) / np.mean(1.0 / M)
+    out = np.zeros((6,) + lam1.shape)
+    out[0] = (S - g) / M
+    out[1] = E[1]
+    out[2] = E[2]
+    out[3] = E[3]
+    for j in (4, 5):  # E13, E12: shear stress S1j = 2 mu (E1j - E_*1j) uniform
+        s1j = (E[j] - np.mean(es[j])) / np.mean(1.0 / (2.0 * mu1))
+        out[j] = es[j] + s1j / (2.0 * mu1)
     return out
 
 

@@ -21,7 +21,7 @@ import numpy as np
 
 from . import fdd, fourier
 from .green import from_voigt, sym_outer, to_voigt, green_inverse
-from .solve3d import _transform, _ebar_matrix, hooke
+from .solve3d import _transform, _ebar_matrix, eigenstrain_field, hooke
 
 
 def _apply_equilibrium(u, lam, mu, qa, qb, disc):
@@ -32,8 +32,9 @@ def _apply_equilibrium(u, lam, mu, qa, qb, disc):
     return np.einsum("...ij,...j->...i", That, qb)
 
 
-def dense_gfp(lam, mu, Ebar, scheme="AFB", disc="TD", h=(1.0, 1.0, 1.0)):
-    """Strain field (6, n3, n2, n1) of the discrete equilibrium, by dense LU."""
+def dense_gfp(lam, mu, Ebar, scheme="AFB", disc="TD", h=(1.0, 1.0, 1.0), eigenstrain=None):
+    """Strain field (6, n3, n2, n1) of the discrete equilibrium, by dense LU.
+    With an eigenstrain E_* the load is the stress C [Ebar - E_*]."""
     n3, n2, n1 = lam.shape
     qa, qb = fdd.scheme_pair(scheme, (n1, n2, n3), h)
     sing = fdd.singular_mask(qa, qb)
@@ -49,7 +50,9 @@ def dense_gfp(lam, mu, Ebar, scheme="AFB", disc="TD", h=(1.0, 1.0, 1.0)):
             A[:, col] = out[~sing].ravel()
             col += 1
     Eb = _ebar_matrix(Ebar)
-    T0 = hooke(lam, mu, np.broadcast_to(Eb, (n3, n2, n1, 3, 3)))
+    Es = eigenstrain_field(eigenstrain, lam.shape)
+    load = np.broadcast_to(Eb, (n3, n2, n1, 3, 3)) - (Es if Es is not None else 0.0)
+    T0 = hooke(lam, mu, load)
     rhs = -np.einsum("...ij,...j->...i", _transform(T0, True, disc), qb)[~sing].ravel()
     sol = np.linalg.solve(A, rhs)
     u = np.zeros((n3, n2, n1, 3), dtype=np.complex128)
@@ -58,18 +61,21 @@ def dense_gfp(lam, mu, Ebar, scheme="AFB", disc="TD", h=(1.0, 1.0, 1.0)):
     return np.moveaxis(to_voigt(E), -1, 0)
 
 
-def dense_dgo(lam, mu, Ebar, lam0, mu0, Gc, disc="PCD"):
-    """DGO fixed point (I - L) eps = Ebar by dense LU; Gc as in solve3d.solve_dgo."""
+def dense_dgo(lam, mu, Ebar, lam0, mu0, Gc, disc="PCD", eigenstrain=None):
+    """DGO fixed point (I - L) eps = Ebar by dense LU; Gc as in solve3d.solve_dgo.
+    With an eigenstrain E_*: (I - L) eps = Ebar - G(C E_*), G the Green map."""
     n3, n2, n1 = lam.shape
     N = n1 * n2 * n3
     dlam, dmu = lam - lam0, mu - mu0
 
-    def L(ev):  # ev: (6, n3, n2, n1) Voigt -> same
-        tau = hooke(dlam, dmu, from_voigt(np.moveaxis(ev, 0, -1)))
-        tv = np.moveaxis(to_voigt(tau), -1, 0)
+    def G(tv):  # polarisation (6, n3, n2, n1) Voigt -> strain, same layout
         th = fourier.pcd_forward(tv) if disc == "PCD" else fourier.td_forward(tv)
         eh = np.einsum("...IJ,J...->I...", Gc, th)
         return (fourier.pcd_inverse(eh) if disc == "PCD" else fourier.td_inverse(eh)).real
+
+    def L(ev):  # ev: (6, n3, n2, n1) Voigt -> same
+        tau = hooke(dlam, dmu, from_voigt(np.moveaxis(ev, 0, -1)))
+        return G(np.moveaxis(to_voigt(tau), -1, 0))
 
     A = np.zeros((6 * N, 6 * N))
     for j in range(6 * N):
@@ -77,6 +83,9 @@ def dense_dgo(lam, mu, Ebar, lam0, mu0, Gc, disc="PCD"):
         e[j] = 1.0
         A[:, j] = e - L(e.reshape(6, n3, n2, n1)).ravel()
     rhs = np.broadcast_to(np.asarray(Ebar, dtype=np.float64)[:, None], (6, N)).ravel()
+    Es = eigenstrain_field(eigenstrain, lam.shape)
+    if Es is not None:
+        rhs = rhs - G(np.moveaxis(to_voigt(hooke(lam, mu, Es)), -1, 0)).ravel()
     return np.linalg.solve(A, rhs).reshape(6, n3, n2, n1)
 
 

@@ -88,8 +88,34 @@ def _voigt_field(A):
     return np.ascontiguousarray(np.moveaxis(to_voigt(A), -1, 0))
 
 
+def eigenstrain_field(eigenstrain, shape):
+    """(n3, n2, n1, 3, 3) eigenstrain E_* from Voigt tensor components of shape
+    (6, n3, n2, n1), or None for none."""
+    if eigenstrain is None:
+        return None
+    e = np.asarray(eigenstrain, dtype=np.float64)
+    if e.shape != (6,) + tuple(shape):
+        raise ValueError("eigenstrain must have shape (6, n3, n2, n1)")
+    return from_voigt(np.moveaxis(e, 0, -1))
+
+
+def eigenstress(lam, mu, Es):
+    """C E_*: the stress the eigenstrain removes, T = C [E - E_*] (Sec. 7)."""
+    return hooke(lam, mu, Es)
+
+
+def eigen_norm(Eb, Es):
+    """Scale of the loading for the DGO stopping test: |Ebar|_F, or the RMS of
+    |E_*|_F over the voxels when Ebar = 0 (reading: the paper normalises by
+    Ebar, which a pure eigenstrain loading does not have)."""
+    nE = frob(Eb)
+    if nE == 0.0 and Es is not None:
+        nE = frob(Es) / np.sqrt(Es.shape[0] * Es.shape[1] * Es.shape[2])
+    return nE
+
+
 def solve_gfp(lam, mu, Ebar, lam0, mu0, scheme="AFB", tol=1e-8, maxit=1000,
-              disc="TD", h=(1.0, 1.0, 1.0), stop="equilibrium", callback=None):
+              disc="TD", h=(1.0, 1.0, 1.0), stop="equilibrium", callback=None, eigenstrain=None):
     """TD / PCD GFP+FDD fixed point (Sec. 5.2 / Sec. 5.4), displacement based.
 
     lam, mu: (n3, n2, n1) moduli sampled at the nodes (TD) or cell centres (PCD);
@@ -97,12 +123,18 @@ def solve_gfp(lam, mu, Ebar, lam0, mu0, scheme="AFB", tol=1e-8, maxit=1000,
     scheme: a key of fdd.SCHEMES.  Steps per iteration, in the paper's order:
         E~ = F^+ sym(u_check (x) q^a);  T = T^(0) + C E~;  T_check = F^- T;
         Delta u = G(q^a, q^b) T_check q^b;  u_check += Delta u.
+    eigenstrain: optional E_* (6, n3, n2, n1), Voigt tensor components; the
+    constitutive law becomes T = C [E - E_*], i.e. T^(0) = C [Ebar - E_*]
+    (Sec. 7).  The returned eps is the total strain E.
     """
     n3, n2, n1 = lam.shape
     qa, qb = fdd.scheme_pair(scheme, (n1, n2, n3), h)
     singular = fdd.singular_mask(qa, qb)
     Eb = _ebar_matrix(Ebar)
+    Es = eigenstrain_field(eigenstrain, lam.shape)
     T0 = hooke(lam, mu, np.broadcast_to(Eb, (n3, n2, n1, 3, 3)))
+    if Es is not None:
+        T0 = T0 - eigenstress(lam, mu, Es)
     u = np.zeros((n3, n2, n1, 3), dtype=np.complex128)
     du_prev = np.zeros_like(u)
     paper_done = False
@@ -138,25 +170,29 @@ def solve_gfp(lam, mu, Ebar, lam0, mu0, scheme="AFB", tol=1e-8, maxit=1000,
     return Result(_voigt_field(eps), _voigt_field(T), sig_mean, k, history[-1], status, history)
 
 
-def solve_dgo(lam, mu, Ebar, lam0, mu0, Gc, tol=1e-8, maxit=1000, disc="PCD"):
+def solve_dgo(lam, mu, Ebar, lam0, mu0, Gc, tol=1e-8, maxit=1000, disc="PCD", eigenstrain=None):
     """DGO fixed point of Sec. 5.4 in polarisation form.
 
     Gc: (n3, n2, n1, 6, 6) discrete Green operator (green.dgo_voigt), with the
     paper's sign (Gamma_H = -sym[G A k (x) k]).  Per iteration:
         tau = (C - C_H) eps;  eps_new = Ebar + F^{c+}[ Gc F^{c-} tau ].
+    eigenstrain: optional E_*; the polarisation becomes
+        tau = T - C_H eps = (C - C_H) eps - C E_*   (T = C [E - E_*], Sec. 7).
     """
     n3, n2, n1 = lam.shape
     N = n1 * n2 * n3
     Eb = _ebar_matrix(Ebar)
+    Es = eigenstrain_field(eigenstrain, lam.shape)
     eps = np.broadcast_to(Eb, (n3, n2, n1, 3, 3)).copy()
     dlam, dmu = lam - lam0, mu - mu0
-    nE = frob(Eb)
+    tau_star = eigenstress(lam, mu, Es) if Es is not None else 0.0
+    nE = eigen_norm(Eb, Es)
     history = []
     r = float("inf")
     k = 0
     status = ENOTCONV
     while k < maxit:
-        tau = hooke(dlam, dmu, eps)
+        tau = hooke(dlam, dmu, eps) - tau_star
         tv = np.moveaxis(to_voigt(tau), -1, 0)
         th = fourier.pcd_forward(tv) if disc == "PCD" else fourier.td_forward(tv)
         eh = np.einsum("...IJ,J...->I...", Gc, th)
@@ -172,7 +208,7 @@ def solve_dgo(lam, mu, Ebar, lam0, mu0, Gc, tol=1e-8, maxit=1000, disc="PCD"):
         if not np.isfinite(r) or r > DIVERGENCE_FACTOR * max(history[0], 1e-300):
             status = EDIVERGED
             break
-    T = hooke(lam, mu, eps)
+    T = hooke(lam, mu, eps) - tau_star
     sig_mean = to_voigt(T.mean(axis=(0, 1, 2)))
     return Result(_voigt_field(eps), _voigt_field(T), sig_mean, k, r, status, history)
 
