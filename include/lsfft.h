@@ -117,6 +117,15 @@ typedef struct {
                               slowest modes of the iteration remove.  0 = off;
                               < 0 is EINVAL.  Costs the memory of an F64
                               solver.                                          */
+  const double *eigenstrain; /* optional eigenstrain E_* (Sec. 7): 6N values,
+                              HOST memory, [6][n3][n2][n1] Voigt tensor
+                              components (eps_23, not 2 eps_23), copied at
+                              create; NULL = none.  The law becomes
+                              T = C [E - E_*]: the iteration starts from
+                              T^(0) = C [Ebar - E_*], eps outputs are the
+                              total strain E and sig outputs C [E - E_*].
+                              In a batch each system has its own (NULL
+                              systems have none).  EINVAL if not finite.    */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda
@@ -147,7 +156,10 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
  * (LSFFT_ENOTCONV).  r_k is the relative equilibrium norm
  * sqrt(sum_xi |sigma_hat(xi) q^b(xi)|^2) / |sigma_hat(0)|_F evaluated before
  * the k-th update (BASIC, FB, AFB), or |eps^k - eps^{k-1}| / (sqrt(N)|Ebar|_F)
- * (DGO).  Outputs: eps and sig (6N doubles, HOST memory, field layout; either
+ * (DGO; with an eigenstrain and Ebar = 0 the RMS over the voxels of
+ * |E_*|_F replaces |Ebar|_F).  With an eigenstrain, r_k is 0 when the whole
+ * stress field vanishes (free expansion), and undefined when only its mean
+ * does (reported as +inf: the solve returns LSFFT_EDIVERGED).  Outputs: eps and sig (6N doubles, HOST memory, field layout; either
  * may be NULL), sig_mean[6] = <sigma> (may be NULL), *iters = k (number of
  * updates applied), *residual = r_k (either may be NULL).  tol >= 0,
  * maxit >= 0.  tol = 0 runs exactly maxit iterations. */
@@ -222,7 +234,8 @@ lsfft_status lsfft_autotune(lsfft_solver s, int32_t iterations, lsfft_schedule *
  * *count receives iters + 1.  EINVAL if no solve has run. */
 lsfft_status lsfft_residual_history(lsfft_solver s, double *out, int32_t cap, int32_t *count);
 
-/* Operator: sig_hat = DFT(C : eps) for a DEVICE strain field eps_dev (6N,
+/* Operator: sig_hat = DFT(C : eps) (with an eigenstrain: DFT(C : [eps -
+ * E_*])) for a DEVICE strain field eps_dev (6N,
  * solver precision, field layout) into DEVICE sig_hat_dev (half-spectrum
  * layout, 6*n3*n2*(n1/2+1) complex).  For DGO the polarisation
  * (C - C_H) : eps is transformed instead.  Sec. 5.2, the steps
@@ -250,6 +263,8 @@ lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev
  *                   E = mu (3 lambda + 2 mu) / (lambda + mu) of voxel x).
  * Outputs: DEVICE arrays of N values of the solver's precision; any may be
  * NULL.  Computed in FP64 with the moduli of system 0 of a batch handle.
+ * J is a property of C_eff and needs no eigenstrain: on a handle with one,
+ * pass strains of solves whose eigenstrain is zero (another handle).
  * The DGO iteration is not self-adjoint: its sensitivities are not given by
  * this entry point.  EINVAL on NULL handle or strain fields. */
 lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, const void *eps_b_dev,

@@ -192,6 +192,7 @@ template <typename T> struct SArgs {
   T ih[3];             // 1 / h_r for the divergence
   double *partial;     // [system][gridDim.x][8]: 6 stress sums, sum |f|^2
   const State *st;     // [system]
+  const T *fstar;      // div sigma_* of the eigenstress at the nodes [system][3][N], or null
   int Z;               // planes per workgroup
   int xcd;             // 1: XCD-aware order of the tiles
   int zero_u;          // u is identically zero (first pass): the LDS variant skips its loads
@@ -205,6 +206,7 @@ template <typename T> __device__ __forceinline__ void stencil_member(SArgs<T> &a
   a.spec += b * a.bs.spec;
   a.nyq += b * a.bs.nyq;
   if (a.partial) a.partial += b * a.bs.part;
+  if (a.fstar) a.fstar += b * 3 * a.bs.field;
 }
 
 template <int SCHEME> struct Stencil;
@@ -447,6 +449,8 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
             }
             acc += Stencil<SCHEME>::div(s, j, ih);
           }
+          // eigenstrain: the force of the eigenstress, T = C [E - E_*]
+          if (a.fstar) acc -= a.fstar[i * N + ((long long)(z % n3) * n2 + y0 + m) * N1 + x];
           f3[i] = acc;
           F[(m * 3 + i) * N1 + x] = acc;
         }
@@ -739,6 +743,12 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
       }
 #pragma unroll
       for (int m = 0; m < T2; ++m) {
+        if (a.fstar) {  // eigenstrain: the force of the eigenstress, T = C [E - E_*]
+          const int yg = (yg0 + m) % n2;  // groups past n2 work on wrapped rows
+          const long long gi = ((long long)(z % n3) * n2 + yg) * N1 + x;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) f[m][i] -= a.fstar[i * N + gi];
+        }
 #pragma unroll
         for (int i = 0; i < 3; ++i) F[((g * T2 + m) * 3 + i) * N1 + x] = f[m][i];
         if (gvalid) sums[6] += (double)(f[m][0] * f[m][0] + f[m][1] * f[m][1] + f[m][2] * f[m][2]);

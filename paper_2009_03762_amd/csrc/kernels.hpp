@@ -74,6 +74,7 @@ template <typename T> struct XArgs {
   Strides bs;
   double *partial;    // [system][gridDim.x][8]
   const State *st;    // [system]
+  const T *sstar;     // eigenstress C E_* [system][6][N] (T = C [E - E_*]), or null
   int mode;
   int polarisation;   // transform (C - C0) : eps instead of C : eps
 };
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   a.spec += sysb * a.bs.spec;
   a.nyq += sysb * a.bs.nyq;
   if (a.partial) a.partial += sysb * a.bs.part;
+  if (a.sstar) a.sstar += sysb * 6 * a.bs.field;
   // the system's constants in registers
   T Ebl[6];
 #pragma unroll
@@ -331,6 +333,13 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
       ev[c][0] = n0;
       ev[c][1] = n1v;
     }
+    // eigenstress of the two voxels (T = C [E - E_*]); zero without eigenstrain
+    T ss[6][2];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      ss[c][0] = ss[c][1] = T(0);
+      if (a.sstar && valid) ld2(a.sstar + c * N + idx, ss[c][0], ss[c][1]);
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const T tr = ev[0][h] + ev[1][h] + ev[2][h];
@@ -338,9 +347,9 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
       const T lp = l - lam0, mp2 = m2 - T(2) * mu0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const T sg = (c < 3 ? l * tr : T(0)) + m2 * ev[c][h];
+        const T sg = (c < 3 ? l * tr : T(0)) + m2 * ev[c][h] - ss[c][h];
         if (valid) sums[c] += (double)sg;
-        const T fin = a.polarisation ? (c < 3 ? lp * tr : T(0)) + mp2 * ev[c][h] : sg;
+        const T fin = a.polarisation ? (c < 3 ? lp * tr : T(0)) + mp2 * ev[c][h] - ss[c][h] : sg;
         if (h == 0) w[c][e].x = fin; else w[c][e].y = fin;
       }
     }
@@ -584,17 +593,17 @@ __global__ void k_stiffness_gradient(const T *__restrict__ ea, const T *__restri
 
 template <typename T>
 __global__ void k_hooke_out(const T *__restrict__ eps, const T *__restrict__ lam, const T *__restrict__ mu,
-                            T *__restrict__ sig, long long N) {
+                            const T *__restrict__ sstar, T *__restrict__ sig, long long N) {
+  // sstar: the eigenstress C E_* [6][N], or null
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     const T e0 = eps[i], e1 = eps[N + i], e2 = eps[2 * N + i];
     const T l = lam[i], m2 = T(2) * mu[i];
     const T tr = e0 + e1 + e2;
-    sig[i] = l * tr + m2 * e0;
-    sig[N + i] = l * tr + m2 * e1;
-    sig[2 * N + i] = l * tr + m2 * e2;
-    sig[3 * N + i] = m2 * eps[3 * N + i];
-    sig[4 * N + i] = m2 * eps[4 * N + i];
-    sig[5 * N + i] = m2 * eps[5 * N + i];
+    T s6[6] = {l * tr + m2 * e0, l * tr + m2 * e1, l * tr + m2 * e2,
+               m2 * eps[3 * N + i], m2 * eps[4 * N + i], m2 * eps[5 * N + i]};
+    if (sstar)
+      for (int c = 0; c < 6; ++c) s6[c] -= sstar[c * N + i];
+    for (int c = 0; c < 6; ++c) sig[c * N + i] = s6[c];
   }
 }
 

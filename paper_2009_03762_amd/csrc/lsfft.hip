@@ -166,6 +166,7 @@ template <typename T> lsfft::XArgs<T> xargs(lsfft_solver s, int mode, const void
   a.bs.part = s->spx;
   a.partial = with_partial ? s->px : nullptr;
   a.st = with_partial ? s->st : nullptr;
+  a.sstar = (const T *)s->sstar;
   a.mode = mode;
   a.polarisation = (s->scheme == LSFFT_DGO) ? 1 : 0;
   return a;
@@ -227,6 +228,7 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   }
   a.partial = s->px;
   a.st = s->st;
+  a.fstar = (const T *)s->fstar;
   a.Z = s->sZ;
   a.xcd = s->xcd & 1;
   a.zero_u = zero_u;
@@ -278,6 +280,8 @@ template <typename T> lsfft_status upload_members(lsfft_solver s, const double *
       nrm += (c < 3 ? 1.0 : 2.0) * m[b].Eb[c] * m[b].Eb[c];
     }
     en[b] = std::sqrt(nrm);
+    // pure eigenstrain loading: scale the DGO stopping test by the RMS of |E_*|_F
+    if (en[b] == 0.0 && s->eig) en[b] = s->estar_rms[b];
     for (int i = 0; i < 3; ++i)
       for (int r = 0; r < 3; ++r) m[b].hE[i][r] = s->h[r] * m[b].Eb[vo[i][r]];
     const double l0 = s->lam0v[b], m0 = s->mu0v[b];
@@ -388,6 +392,7 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   ra.hist = s->hist;
   ra.hcap = s->hist_cap;
   ra.ebar_norms = s->enorm;
+  ra.smean = (disp && s->eig) ? s->smean : nullptr;  // the stencil sums C E, not C [E - E_*]
   ra.maxit = maxit;
   ra.tol = s->tuning ? -1.0 : tol;
   ra.dgo = dgo ? 1 : 0;
@@ -570,8 +575,9 @@ template <typename T> lsfft_status finish_outputs(lsfft_solver s, void *eps_out,
     const int blocks = (int)std::min<long long>((s->d.N + 255) / 256, 65536);
     for (int b = 0; b < s->B; ++b) {
       const long long off = (long long)b * s->d.N;
+      const T *ss = s->sstar ? (const T *)s->sstar + 6 * off : nullptr;
       hipLaunchKernelGGL(lsfft::k_hooke_out<T>, dim3(blocks), dim3(256), 0, s->stream, (const T *)s->eps + 6 * off,
-                         (const T *)s->lam + off, (const T *)s->mu + off, dst + 6 * off, s->d.N);
+                         (const T *)s->lam + off, (const T *)s->mu + off, ss, dst + 6 * off, s->d.N);
       LSFFT_CHECK(hipGetLastError());
     }
     if (host) {
@@ -699,7 +705,8 @@ void release(lsfft_solver s) {
     s->hist = nullptr;
   }
   void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
-                  s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm};
+                  s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm,
+                  s->sstar, s->fstar, s->smean};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -735,6 +742,94 @@ template <typename T> lsfft_status green_impl(lsfft_solver s, const void *in, vo
   double tot = 0.0;
   for (double v : part) tot += v;
   if (res_sq) *res_sq = tot;
+  return LSFFT_OK;
+}
+
+// Eigenstrain of every system (T = C [E - E_*], Sec. 7), all in FP64 here:
+// the eigenstress C E_* per voxel, which the strain form's Hooke step and
+// the stress output subtract; its mean, which the displacement form takes
+// out of its stress sums; and, in the displacement form, the force
+// div^b (C E_*) at the nodes (the same cell-to-node stencil as the stencil
+// kernel), which that kernel subtracts from div^b (C E).
+template <typename T> lsfft_status setup_eigenstrain(lsfft_solver s, const lsfft_config *cfgs) {
+  bool any = false;
+  for (int m = 0; m < s->B; ++m) any = any || cfgs[m].eigenstrain != nullptr;
+  if (!any) return LSFFT_OK;
+  s->eig = 1;
+  const long long N = s->d.N;
+  const int n1 = s->n[0], n2 = s->n[1], n3 = s->n[2];
+  const size_t B = (size_t)s->B;
+  LSFFT_CHECK(hipMalloc(&s->sstar, B * 6 * (size_t)N * sizeof(T)));
+  LSFFT_CHECK(hipMalloc(&s->smean, B * 6 * sizeof(double)));
+  if (s->disp) LSFFT_CHECK(hipMalloc(&s->fstar, B * 3 * (size_t)N * sizeof(T)));
+  std::vector<double> sd(6 * (size_t)N), fd(s->disp ? 3 * (size_t)N : 0), mean(6 * B, 0.0);
+  std::vector<T> tmp(6 * (size_t)N);
+  s->estar_rms.assign(B, 0.0);
+  static const int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  for (size_t m = 0; m < B; ++m) {
+    const double *es = cfgs[m].eigenstrain;
+    const double *l = cfgs[m].lambda, *mu = cfgs[m].mu;
+    double ss = 0.0;
+    for (long long i = 0; i < N; ++i) {
+      double e[6];
+      for (int c = 0; c < 6; ++c) e[c] = es ? es[c * N + i] : 0.0;
+      const double tr = e[0] + e[1] + e[2];
+      for (int c = 0; c < 6; ++c) {
+        sd[c * N + i] = (c < 3 ? l[i] * tr : 0.0) + 2.0 * mu[i] * e[c];
+        mean[6 * m + c] += sd[c * N + i];
+        ss += (c < 3 ? 1.0 : 2.0) * e[c] * e[c];
+      }
+    }
+    for (int c = 0; c < 6; ++c) mean[6 * m + c] /= (double)N;
+    s->estar_rms[m] = std::sqrt(ss / (double)N);
+    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (T)sd[i];
+    LSFFT_CHECK(hipMemcpy((T *)s->sstar + m * 6 * N, tmp.data(), 6 * N * sizeof(T), hipMemcpyHostToDevice));
+    if (!s->disp) continue;
+    // f_i = sum_j d_j sigma_ij at node (x, y, z), the upper corner of cells
+    // (x - a, y - b, z - d), a, b, d in {0, 1}.  AFB: each d_j averages the
+    // four cell differences across the node; with z-pair sums P and z
+    // differences D of the cell stress these are 2 x 2 sums over (x, y).
+    const double q[3] = {0.25 / s->h[0], 0.25 / s->h[1], 0.25 / s->h[2]};
+    const double ih[3] = {1.0 / s->h[0], 1.0 / s->h[1], 1.0 / s->h[2]};
+    for (int z = 0; z < n3; ++z) {
+      const int zm = (z + n3 - 1) % n3;
+      for (int y = 0; y < n2; ++y) {
+        const int ym = (y + n2 - 1) % n2;
+        const long long r00 = ((long long)z * n2 + y) * n1, r01 = ((long long)z * n2 + ym) * n1;
+        const long long r10 = ((long long)zm * n2 + y) * n1, r11 = ((long long)zm * n2 + ym) * n1;
+        for (int x = 0; x < n1; ++x) {
+          const int xm = x ? x - 1 : n1 - 1;
+          double f[3] = {0.0, 0.0, 0.0};
+          for (int c = 0; c < 6; ++c) {
+            const double *sc = sd.data() + c * N;
+            double dd[3];
+            if (s->scheme == LSFFT_AFB) {
+              // [a][b]: cell column x - a, cell line y - b
+              const double P[2][2] = {{sc[r00 + x] + sc[r10 + x], sc[r01 + x] + sc[r11 + x]},
+                                      {sc[r00 + xm] + sc[r10 + xm], sc[r01 + xm] + sc[r11 + xm]}};
+              const double D[2][2] = {{sc[r00 + x] - sc[r10 + x], sc[r01 + x] - sc[r11 + x]},
+                                      {sc[r00 + xm] - sc[r10 + xm], sc[r01 + xm] - sc[r11 + xm]}};
+              dd[0] = q[0] * ((P[0][0] + P[0][1]) - (P[1][0] + P[1][1]));
+              dd[1] = q[1] * ((P[0][0] + P[1][0]) - (P[0][1] + P[1][1]));
+              dd[2] = q[2] * ((D[0][0] + D[0][1]) + (D[1][0] + D[1][1]));
+            } else {  // FB: backward differences of the cell stress
+              const double own = sc[r00 + x];
+              dd[0] = ih[0] * (own - sc[r00 + xm]);
+              dd[1] = ih[1] * (own - sc[r01 + x]);
+              dd[2] = ih[2] * (own - sc[r10 + x]);
+            }
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j)
+                if (vo[i][j] == c) f[i] += dd[j];
+          }
+          for (int i = 0; i < 3; ++i) fd[i * N + r00 + x] = f[i];
+        }
+      }
+    }
+    for (size_t i = 0; i < fd.size(); ++i) tmp[i] = (T)fd[i];
+    LSFFT_CHECK(hipMemcpy((T *)s->fstar + m * 3 * N, tmp.data(), 3 * N * sizeof(T), hipMemcpyHostToDevice));
+  }
+  LSFFT_CHECK(hipMemcpy(s->smean, mean.data(), mean.size() * sizeof(double), hipMemcpyHostToDevice));
   return LSFFT_OK;
 }
 
@@ -930,6 +1025,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     if (cfg->scheme == LSFFT_DGO && (c->lambda0 != cfg->lambda0 || c->mu0 != cfg->mu0)) return LSFFT_EINVAL;
     for (long long i = 0; i < N; ++i)
       if (!ok_moduli(c->lambda[i], c->mu[i])) return LSFFT_EINVAL;
+    if (c->eigenstrain && !finite_all(c->eigenstrain, 6 * N)) return LSFFT_EINVAL;
   }
 
   lsfft_solver s = new lsfft_solver_s();
@@ -1021,6 +1117,8 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   if (hipMalloc(&s->pstage, sizeof(double) * B * 8 * lsfft::RSTAGE) != hipSuccess) return fail(LSFFT_ENOMEM);
   s->ngb = 1024;
   if (hipMalloc(&s->pg, sizeof(double) * (size_t)s->ngb) != hipSuccess) return fail(LSFFT_ENOMEM);
+  st = (s->prec == LSFFT_F32) ? setup_eigenstrain<float>(s, cfgs) : setup_eigenstrain<double>(s, cfgs);
+  if (st != LSFFT_OK) return fail(st);
   // reference media of the systems for the operator entry points and the DGO
   st = (s->prec == LSFFT_F32) ? upload_members<float>(s, nullptr) : upload_members<double>(s, nullptr);
   if (st != LSFFT_OK) return fail(st);

@@ -22,7 +22,8 @@ struct ReduceArgs {
   State *st;          // [system]
   double *hist;       // [system][hcap]
   long long hcap;
-  const double *ebar_norms;  // [system] |Ebar|_F
+  const double *ebar_norms;  // [system] |Ebar|_F (RMS |E_*|_F for Ebar = 0 under eigenstrain)
+  const double *smean;       // [system][6] mean eigenstress <C E_*> left out of the x-side sums, or null
   int maxit;
   double tol;
   int dgo;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   double mean[6];
   double sn = 0.0;
   for (int c = 0; c < 6; ++c) {
-    mean[c] = vals[c] / a.N;
+    mean[c] = vals[c] / a.N - (a.smean ? a.smean[6 * sysb + c] : 0.0);
     sn += (c < 3 ? 1.0 : 2.0) * mean[c] * mean[c];
   }
   double r;

@@ -163,6 +163,13 @@ struct lsfft_solver_s {
   int yv = 0, zv = 0, xcd = 7;
   // Set while the schedule tuner times iterations: no stopping test.
   int tuning = 0;
+  // Eigenstrain (T = C [E - E_*]) of the systems, when any has one: the
+  // eigenstress C E_* [B][6][N] (T), its mean [B][6] (FP64) and, in the
+  // displacement form, its force div^b (C E_*) at the nodes [B][3][N] (T).
+  int eig = 0;
+  void *sstar = nullptr, *fstar = nullptr;
+  double *smean = nullptr;
+  std::vector<double> estar_rms;  // RMS of |E_*|_F of each system
 };
 
 namespace lsfft_host {

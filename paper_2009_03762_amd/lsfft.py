@@ -41,6 +41,7 @@ class Config(C.Structure):
         ("stream", C.c_void_p),
         ("form", C.c_int32),
         ("f64_warmup", C.c_int32),
+        ("eigenstrain", C.POINTER(C.c_double)),
     ]
 
 
@@ -136,7 +137,18 @@ def _stream_handle(stream):
 FORMS = {"auto": 0, "strain": 1, "displacement": 2}
 
 
-def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form, f64_warmup):
+def _eigenstrain(es, shape):
+    """Host float64 copy (6, n3, n2, n1) of an eigenstrain, or None."""
+    if es is None:
+        return None
+    es = np.ascontiguousarray(es, dtype=np.float64)
+    if es.shape != (6,) + tuple(shape):
+        raise ValueError(f"eigenstrain must have shape (6,) + {tuple(shape)}")
+    return es
+
+
+def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form, f64_warmup,
+            eigenstrain=None):
     if lam.ndim != 3 or lam.shape != mu.shape:
         raise ValueError("lam and mu must be 3D arrays of equal shape (n3, n2, n1)")
     n3, n2, n1 = lam.shape
@@ -155,16 +167,19 @@ def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight
     cfg.stream = _stream_handle(stream)
     cfg.form = FORMS[form] if isinstance(form, str) else int(form)
     cfg.f64_warmup = int(f64_warmup)
+    cfg.eigenstrain = _dptr(eigenstrain)  # the caller keeps the array alive through the call
     return cfg
 
 
 def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
-    """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1)."""
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, eigenstrain=None):
+    """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1);
+    eigenstrain: optional (6, n3, n2, n1) Voigt tensor components."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
+    es = _eigenstrain(eigenstrain, lam.shape)
     cfg = _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                  f64_warmup)
+                  f64_warmup, es)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:
@@ -174,16 +189,19 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
 
 def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0), dgo_images=4,
                  dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
-    """lsfft_create_batch.  systems: sequence of (lam, mu, lambda0, mu0) with
-    float64 host arrays of one shape (n3, n2, n1)."""
+    """lsfft_create_batch.  systems: sequence of (lam, mu, lambda0, mu0) or
+    (lam, mu, lambda0, mu0, eigenstrain) with float64 host arrays of one shape
+    (n3, n2, n1) (eigenstrain: (6, n3, n2, n1) or None)."""
     arrays = []
     cfgs = (Config * len(systems))()
-    for m, (lam, mu, l0, m0) in enumerate(systems):
+    for m, sysm in enumerate(systems):
+        lam, mu, l0, m0 = sysm[:4]
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         mu = np.ascontiguousarray(mu, dtype=np.float64)
-        arrays.append((lam, mu))   # keep the buffers alive through the call
+        es = _eigenstrain(sysm[4] if len(sysm) > 4 else None, lam.shape)
+        arrays.append((lam, mu, es))   # keep the buffers alive through the call
         cfgs[m] = _config(lam, mu, l0, m0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                          f64_warmup)
+                          f64_warmup, es)
     handle = C.c_void_p()
     st = _lib.lsfft_create_batch(cfgs, len(systems), C.byref(handle))
     if st != OK:

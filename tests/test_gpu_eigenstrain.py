@@ -1,0 +1,225 @@
+"""Eigenstrain loading (T = C [E - E_*], Sec. 7) on the GPU, through the C ABI,
+against the oracle and closed forms: every scheme and form at fixed
+iterations, converged FP64 solves, the DGO (including a pure eigenstrain
+load), the laminate closed form at 128^3, batches with and without
+eigenstrain, the FP64 warm start and the stress operator."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bounds, green, solve3d  # noqa: E402
+from paper_2009_03762_amd import inputs  # noqa: E402
+
+from oracle_ref import half_spectrum, hooke_voigt, rel  # noqa: E402
+
+NAMES = {"basic": "basic", "fb": "FB", "afb": "AFB", "cd": "CD", "acd": "ACD"}
+EB = np.array([1e-3, 2e-4, -1e-4, 3e-4, -2e-4, 5e-4])
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _dt(prec):
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _eig(lam, seed, scale=1e-3):
+    return scale * np.random.default_rng(seed).standard_normal((6,) + lam.shape)
+
+
+CASES = [("afb", "displacement", (16, 16, 16)), ("afb", "displacement", (24, 8, 12)),
+         ("fb", "displacement", (16, 12, 8)), ("afb", "strain", (16, 16, 16)), ("fb", "strain", (12, 16, 8)),
+         ("basic", "auto", (24, 8, 12)), ("cd", "auto", (16, 12, 8)), ("acd", "auto", (16, 16, 16))]
+
+
+@pytest.mark.parametrize("scheme,form,shape", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fixed_iterations_match_oracle(L, scheme, form, shape, prec):
+    print(f"\n[eig fixed] {scheme} {form} {shape} {prec}", flush=True)
+    K = 12
+    lam, mu = inputs.cubic_inclusion(shape, tuple(v // 2 for v in shape), 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    es = _eig(lam, 3)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec, form=form, eigenstrain=es)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K, eigenstrain=es)
+    s.close()
+    assert out["iters"] == K and out["status"] == L.ENOTCONV
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert rel(out["eps"], ref.eps) < tol
+    assert rel(out["sig"], ref.sig) < tol
+    assert rel(out["sig_mean"], ref.sig_mean) < tol
+    assert abs(out["residual"] - ref.residual) / ref.residual < (1e-9 if prec == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("scheme,form", [("afb", "displacement"), ("fb", "displacement"), ("afb", "strain"),
+                                         ("basic", "auto")])
+def test_converged_matches_oracle_fp64(L, scheme, form):
+    print(f"\n[eig converged] {scheme} {form}", flush=True)
+    lam, mu = inputs.cubic_inclusion(16, 8, 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    es = _eig(lam, 4)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f64", form=form, eigenstrain=es)
+    out = s.solve(EB, tol=1e-8, maxit=3000)
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=1e-8, maxit=3000, eigenstrain=es)
+    s.close()
+    assert out["status"] == L.OK and ref.status == solve3d.OK
+    assert out["iters"] == ref.iters
+    assert rel(out["eps"], ref.eps) < 1e-11
+    assert rel(out["sig_mean"], ref.sig_mean) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("eb", ["nonzero", "zero"])
+def test_dgo_matches_oracle(L, prec, eb):
+    shape = (8, 8, 8)
+    print(f"\n[eig dgo] {prec} Ebar {eb}", flush=True)
+    K, M, p = 10, 2, 2
+    lam, mu = inputs.cubic_inclusion(8, 4, 1.0, 5.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 5.0)
+    es = _eig(lam, 5)
+    Eb = EB if eb == "nonzero" else np.zeros(6)
+    s = L.Solver(lam, mu, l0, m0, scheme="dgo", disc="pcd", prec=prec, dgo_images=M, dgo_weight_power=p,
+                 eigenstrain=es)
+    out = s.solve(Eb, tol=0.0, maxit=K)
+    s.close()
+    Gc = green.dgo_voigt(shape, l0, m0, M, p)
+    ref = solve3d.solve_dgo(lam, mu, Eb, l0, m0, Gc, tol=0.0, maxit=K, eigenstrain=es)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < tol
+    assert rel(out["sig"], ref.sig) < tol
+    assert abs(out["residual"] - ref.residual) / ref.residual < (1e-9 if prec == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("scheme,form", [("afb", "displacement"), ("fb", "displacement"), ("afb", "strain"),
+                                         ("basic", "auto")])
+def test_free_expansion_stays_stress_free(L, scheme, form):
+    """E_* = Ebar in a heterogeneous cell: the stress stays at rounding level.
+    (The residual is then a ratio of rounding errors, so the iteration works
+    on a rounding-level force; the Green step amplifies its low frequencies,
+    hence the bound of 1e-10 of the eigenstress, against O(1) for a sign
+    error.)"""
+    print(f"\n[eig free expansion] {scheme} {form}", flush=True)
+    lam, mu = inputs.random_moduli((16, 12, 8), seed=4, E_range=(1.0, 30.0))
+    es = np.broadcast_to(EB[:, None, None, None], (6,) + lam.shape).copy()
+    s = L.Solver(lam, mu, 2.0, 1.0, scheme=scheme, prec="f64", form=form, eigenstrain=es)
+    out = s.solve(EB, tol=0.0, maxit=5)
+    s.close()
+    scale = np.abs(hooke_voigt(lam, mu, es)).max()
+    assert np.abs(out["sig"]).max() < 1e-10 * scale
+    assert rel(out["eps"], es) < 1e-12
+
+
+def test_homogeneous_uniform_eigenstrain(L):
+    lam = np.full((8, 16, 16), 2.0)
+    mu = np.full((8, 16, 16), 1.5)
+    E0 = np.array([3e-4, -1e-4, 2e-4, 0.0, 1e-4, -2e-4])
+    es = np.broadcast_to(E0[:, None, None, None], (6,) + lam.shape).copy()
+    d = EB - E0
+    tr = d[0] + d[1] + d[2]
+    want = np.array([2.0 * tr + 3.0 * d[0], 2.0 * tr + 3.0 * d[1], 2.0 * tr + 3.0 * d[2],
+                     3.0 * d[3], 3.0 * d[4], 3.0 * d[5]])
+    for scheme, form in (("afb", "displacement"), ("fb", "displacement"), ("afb", "strain"), ("basic", "auto"),
+                         ("cd", "auto"), ("acd", "auto")):
+        print(f"\n[eig homogeneous] {scheme} {form}", flush=True)
+        s = L.Solver(lam, mu, 1.0, 1.0, scheme=scheme, prec="f64", form=form, eigenstrain=es)
+        out = s.solve(EB, tol=1e-12, maxit=10)
+        s.close()
+        assert out["status"] == L.OK and out["iters"] == 0
+        assert np.allclose(out["eps"], EB[:, None, None, None], rtol=0, atol=1e-17)
+        assert np.allclose(out["sig_mean"], want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("prec,form", [("f64", "displacement"), ("f32", "displacement"), ("f64", "strain")])
+def test_laminate_128_closed_form(L, prec, form):
+    """Layers along x1 with layer moduli and layer eigenstrains, 128^3: the
+    exact solution of every scheme is the laminate closed form."""
+    n = 128
+    print(f"\n[eig laminate128] {prec} {form}", flush=True)
+    lam1, mu1 = inputs.laminate((n, 1, 1), seed=9, E_range=(1.0, 10.0))
+    lam = np.ascontiguousarray(np.broadcast_to(lam1[0, 0], (n, n, n)))
+    mu = np.ascontiguousarray(np.broadcast_to(mu1[0, 0], (n, n, n)))
+    e1 = 1e-3 * np.random.default_rng(8).standard_normal((6, n))
+    es = np.ascontiguousarray(np.broadcast_to(e1[:, None, None, :], (6, n, n, n)))
+    l0, m0 = 0.5 * (lam1.min() + lam1.max()), 0.5 * (mu1.min() + mu1.max())
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec=prec, form=form, eigenstrain=es)
+    dt = _dt(prec)
+    eps = torch.zeros((6, n, n, n), dtype=dt, device="cuda")
+    tol = 1e-10 if prec == "f64" else 0.0
+    out = s.solve_device(EB, tol=tol, maxit=400, eps_dev=eps)
+    s.close()
+    exact = bounds.laminate_strain_eig(lam1[0, 0], mu1[0, 0], EB, e1)
+    got = eps.cpu().double().numpy()
+    if prec == "f64":
+        assert out["status"] == L.OK
+    err = rel(got, np.broadcast_to(exact[:, None, None, :], got.shape))
+    print(f"  iterations {out['iters']}, field error {err:.2e}", flush=True)
+    assert err < (1e-9 if prec == "f64" else 1e-5)
+
+
+def test_batch_with_and_without_eigenstrain(L):
+    shape = (16, 12, 8)
+    cells = []
+    for b, chi in enumerate((3.0, 10.0, 30.0)):
+        lam, mu = inputs.cubic_inclusion(shape, (8, 6, 4), 1.0, chi)
+        l0, m0 = inputs.reference_medium_mean(1.0, chi)
+        cells.append((lam, mu, l0, m0, None if b == 1 else _eig(lam, 20 + b)))
+    print("\n[eig batch]", flush=True)
+    K = 10
+    Ebs = np.tile(EB, (3, 1))
+    for scheme, form in (("afb", "displacement"), ("basic", "auto")):
+        h = L.create_batch(cells, scheme=scheme, prec="f64", form=form)
+        eps = torch.zeros((3, 6) + cells[0][0].shape, dtype=torch.float64, device="cuda")
+        st, sm, it, r, sts = L.solve_batch(h, Ebs, 0.0, K, eps, None)
+        L.destroy(h)
+        got = eps.cpu().numpy()
+        for b, (lam, mu, l0, m0, es) in enumerate(cells):
+            ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K, eigenstrain=es)
+            assert rel(got[b], ref.eps) < 1e-12
+            assert rel(sm[b], ref.sig_mean) < 1e-12
+
+
+def test_fp64_warm_start_with_eigenstrain(L):
+    """F32 with five FP64 warm-start iterations: the twin FP64 solver carries the
+    eigenstrain too (same iterates as the oracle to FP32 accuracy)."""
+    print("\n[eig warm start]", flush=True)
+    lam, mu = inputs.cubic_inclusion(16, 8, 1.0, 10.0)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    es = _eig(lam, 6)
+    K = 30
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", f64_warmup=5, eigenstrain=es)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K, eigenstrain=es)
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < 1e-5
+    assert rel(out["sig_mean"], ref.sig_mean) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stress_spectrum_subtracts_eigenstress(L, prec):
+    shape = (16, 12, 8)
+    n1, n2, n3 = shape
+    print(f"\n[eig stress_spectrum] {prec}", flush=True)
+    lam, mu = inputs.random_moduli(shape, seed=2)
+    eps = inputs.random_strain_field(shape, seed=3)
+    es = _eig(lam, 7)
+    s = L.Solver(lam, mu, 2.0, 1.0, scheme="afb", prec=prec, eigenstrain=es)
+    e_dev = torch.tensor(eps, dtype=_dt(prec), device="cuda").contiguous()
+    out = torch.zeros((6, n3, n2, n1 // 2 + 1, 2), dtype=_dt(prec), device="cuda")
+    L.stress_spectrum(s.handle, e_dev, out)
+    torch.cuda.synchronize()
+    s.close()
+    got = out.cpu().double().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = half_spectrum(hooke_voigt(lam, mu, eps - es))
+    assert rel(got, ref) < (1e-13 if prec == "f64" else 2e-6)
