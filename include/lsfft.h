@@ -265,8 +265,10 @@ lsfft_status lsfft_green_apply(lsfft_solver s, const void *in_dev, void *out_dev
  * NULL.  Computed in FP64 with the moduli of system 0 of a batch handle.
  * J is a property of C_eff and needs no eigenstrain: on a handle with one,
  * pass strains of solves whose eigenstrain is zero (another handle).
- * The DGO iteration is not self-adjoint: its sensitivities are not given by
- * this entry point.  EINVAL on NULL handle or strain fields. */
+ * The DGO (Sec. 5.4) is self-adjoint as well: its Green map is a real
+ * symmetric operator, even in the frequency, that annihilates uniform
+ * fields, so the same formula holds with the DGO's own converged strains.
+ * EINVAL on NULL handle or strain fields. */
 lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, const void *eps_b_dev,
                                       void *dj_dlambda_dev, void *dj_dmu_dev, void *dj_dyoung_dev);
 

@@ -14,6 +14,15 @@ is the partial derivative at the solution:
 At fixed Poisson ratio, lambda and mu scale with E, so
     dJ/dE(x) = (lambda dJ/dlambda + mu dJ/dmu) / E.
 The adjoint field of the load A is the primal solution under A.
+
+The DGO of Sec. 5.4 (D3, polarisation form eps = Ebar + G (C - C_H) eps with
+G = F^{c+} Gamma^c F^{c-}) is not derived from an energy, but G is
+self-adjoint: Gamma^c is a real symmetric 6 x 6 per frequency (Mandel
+metric; sums of Gamma_H) and even in xi (symmetric image window), and it
+annihilates uniform fields (Gamma^c_0 = 0).  Differentiating eps[B] and
+solving the adjoint equation w - dC G w = C A (dC = C - C_H) gives
+dJ = <(A + G w) : dC : eps[B]>, and A + G w solves the primal equation under
+A: so the same formula holds with the DGO's own eps[A], eps[B].
 """
 from __future__ import annotations
 
@@ -29,13 +38,15 @@ def contract(a, b):
     return np.tensordot(W, np.asarray(a) * np.asarray(b), axes=(0, 0))
 
 
-def objective(lam, mu, A, B, lam0, mu0, scheme="AFB", tol=1e-12, maxit=5000):
-    """(J, eps[A], eps[B]) with J = A : <sigma[B]>."""
-    rb = solve3d.solve_gfp(lam, mu, B, lam0, mu0, scheme=scheme, tol=tol, maxit=maxit)
-    if np.array_equal(np.asarray(A), np.asarray(B)):
-        ra = rb
-    else:
-        ra = solve3d.solve_gfp(lam, mu, A, lam0, mu0, scheme=scheme, tol=tol, maxit=maxit)
+def objective(lam, mu, A, B, lam0, mu0, scheme="AFB", tol=1e-12, maxit=5000, Gc=None):
+    """(J, eps[A], eps[B]) with J = A : <sigma[B]>.  scheme="DGO" iterates D3
+    with the discrete Green operator Gc (green.dgo_voigt)."""
+    def solve(Eb):
+        if scheme == "DGO":
+            return solve3d.solve_dgo(lam, mu, Eb, lam0, mu0, Gc, tol=tol, maxit=maxit)
+        return solve3d.solve_gfp(lam, mu, Eb, lam0, mu0, scheme=scheme, tol=tol, maxit=maxit)
+    rb = solve(B)
+    ra = rb if np.array_equal(np.asarray(A), np.asarray(B)) else solve(A)
     return float(contract(A, rb.sig_mean)), ra.eps, rb.eps
 
 

@@ -63,6 +63,40 @@ def test_lambda_and_mu_gradients_match_central_differences():
             assert abs(fd - g[v]) < 1e-6 * np.max(np.abs(g)), (which, v, fd, g[v])
 
 
+@pytest.mark.parametrize("p", [1, 2])
+def test_dgo_gradients_match_central_differences(p):
+    """The DGO is self-adjoint too (G symmetric, even, zero on uniform fields):
+    its own primal fields give dJ/dlambda and dJ/dmu."""
+    from oracle import green
+    n = (4, 4, 4)
+    lam, mu = inputs.random_moduli(n, seed=3, E_range=(1.0, 4.0))
+    l0, m0 = 0.5 * (lam.min() + lam.max()), 0.5 * (mu.min() + mu.max())
+    Gc = green.dgo_voigt(n, l0, m0, M=2, p=p)
+    A = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    B = np.array([0.0, 0.5, 0.0, 0.0, 0.0, 0.3])
+
+    def J(lam_, mu_):
+        return adjoint.objective(lam_, mu_, A, B, l0, m0, scheme="DGO", tol=1e-15, maxit=20000, Gc=Gc)
+
+    J0, ea, eb = J(lam, mu)
+    gl, gm, _ = adjoint.modulus_gradient(lam, mu, ea, eb)
+    h = 1e-6
+    for v in [(0, 0, 0), (1, 2, 3), (3, 1, 0)]:
+        lp, lm_ = lam.copy(), lam.copy()
+        lp[v] += h
+        lm_[v] -= h
+        fd_l = (J(lp, mu)[0] - J(lm_, mu)[0]) / (2 * h)
+        mp, mm = mu.copy(), mu.copy()
+        mp[v] += h
+        mm[v] -= h
+        fd_m = (J(lam, mp)[0] - J(lam, mm)[0]) / (2 * h)
+        assert abs(fd_l - gl[v]) < 1e-6 * np.max(np.abs(gl)), (v, fd_l, gl[v])
+        assert abs(fd_m - gm[v]) < 1e-6 * np.max(np.abs(gm)), (v, fd_m, gm[v])
+    # and its effective stiffness is symmetric
+    Jba = adjoint.objective(lam, mu, B, A, l0, m0, scheme="DGO", tol=1e-15, maxit=20000, Gc=Gc)[0]
+    assert abs(J0 - Jba) < 1e-12 * abs(J0)
+
+
 def test_objective_is_symmetric_in_the_loads():
     E, lam, mu, l0, m0 = _cell(7)
     A = np.array([1.0, 0.2, -0.3, 0.1, 0.05, 0.4])
