@@ -286,6 +286,48 @@ const char *lsfft_kernel_name(int32_t kernel_id);
 /* Release all device memory of the solver.  lsfft_destroy(NULL) is a no-op. */
 lsfft_status lsfft_destroy(lsfft_solver s);
 
+/* ---------------------------------------------------------------- 1D
+ * The 1D algorithms of Sec. 3 for many independent periodic bars of one
+ * length, solved by one launch (a workgroup per bar iterates to its own
+ * stopping test):
+ *   GFP (Sec. 3.1 on nodal samples, disc TD; Sec. 3.2 on cell-centred
+ *   samples, disc PCD): u^ += G T^ q^b, G = -1 / (C_H q^a q^b), with the
+ *   pair (q^a, q^b) of `scheme`; stops on r = |T^ q^b| / |T^(0)| <= tol or at
+ *   k = maxit (same reading as lsfft_solve).
+ *   DGO (Sec. 3.3, PCD only, polarisation form): E <- Ebar + F^+ Gamma^c
+ *   F^- (C - C_H) E with Gamma^c = -c_p / C_H, c_p the image sum of sinc^p
+ *   (window as for the 3D DGO); stops on |E' - E| / (sqrt(n) |Ebar|) <= tol or
+ *   after maxit updates. */
+typedef enum {
+  LSFFT_1D_F = 0,     /* Fourier symbol i k, with its conjugate             */
+  LSFFT_1D_FD = 1,    /* forward difference, with its conjugate (-BD)       */
+  LSFFT_1D_CD = 2,    /* central difference, with its conjugate             */
+  LSFFT_1D_FD_HC = 3, /* forward difference with the half-central divergence
+                         (the non-conjugate pair of Sec. 3.1)               */
+  LSFFT_1D_DGO = 4    /* discrete Green operator                            */
+} lsfft_scheme_1d;
+
+typedef struct {
+  int32_t n;                /* samples per bar: 2^a or 3*2^a, 4..512         */
+  double h;                 /* spacing; 0 means 1.0                          */
+  int32_t scheme;           /* lsfft_scheme_1d                               */
+  int32_t disc;             /* lsfft_disc (DGO: PCD)                          */
+  int32_t prec;             /* lsfft_prec                                     */
+  int32_t dgo_images;       /* DGO: image window M, 0..64                     */
+  int32_t dgo_weight_power; /* DGO: 1 or 2                                    */
+  void *stream;             /* hipStream_t; NULL = default stream             */
+} lsfft_config_1d;
+
+/* Solve `count` bars (1..65535): C[count][n] stiffness samples, C_H[count],
+ * Ebar[count] (HOST).  Outputs (HOST, each may be NULL): E and T [count][n]
+ * (strain Ebar + E~ and stress), iters, residual, status [count].  Returns
+ * the largest per-bar status (OK or ENOTCONV).  Synchronous.  EINVAL: NULL
+ * inputs, unsupported n, h < 0, C <= 0 or C_H <= 0 or non-finite, unknown
+ * enums, DGO with TD or with Ebar = 0, tol < 0, maxit < 0 or > 1e7. */
+lsfft_status lsfft_solve_1d(const lsfft_config_1d *cfg, int32_t count, const double *C, const double *C_H,
+                            const double *Ebar, double tol, int32_t maxit, double *E, double *T, int32_t *iters,
+                            double *residual, int32_t *status);
+
 /* Static string for a status code. */
 const char *lsfft_status_string(lsfft_status st);
 

@@ -5,6 +5,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <vector>
 
 #include "../../include/lsfft.h"
@@ -173,6 +174,43 @@ struct lsfft_solver_s {
 };
 
 namespace lsfft_host {
+
+// The transform lengths the kernels are instantiated for: 2^a or 3 * 2^a.
+inline bool supported_len(int n) {
+  if (n < 4 || n > 512 || (n & 1)) return false;
+  int m = n;
+  while (m % 2 == 0) m /= 2;
+  return m == 1 || m == 3;
+}
+
+// ------------------------------------------------------------------ tables
+// exp(-2 pi i m / n) and friends, from long double with exact values at
+// multiples of a quarter turn.
+inline void cis_exact(long long num, long long den, long double &c, long double &s) {
+  // angle 2 pi num / den
+  long long q = ((num % den) + den) % den;
+  if ((4 * q) % den == 0) {
+    const int k = (int)((4 * q) / den) % 4;
+    const long double cc[4] = {1.0L, 0.0L, -1.0L, 0.0L};
+    const long double ss[4] = {0.0L, 1.0L, 0.0L, -1.0L};
+    c = cc[k];
+    s = ss[k];
+    return;
+  }
+  const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)q / (long double)den;
+  c = cosl(a);
+  s = sinl(a);
+}
+
+template <typename T> inline std::vector<cplx<T>> twiddles(int n) {
+  std::vector<cplx<T>> w(n);
+  for (int m = 0; m < n; ++m) {
+    long double c, s;
+    cis_exact(-m, n, c, s);
+    w[m] = cplx<T>{(T)c, (T)s};
+  }
+  return w;
+}
 
 // Workgroup counts and tile widths of the passes (no kernels referenced).
 template <typename T> struct Tiles {

@@ -45,6 +45,23 @@ class Config(C.Structure):
     ]
 
 
+class Config1d(C.Structure):
+    """lsfft_config_1d."""
+    _fields_ = [
+        ("n", C.c_int32),
+        ("h", C.c_double),
+        ("scheme", C.c_int32),
+        ("disc", C.c_int32),
+        ("prec", C.c_int32),
+        ("dgo_images", C.c_int32),
+        ("dgo_weight_power", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+SCHEMES_1D = {"f": 0, "fd": 1, "cd": 2, "fd_hc": 3, "dgo": 4}
+
+
 class Schedule(C.Structure):
     """lsfft_schedule: how one iteration's passes are cut into workgroups."""
     _fields_ = [
@@ -74,6 +91,8 @@ def _load():
         "lsfft_get_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
         "lsfft_set_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
         "lsfft_autotune": (C.c_int, [h, C.c_int32, C.POINTER(Schedule), dp, dp]),
+        "lsfft_solve_1d": (C.c_int, [C.POINTER(Config1d), C.c_int32, dp, dp, dp, C.c_double, C.c_int32, dp, dp,
+                                     C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
         "lsfft_solve": (C.c_int, [h, dp, C.c_double, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), dp]),
         "lsfft_solve_device": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                          C.POINTER(C.c_int32), dp]),
@@ -97,7 +116,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_device", "lsfft_solve_batch",
-           "lsfft_batch_size", "lsfft_get_schedule", "lsfft_set_schedule", "lsfft_autotune",
+           "lsfft_batch_size", "lsfft_get_schedule", "lsfft_set_schedule", "lsfft_autotune", "lsfft_solve_1d",
            "lsfft_residual_history",
            "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
            "lsfft_get_timing",
@@ -211,6 +230,40 @@ def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0)
 
 def batch_size(handle):
     return int(_lib.lsfft_batch_size(handle))
+
+
+def solve_1d(stiffness, CH, Ebar, scheme="f", disc="td", prec="f64", h=1.0, dgo_images=4, dgo_weight_power=1,
+             tol=1e-12, maxit=10000, stream=None):
+    """lsfft_solve_1d for bars of stiffness samples C, shaped (n,) or
+    (count, n); CH and Ebar are scalars or (count,) arrays.  Returns a dict
+    with status, E and T (shaped like C), iters, residual and the per-bar
+    status."""
+    Cin = np.asarray(stiffness, dtype=np.float64)
+    Cb = np.ascontiguousarray(np.atleast_2d(Cin))
+    count, n = Cb.shape
+    CHb = np.ascontiguousarray(np.broadcast_to(np.asarray(CH, dtype=np.float64), (count,)))
+    Ebb = np.ascontiguousarray(np.broadcast_to(np.asarray(Ebar, dtype=np.float64), (count,)))
+    cfg = Config1d()
+    cfg.n = n
+    cfg.h = float(h)
+    cfg.scheme = SCHEMES_1D[scheme.lower()] if isinstance(scheme, str) else int(scheme)
+    cfg.disc = DISCS[disc.lower()] if isinstance(disc, str) else int(disc)
+    cfg.prec = PRECS[prec.lower()] if isinstance(prec, str) else int(prec)
+    cfg.dgo_images = int(dgo_images)
+    cfg.dgo_weight_power = int(dgo_weight_power)
+    cfg.stream = _stream_handle(stream)
+    E = np.zeros((count, n))
+    T = np.zeros((count, n))
+    it = (C.c_int32 * count)()
+    r = np.zeros(count)
+    sts = (C.c_int32 * count)()
+    st = _lib.lsfft_solve_1d(C.byref(cfg), count, _dptr(Cb), _dptr(CHb), _dptr(Ebb), float(tol), int(maxit),
+                             _dptr(E), _dptr(T), it, _dptr(r), sts)
+    if st < 0:
+        raise LsfftError(st, "lsfft_solve_1d")
+    shape = Cin.shape
+    return {"status": st, "E": E.reshape(shape), "T": T.reshape(shape), "iters": np.array(list(it)),
+            "residual": r, "bar_status": np.array(list(sts))}
 
 
 def get_schedule(handle):

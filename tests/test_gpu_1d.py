@@ -1,0 +1,125 @@
+"""The 1D algorithms of Sec. 3 on the GPU (lsfft_solve_1d) against the oracle's
+1D solvers (fixed iterations and converged, TD and PCD, every pair, the DGO
+with p = 1, 2) and against the analytic nodal solution of eq. (3), for
+batches of bars of one length with different stiffness, C_H and Ebar."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import solve1d  # noqa: E402
+
+NAMES = {"f": "F", "fd": "FD", "cd": "CD", "fd_hc": "FD_hC"}
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _bars(n, count, seed, chi=100.0, smooth=False):
+    """Inclusion bars: a stiff segment of random length and position."""
+    rng = np.random.default_rng(seed)
+    C = np.ones((count, n))
+    x = (np.arange(n) + 0.5) / n
+    for b in range(count):
+        lo, w = rng.uniform(0.1, 0.5), rng.uniform(0.2, 0.4)
+        inside = (x > lo) & (x < lo + w)
+        if smooth:
+            d = np.minimum(np.abs(x - lo), np.abs(x - lo - w)) * n
+            C[b] = 1.0 + (chi - 1.0) * np.where(inside, 1.0, np.exp(-d))
+        else:
+            C[b, inside] = chi
+        C[b] *= rng.uniform(0.5, 2.0)
+    CH = 0.5 * (C.min(axis=1) + C.max(axis=1))
+    Eb = rng.uniform(0.5, 2.0, count) * np.where(rng.random(count) < 0.5, -1.0, 1.0)
+    return C, CH, Eb
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("scheme", ["f", "fd", "cd", "fd_hc"])
+@pytest.mark.parametrize("disc", ["td", "pcd"])
+@pytest.mark.parametrize("n", [4, 12, 64, 96, 512])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gfp_fixed_iterations_match_oracle(L, scheme, disc, n, prec):
+    print(f"\n[1d gfp] {scheme} {disc} n={n} {prec}", flush=True)
+    C, CH, Eb = _bars(n, 5, seed=n)
+    K = 15
+    out = L.solve_1d(C, CH, Eb, scheme=scheme, disc=disc, prec=prec, tol=0.0, maxit=K)
+    # FP32: the stress of a contrast-100 bar carries the FP32 rounding of the
+    # small strain in its stiff segment times the contrast
+    tol_e, tol_t = (1e-12, 1e-12) if prec == "f64" else (1e-5, 5e-5)
+    # residuals near convergence are differences at rounding level: absolute
+    # floor (FP32: its residual floor at contrast 100, about chi x 2^-24 x 10)
+    r_rel, r_abs = (1e-9, 1e-13) if prec == "f64" else (1e-3, 1e-4)
+    for b in range(C.shape[0]):
+        E, T, k, r = solve1d.solve_gfp_1d(C[b], Eb[b], CH[b], scheme=NAMES[scheme], tol=0.0, maxit=K,
+                                          disc=disc.upper())
+        assert out["iters"][b] == k == K
+        assert _rel(out["E"][b], E) < tol_e
+        assert _rel(out["T"][b], T) < tol_t
+        assert abs(out["residual"][b] - r) <= r_rel * r + r_abs
+
+
+@pytest.mark.parametrize("scheme", ["f", "fd", "cd", "fd_hc"])
+@pytest.mark.parametrize("disc", ["td", "pcd"])
+def test_gfp_converged_matches_oracle_and_analytic(L, scheme, disc):
+    n = 48
+    print(f"\n[1d gfp converged] {scheme} {disc}", flush=True)
+    C, CH, Eb = _bars(n, 4, seed=3)
+    out = L.solve_1d(C, CH, Eb, scheme=scheme, disc=disc, prec="f64", tol=1e-12, maxit=20000)
+    assert out["status"] == L.OK
+    for b in range(C.shape[0]):
+        E, T, k, r = solve1d.solve_gfp_1d(C[b], Eb[b], CH[b], scheme=NAMES[scheme], tol=1e-12, maxit=20000,
+                                          disc=disc.upper())
+        assert abs(out["iters"][b] - k) <= 1
+        assert _rel(out["E"][b], E) < 1e-11
+        # every pair reaches the exact nodal solution (the 1D claim of Sec. 3.4),
+        # except CD on even grids, whose symbol also vanishes at the Nyquist index
+        if scheme == "cd":
+            continue
+        exact, Tbar = solve1d.analytic_strain(C[b], Eb[b])
+        assert _rel(out["E"][b], exact) < 1e-10
+        assert np.allclose(out["T"][b], Tbar, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("n", [8, 24, 256])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dgo_matches_oracle(L, p, n, prec):
+    print(f"\n[1d dgo] p={p} n={n} {prec}", flush=True)
+    C, CH, Eb = _bars(n, 4, seed=10 + n, chi=10.0)
+    M = 3
+    K = 20
+    out = L.solve_1d(C, CH, Eb, scheme="dgo", disc="pcd", prec=prec, dgo_images=M, dgo_weight_power=p, tol=0.0,
+                     maxit=K)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for b in range(C.shape[0]):
+        E, T, k, r = solve1d.solve_dgo_1d(C[b], Eb[b], CH[b], M, p=p, tol=0.0, maxit=K)
+        assert out["iters"][b] == k
+        assert _rel(out["E"][b], E) < tol
+        assert _rel(out["T"][b], T) < tol
+        assert abs(out["residual"][b] - r) <= (1e-8 if prec == "f64" else 1e-2) * r
+
+
+def test_bars_stop_on_their_own_tests(L):
+    """A homogeneous bar (exact at once) beside inclusion bars: per-bar
+    iteration counts equal the oracle's."""
+    n = 64
+    C, CH, Eb = _bars(n, 3, seed=5)
+    C[1] = 3.0
+    CH[1] = 2.0
+    print("\n[1d independent stops]", flush=True)
+    out = L.solve_1d(C, CH, Eb, scheme="fd", disc="td", prec="f64", tol=1e-10, maxit=5000)
+    assert out["iters"][1] == 0 and out["bar_status"][1] == L.OK
+    for b in (0, 2):
+        k = solve1d.solve_gfp_1d(C[b], Eb[b], CH[b], scheme="FD", tol=1e-10, maxit=5000)[2]
+        assert abs(out["iters"][b] - k) <= 1

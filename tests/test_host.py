@@ -109,3 +109,30 @@ def test_batch_configs_must_agree(L):
         L.create_batch([])
     assert e.value.status == L.EINVAL
     assert L.batch_size(None) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(scheme="dgo", disc="td"), dict(scheme="dgo", disc="pcd", dgo_images=65),
+                                dict(scheme="dgo", disc="pcd", dgo_weight_power=0), dict(scheme=5),
+                                dict(disc=2), dict(prec=3), dict(h=-1.0), dict(tol=-1.0), dict(maxit=-1),
+                                dict(maxit=20000000)])
+def test_1d_bad_options_rejected(L, kw):
+    C = np.linspace(1.0, 2.0, 16)
+    with pytest.raises(L.LsfftError) as e:
+        L.solve_1d(C, 1.5, 1e-3, **kw)
+    assert e.value.status == L.EINVAL
+
+
+@pytest.mark.parametrize("C,CH,Eb", [(np.ones(10), 1.0, 1.0), (np.ones(1024), 1.0, 1.0),
+                                     (np.array([1.0, -1.0, 1.0, 1.0]), 1.0, 1.0),
+                                     (np.array([1.0, np.nan, 1.0, 1.0]), 1.0, 1.0),
+                                     (np.ones(8), 0.0, 1.0), (np.ones(8), 1.0, np.inf)])
+def test_1d_bad_inputs_rejected(L, C, CH, Eb):
+    with pytest.raises(L.LsfftError) as e:
+        L.solve_1d(C, CH, Eb)
+    assert e.value.status == L.EINVAL
+
+
+def test_1d_dgo_needs_a_macroscopic_strain(L):
+    with pytest.raises(L.LsfftError) as e:
+        L.solve_1d(np.ones(8), 1.0, 0.0, scheme="dgo", disc="pcd")
+    assert e.value.status == L.EINVAL
