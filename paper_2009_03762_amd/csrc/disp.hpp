@@ -193,6 +193,8 @@ template <typename T> struct SArgs {
   double *partial;     // [system][gridDim.x][8]: 6 stress sums, sum |f|^2
   const State *st;     // [system]
   const T *fstar;      // div sigma_* of the eigenstress at the nodes [system][3][N], or null
+  ReduceArgs red;      // the iteration's reduction and stop test ...
+  unsigned *counter;   // ... taken by the last workgroup: arrivals [system], or null (no reduction)
   int Z;               // planes per workgroup
   int xcd;             // 1: XCD-aware order of the tiles
   int zero_u;          // u is identically zero (first pass): the LDS variant skips its loads
@@ -487,10 +489,14 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
     block_sum<WG>(sums, 7, red);
     if (tid == 0) {
       double *dst = a.partial + (long long)blockIdx.x * 8;
-      for (int i = 0; i < 7; ++i) dst[i] = sums[i];
-      dst[7] = 0.0;
+      sums[7] = 0.0;
+      if (a.counter)
+        store_row_coherent(dst, sums, 8);  // read by the last workgroup of this launch
+      else
+        for (int i = 0; i < 8; ++i) dst[i] = sums[i];
     }
   }
+  if (a.counter) last_block_reduce<WG>(a.red, a.counter, sysb, red);
 }
 
 // Register-resident variant for power-of-two n1: every thread owns fixed x
@@ -802,10 +808,14 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
     block_sum<WG>(sums, 7, red);
     if (tid == 0) {
       double *dst = a.partial + (long long)blockIdx.x * 8;
-      for (int i = 0; i < 7; ++i) dst[i] = sums[i];
-      dst[7] = 0.0;
+      sums[7] = 0.0;
+      if (a.counter)
+        store_row_coherent(dst, sums, 8);  // read by the last workgroup of this launch
+      else
+        for (int i = 0; i < 8; ++i) dst[i] = sums[i];
     }
   }
+  if (a.counter) last_block_reduce<WG>(a.red, a.counter, sysb, red);
 }
 
 // ---------------------------------------------------------------- z pass, displacement form

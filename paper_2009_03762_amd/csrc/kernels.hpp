@@ -555,6 +555,125 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------- reduction
+// Strain form: two kernels, both in a fixed order (deterministic):
+// k_reduce_stage sums contiguous chunks of the x-pass and z-pass block sums
+// into RSTAGE rows of 8 doubles; k_reduce sums those rows and takes the stop
+// decision.  Displacement form: the last workgroup of the stencil launch
+// does both (last_block_reduce below).
+constexpr int RSTAGE = 64;
+
+struct ReduceArgs {
+  const double *px;   // x-pass block sums [system][nx][8] (6 stress sums, |d eps|^2, unused)
+  int nx;
+  const double *pz;   // z-pass block sums [system][nz]
+  int nz;
+  long long spx, spz; // strides between systems
+  double *stage;      // [system][RSTAGE][8]: 6 stress sums, |d eps|^2, residual
+  State *st;          // [system]
+  double *hist;       // [system][hcap]
+  long long hcap;
+  const double *ebar_norms;  // [system] |Ebar|_F (RMS |E_*|_F for Ebar = 0 under eigenstrain)
+  const double *smean;       // [system][6] mean eigenstress <C E_*> left out of the x-side sums, or null
+  int maxit;
+  double tol;
+  int dgo;
+  int disp;           // displacement form: residual from sum_x |div sigma|^2 (x-side slot 6)
+  double N;
+  double div_factor;
+};
+
+// The stop decision of system sysb from its summed partials vals[8] (6
+// stress sums, x-side residual or |d eps|^2, z-side residual); one thread.
+__device__ inline void reduce_decide(const ReduceArgs &a, int sysb, const double (&vals)[8]) {
+  State &s = a.st[sysb];
+  double *hist = a.hist + sysb * a.hcap;
+  const double ebar_norm = a.ebar_norms[sysb];
+  // the iteration index lives on the device, so that a captured sequence of
+  // iterations can be replayed unchanged
+  const int k = s.k;
+  double mean[6];
+  double sn = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    mean[c] = vals[c] / a.N - (a.smean ? a.smean[6 * sysb + c] : 0.0);
+    sn += (c < 3 ? 1.0 : 2.0) * mean[c] * mean[c];
+  }
+  double r;
+  if (a.dgo) {
+    r = (k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * ebar_norm);
+  } else {
+    const double num = a.disp ? sqrt(a.N * vals[6]) : sqrt(vals[7]);
+    const double den = a.N * sqrt(sn);
+    r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : __builtin_huge_val());
+  }
+  hist[k] = r;
+  s.r = r;
+  for (int c = 0; c < 6; ++c) s.sig_mean[c] = mean[c];
+  s.iters = k;
+  const int first = a.dgo ? 1 : 0;
+  if (k == first) s.r0 = r;
+  int done = 0, status = 1;
+  const bool finite = (r == r) && (r < __builtin_huge_val());
+  if (a.dgo && k == 0) {
+    if (k == a.maxit) { done = 1; status = 1; }
+  } else if (r <= a.tol) {
+    done = 1;
+    status = 0;
+  } else if (!a.dgo && k == a.maxit) {
+    done = 1;
+    status = 1;
+  } else if (!finite || r > a.div_factor * fmax(s.r0, 1e-300)) {
+    done = 1;
+    status = 2;
+  } else if (a.dgo && k == a.maxit) {
+    done = 1;
+    status = 1;
+  }
+  if (done) {
+    s.status = status;
+    s.done = 1;
+  } else {
+    s.k = k + 1;
+  }
+}
+
+// Rows of block sums that another XCD will read inside the same launch are
+// written and read with device-scope atomics: such accesses go to the
+// device's coherence point, so no write-back of the whole L2 (which a
+// device-scope fence would issue) is needed to publish eight doubles.
+__device__ __forceinline__ void store_row_coherent(double *dst, const double *vals, int nv) {
+  for (int i = 0; i < nv; ++i) __hip_atomic_store(dst + i, vals[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by every workgroup of a launch that wrote its row of 8 block sums
+// into ra.px (system sysb) with store_row_coherent: the workgroup that arrives
+// last sums every row in a fixed order (deterministic, whichever workgroup it
+// is) and takes the stop decision, then rearms the system's arrival counter.
+// The row's stores complete (s_waitcnt) before the arrival is counted.
+template <int WG>
+__device__ __forceinline__ void last_block_reduce(const ReduceArgs &ra, unsigned *counter, int sysb, double *red) {
+  __shared__ int last;
+  __syncthreads();  // this workgroup's row is issued (by thread 0)
+  if (threadIdx.x == 0) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const unsigned prev = __hip_atomic_fetch_add(counter + sysb, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  const double *px = ra.px + sysb * ra.spx;
+  double vals[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long i = threadIdx.x; i < ra.nx; i += WG)
+    for (int c = 0; c < 7; ++c) vals[c] += __hip_atomic_load(px + i * 8 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  block_sum<WG>(vals, 8, red);
+  if (threadIdx.x == 0) {
+    reduce_decide(ra, sysb, vals);
+    counter[sysb] = 0u;
+  }
+}
+
 // ---------------------------------------------------------------- pointwise helpers
 // Sensitivity of J = <eps_a : C : eps_b> (= A : C_eff : B for the converged
 // strains under macroscopic loads A and B) to the moduli of each voxel: the

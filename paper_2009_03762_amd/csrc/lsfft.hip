@@ -192,6 +192,8 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   a.partial = s->px;
   a.st = s->st;
   a.fstar = (const T *)s->fstar;
+  a.red = lsfft::ReduceArgs{};
+  a.counter = nullptr;
   a.Z = s->sZ;
   a.xcd = s->xcd & 1;
   a.zero_u = zero_u;
@@ -319,30 +321,6 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   const bool disp = s->disp != 0;
   const int ncomp = disp ? 3 : 6;
   s->launch_b = s->B;
-  if (fresh) {
-    hipLaunchKernelGGL(lsfft::k_state_init, dim3((s->B + 63) / 64), dim3(64), 0, s->stream, s->st, s->B);
-    LSFFT_CHECK(hipGetLastError());
-  }
-  if (disp) {
-    if (fresh) {
-      const long long nu = 3 * s->d.N * s->B;
-      hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
-                         dim3(256), 0, s->stream, (double *)s->u, nu);
-      LSFFT_CHECK(hipGetLastError());
-    }
-    Timed tm(s, 0);
-    LSFFT_CHECK(L::stencil(s, sargs<T>(s, fresh ? 1 : 0), s->nsb));
-  } else {
-    Timed tm(s, 0);
-    LSFFT_CHECK(L::xpass(s, xargs<T>(s, lsfft::XMODE_INIT, nullptr, true), s->nxb));
-  }
-  const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
-  const int nyg = ygrid<T>(s, ncomp);
-  lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
-  if (disp) za.main_blocks = s->zu_main_blocks;
-  const lsfft::XArgs<T> xa = xargs<T>(s, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
-  const lsfft::SArgs<T> sa = sargs<T>(s, 0);
-  const lsfft::UArgs<T> ua = uargs<T>(s);
   lsfft::ReduceArgs ra;
   ra.px = s->px;
   ra.nx = disp ? s->nsb : s->nxb;
@@ -362,10 +340,42 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   ra.disp = disp ? 1 : 0;
   ra.N = (double)s->d.N;
   ra.div_factor = s->tuning ? __builtin_huge_val() : 1e6;
+  // displacement form: the stencil's last workgroup takes the reduction and
+  // stop test of the iterate the stencil has just evaluated
+  auto with_reduce = [&](lsfft::SArgs<T> a) {
+    a.red = ra;
+    a.counter = s->counter;
+    return a;
+  };
+  if (fresh) {
+    hipLaunchKernelGGL(lsfft::k_state_init, dim3((s->B + 63) / 64), dim3(64), 0, s->stream, s->st, s->B);
+    LSFFT_CHECK(hipGetLastError());
+  }
+  if (disp) {
+    if (fresh) {
+      const long long nu = 3 * s->d.N * s->B;
+      hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
+                         dim3(256), 0, s->stream, (double *)s->u, nu);
+      LSFFT_CHECK(hipGetLastError());
+    }
+    Timed tm(s, 0);
+    LSFFT_CHECK(L::stencil(s, with_reduce(sargs<T>(s, fresh ? 1 : 0)), s->nsb));
+  } else {
+    Timed tm(s, 0);
+    LSFFT_CHECK(L::xpass(s, xargs<T>(s, lsfft::XMODE_INIT, nullptr, true), s->nxb));
+  }
+  const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
+  const int nyg = ygrid<T>(s, ncomp);
+  lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
+  if (disp) za.main_blocks = s->zu_main_blocks;
+  const lsfft::XArgs<T> xa = xargs<T>(s, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
+  const lsfft::SArgs<T> sa = with_reduce(sargs<T>(s, 0));
+  const lsfft::UArgs<T> ua = uargs<T>(s);
   // One iteration of every system: forward y, z-pass with the Green step,
-  // reduction and stopping test, inverse y, then the x side (displacement
-  // update and stencil, or x-pass).  `last` omits the trailing stencil (the
-  // next phase evaluates it in its own precision).
+  // (strain form: reduction and stopping test,) inverse y, then the x side:
+  // displacement update and stencil, whose last workgroup reduces and tests
+  // the new iterate, or the x-pass.  `last` omits the trailing stencil (the
+  // next phase evaluates it, and tests that iterate, in its own precision).
   auto iteration = [&](bool last) -> hipError_t {
     hipError_t e;
     {
@@ -376,7 +386,7 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
       Timed tm(s, 2);
       if ((e = disp ? L::zpass_u(s, za, s->nzub) : L::zpass(s, za, s->nzb)) != hipSuccess) return e;
     }
-    {
+    if (!disp) {
       Timed tm(s, 5);
       hipLaunchKernelGGL(lsfft::k_reduce_stage, dim3(lsfft::RSTAGE, s->B), dim3(256), 0, s->stream, ra);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -669,7 +679,7 @@ void release(lsfft_solver s) {
   }
   void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm,
-                  s->sstar, s->fstar, s->smean};
+                  s->sstar, s->fstar, s->smean, s->counter};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -1068,6 +1078,8 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
       }
     }
     s->sZ = Z;
+    if (hipMalloc(&s->counter, B * sizeof(unsigned)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMemset(s->counter, 0, B * sizeof(unsigned)) != hipSuccess) return fail(LSFFT_EDEVICE);
   }
   st = (s->prec == LSFFT_F32) ? set_grids<float>(s) : set_grids<double>(s);
   if (st != LSFFT_OK) return fail(st);

@@ -169,6 +169,7 @@ struct lsfft_solver_s {
   // displacement form, its force div^b (C E_*) at the nodes [B][3][N] (T).
   int eig = 0;
   void *sstar = nullptr, *fstar = nullptr;
+  unsigned *counter = nullptr;  // displacement form: stencil workgroup arrivals [B]
   double *smean = nullptr;
   std::vector<double> estar_rms;  // RMS of |E_*|_F of each system
 };
