@@ -819,11 +819,17 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
 }
 
 // ---------------------------------------------------------------- z pass, displacement form
+// Waves per SIMD the compiler must leave room for: the FP32 AFB pass fits
+// in 128 VGPRs without spilling (four waves); the FB and FP64 passes would
+// spill there and keep the compiler's own choice.
 #ifndef LSFFT_ZU_WAVES
-#define LSFFT_ZU_WAVES 1
+#define LSFFT_ZU_WAVES 4
 #endif
+template <typename T, int SCH> constexpr int zu_min_waves() {
+  return (sizeof(T) == 4 && SCH == SCHEME_AFB) ? LSFFT_ZU_WAVES : 1;
+}
 template <typename T, int NZ, int E, int P, int SCH>
-__global__ __launch_bounds__(P *(NZ / E), LSFFT_ZU_WAVES) void k_zpass_u(ZArgs<T> a) {
+__global__ __launch_bounds__(P *(NZ / E), (zu_min_waves<T, SCH>())) void k_zpass_u(ZArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
   a.spec += sysb * a.bs.spec;
