@@ -212,8 +212,19 @@ __device__ __forceinline__ long long tile_of(long long b, long long nblocks, int
 // All global loads of the workgroup (six spectrum rows, the Nyquist values,
 // the moduli and, in FP32, the old strain) are issued before any transform so
 // that their latencies overlap.
-template <typename T, int L, int E, int WG>
-__global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
+// EIG: the system has an eigenstress (a.sstar); a separate instantiation,
+// since its loads would otherwise size every x-pass's registers.
+#ifndef LSFFT_X_WAVES
+#define LSFFT_X_WAVES 3
+#endif
+// Three waves per SIMD for the FP32 power-of-two lengths up to 128 complex
+// points per line, which fit 168 VGPRs with at most a few spilled values;
+// the others keep the compiler's own choice.
+template <typename T, int L, int E, bool EIG> constexpr int x_min_waves() {
+  return (sizeof(T) == 4 && !EIG && E == 4 && L <= 128) ? LSFFT_X_WAVES : 1;
+}
+template <typename T, int L, int E, int WG, bool EIG>
+__global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
   a.eps += sysb * 6 * a.bs.field;
@@ -222,7 +233,7 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
   a.spec += sysb * a.bs.spec;
   a.nyq += sysb * a.bs.nyq;
   if (a.partial) a.partial += sysb * a.bs.part;
-  if (a.sstar) a.sstar += sysb * 6 * a.bs.field;
+  if (EIG) a.sstar += sysb * 6 * a.bs.field;
   // the system's constants in registers
   T Ebl[6];
 #pragma unroll
@@ -338,7 +349,7 @@ __global__ __launch_bounds__(WG) void k_xpass(XArgs<T> a) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       ss[c][0] = ss[c][1] = T(0);
-      if (a.sstar && valid) ld2(a.sstar + c * N + idx, ss[c][0], ss[c][1]);
+      if (EIG && valid) ld2(a.sstar + c * N + idx, ss[c][0], ss[c][1]);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {

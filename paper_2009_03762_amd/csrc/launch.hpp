@@ -10,7 +10,12 @@ hipError_t Launch<T>::xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid) 
   switch (s->d.L) {
 #define XCASE(Lv)                                                                                        \
 case Lv:                                                                                               \
-  hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
+  if (a.sstar)                                                                                           \
+    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, true>), dim3(grid, s->launch_b), dim3(XWG), 0,    \
+                       s->stream, a);                                                                    \
+  else                                                                                                   \
+    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, false>), dim3(grid, s->launch_b), dim3(XWG), 0,   \
+                       s->stream, a);                                                                    \
   return hipGetLastError();
     LSFFT_X_LENGTHS(XCASE)
 #undef XCASE
