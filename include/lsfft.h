@@ -126,6 +126,27 @@ typedef struct {
                               total strain E and sig outputs C [E - E_*].
                               In a batch each system has its own (NULL
                               systems have none).  EINVAL if not finite.    */
+  int32_t refine;          /* F32 displacement form: FP64 iterative refinement
+                              with cycles of `refine` iterations; 0 = off,
+                              < 0 is EINVAL, > 0 with an F32 strain-form
+                              solver is EINVAL, ignored in F64.  The solve
+                              keeps u = u_b + delta: at the start of each
+                              cycle delta is folded into u_b and the residual
+                              force of u_b is evaluated in FP64; the F32
+                              sweeps then iterate on delta with that force as
+                              a fixed load.  The fixed point keeps no memory
+                              beyond its iterate, so the iterates are the same
+                              as without refinement up to rounding, but the
+                              FP32 rounding is relative to the residual of the
+                              cycle: the residual floor of F32 (see
+                              lsfft_prec) goes away.  Every stop for r <= tol
+                              (or maxit) is confirmed at an FP64 evaluation:
+                              a stop found inside a cycle is re-tested on the
+                              FP64 force of the folded u, and the reported
+                              residual and mean stress are that evaluation's.
+                              Costs 3N FP64 + 3N T + 2N FP64 per system
+                              (+ 6N FP64 with an eigenstrain) and one FP64
+                              residual evaluation per cycle.                 */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda

@@ -935,6 +935,91 @@ __global__ void k_strain_from_u(const double *__restrict__ u, T *__restrict__ ep
   }
 }
 
+// ---------------------------------------------------------------- FP64 refinement
+// Iterative refinement of an F32 displacement-form solve.  The fixed point
+// keeps no memory beyond its iterate, so restarting it on the correction
+// delta of u = u_b + delta, with the residual force of u_b as a fixed load,
+// continues the same iteration; its rounding errors are then relative to
+// the residual at the restart, not to the solution.  k_refine_fold moves
+// delta into u_b; k_refine_force evaluates, in FP64, the total stress
+// sigma_b = C : (Ebar + grad^a u_b) - C E_* at the cells and its divergence
+// F_b = div^b sigma_b at the nodes with the stencils' own operators, and
+// stores -F_b in T as the load of the next FP32 sweeps (they subtract it from
+// div^b C grad^a delta) together with block sums of sigma_b, whose mean the
+// stopping test adds to the mean stress of delta (k_refine_mean).
+template <typename T> struct RefineArgs {
+  Dims d;
+  const double *u;         // folded displacement [system][3][N]
+  const double *lam, *mu;  // FP64 moduli [system][N]
+  const double *sstar;     // FP64 eigenstress C E_* [system][6][N], or null
+  const Member<T> *mem;    // macroscopic strain of each system
+  T *fref;                 // out: -F_b [system][3][N]
+  double *part;            // out: stress sums [system][gridDim.x][8]
+  const State *st;         // [system]
+  double ih[3];            // 1 / h_r
+};
+
+template <typename T, int SCH> __global__ __launch_bounds__(256) void k_refine_force(RefineArgs<T> a) {
+  const int sysb = blockIdx.y;
+  if (a.st[sysb].done) return;
+  const long long N = a.d.N;
+  const int n1 = a.d.n1, n2 = a.d.n2, n3 = a.d.n3;
+  const double *u = a.u + sysb * 3 * N;
+  const double *lam = a.lam + sysb * N, *mu = a.mu + sysb * N;
+  const double *ss = a.sstar ? a.sstar + sysb * 6 * N : nullptr;
+  T *fref = a.fref + sysb * 3 * N;
+  const double *E = a.mem[sysb].Eb;
+  static constexpr int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  __shared__ double red[4 * 8];
+  double sums[6] = {0, 0, 0, 0, 0, 0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % n1);
+    const long long row = i / n1;
+    const int y = (int)(row % n2), z = (int)(row / n2);
+    // sg[c][a][b][d]: stress component c of the cell (x - a, y - b, z - d)
+    double sg[6][2][2][2];
+    for (int o = 0; o < 8; ++o) {
+      const int oa = o & 1, ob = (o >> 1) & 1, od = o >> 2;
+      const int cx = (x - oa + n1) % n1, cy = (y - ob + n2) % n2, cz = (z - od + n3) % n3;
+      double gr[3][3];
+      for (int c = 0; c < 3; ++c) {
+        double cv[2][2][2];
+        for (int p = 0; p < 2; ++p)
+          for (int q = 0; q < 2; ++q)
+            for (int r = 0; r < 2; ++r)
+              cv[p][q][r] = u[c * N + ((long long)((cz + r) % n3) * n2 + (cy + q) % n2) * n1 + (cx + p) % n1];
+        Stencil<SCH>::grad(cv, a.ih, gr[c]);
+      }
+      double e[6];
+      e[0] = E[0] + gr[0][0];
+      e[1] = E[1] + gr[1][1];
+      e[2] = E[2] + gr[2][2];
+      e[3] = E[3] + 0.5 * (gr[1][2] + gr[2][1]);
+      e[4] = E[4] + 0.5 * (gr[0][2] + gr[2][0]);
+      e[5] = E[5] + 0.5 * (gr[0][1] + gr[1][0]);
+      const long long cell = ((long long)cz * n2 + cy) * n1 + cx;
+      const double l = lam[cell], m = mu[cell], tr = e[0] + e[1] + e[2];
+      for (int c = 0; c < 6; ++c) {
+        double v = (c < 3 ? l * tr : 0.0) + 2.0 * m * e[c];
+        if (ss) v -= ss[c * N + cell];
+        sg[c][oa][ob][od] = v;
+      }
+    }
+    // the cell (x, y, z) is counted by its upper node (x, y, z) only
+    for (int c = 0; c < 6; ++c) sums[c] += sg[c][0][0][0];
+    for (int r = 0; r < 3; ++r) {
+      double f = 0.0;
+      for (int j = 0; j < 3; ++j) f += Stencil<SCH>::div(sg[vo[r][j]], j, a.ih);
+      fref[r * N + i] = (T)(-f);
+    }
+  }
+  block_sum<256>(sums, 6, red);
+  if (threadIdx.x == 0) {
+    double *dst = a.part + ((long long)sysb * gridDim.x + blockIdx.x) * 8;
+    for (int c = 0; c < 6; ++c) dst[c] = sums[c];
+  }
+}
+
 template <typename T> __global__ void k_fill_zero(T *p, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = T(0);

@@ -176,13 +176,15 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
 template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   lsfft::SArgs<T> a;
   a.d = s->d;
-  a.u = (const double *)s->u;
+  // refinement: the sweeps iterate on the correction with Ebar = 0 and the
+  // FP64 residual force of the folded displacement as their load
+  a.u = (const double *)(s->refine ? s->du : s->u);
   a.lam = (const T *)s->lam;
   a.mu = (const T *)s->mu;
   a.spec = (cplx<T> *)s->spec;
   a.nyq = (cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
-  a.mem = (const lsfft::Member<T> *)s->mem;
+  a.mem = (const lsfft::Member<T> *)(s->refine ? s->mem_ref : s->mem);
   a.bs = s->bs;
   a.bs.part = s->spx;
   for (int r = 0; r < 3; ++r) {
@@ -191,7 +193,7 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   }
   a.partial = s->px;
   a.st = s->st;
-  a.fstar = (const T *)s->fstar;
+  a.fstar = (const T *)(s->refine ? s->fref : s->fstar);
   a.red = lsfft::ReduceArgs{};
   a.counter = nullptr;
   a.Z = s->sZ;
@@ -203,7 +205,7 @@ template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
 template <typename T> lsfft::UArgs<T> uargs(lsfft_solver s) {
   lsfft::UArgs<T> a;
   a.d = s->d;
-  a.u = (double *)s->u;
+  a.u = (double *)(s->refine ? s->du : s->u);
   a.spec = (const cplx<T> *)s->spec;
   a.nyq = (const cplx<T> *)s->nyq;
   a.tw = (const cplx<T> *)s->twx;
@@ -258,6 +260,15 @@ template <typename T> lsfft_status upload_members(lsfft_solver s, const double *
   }
   LSFFT_CHECK(hipMemcpyAsync(s->mem, m.data(), sizeof(lsfft::Member<T>) * s->B, hipMemcpyHostToDevice, s->stream));
   LSFFT_CHECK(hipMemcpyAsync(s->enorm, en.data(), sizeof(double) * s->B, hipMemcpyHostToDevice, s->stream));
+  if (s->mem_ref) {
+    for (auto &x : m) {
+      for (int c = 0; c < 6; ++c) x.Eb[c] = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int r = 0; r < 3; ++r) x.hE[i][r] = 0.0;
+    }
+    LSFFT_CHECK(hipMemcpyAsync(s->mem_ref, m.data(), sizeof(lsfft::Member<T>) * s->B, hipMemcpyHostToDevice,
+                               s->stream));
+  }
   // the host vectors go out of scope: wait for the copies
   LSFFT_CHECK(hipStreamSynchronize(s->stream));
   return LSFFT_OK;
@@ -333,7 +344,9 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   ra.hist = s->hist;
   ra.hcap = s->hist_cap;
   ra.ebar_norms = s->enorm;
-  ra.smean = (disp && s->eig) ? s->smean : nullptr;  // the stencil sums C E, not C [E - E_*]
+  // the stencil sums C E, not C [E - E_*]; refined sweeps sum C grad delta,
+  // and sref holds minus the mean total stress of the folded displacement
+  ra.smean = s->refine ? s->sref : ((disp && s->eig) ? s->smean : nullptr);
   ra.maxit = maxit;
   ra.tol = s->tuning ? -1.0 : tol;
   ra.dgo = dgo ? 1 : 0;
@@ -355,11 +368,12 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
     if (fresh) {
       const long long nu = 3 * s->d.N * s->B;
       hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3((unsigned)std::min<long long>((nu + 255) / 256, 65536)),
-                         dim3(256), 0, s->stream, (double *)s->u, nu);
+                         dim3(256), 0, s->stream, (double *)(s->refine ? s->du : s->u), nu);
       LSFFT_CHECK(hipGetLastError());
     }
     Timed tm(s, 0);
-    LSFFT_CHECK(L::stencil(s, with_reduce(sargs<T>(s, fresh ? 1 : 0)), s->nsb));
+    // a refinement cycle starts from delta = 0
+    LSFFT_CHECK(L::stencil(s, with_reduce(sargs<T>(s, (fresh || s->refine) ? 1 : 0)), s->nsb));
   } else {
     Timed tm(s, 0);
     LSFFT_CHECK(L::xpass(s, xargs<T>(s, lsfft::XMODE_INIT, nullptr, true), s->nxb));
@@ -475,6 +489,82 @@ void drop_graph(lsfft_solver s) {
   s->g_maxit = -1;
 }
 
+// Start of a refinement cycle (systems not done): fold delta into u, then
+// the FP64 residual force of u and its mean stress (k_refine_force).
+template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
+  const long long n3 = 3 * s->d.N;
+  const unsigned fb = (unsigned)std::min<long long>((n3 + 255) / 256, 4096);
+  hipLaunchKernelGGL(lsfft::k_refine_fold, dim3(fb, s->B), dim3(256), 0, s->stream, (double *)s->u, s->du, s->st,
+                     n3);
+  LSFFT_CHECK(hipGetLastError());
+  lsfft::RefineArgs<T> a;
+  a.d = s->d;
+  a.u = (const double *)s->u;
+  a.lam = s->lam64;
+  a.mu = s->mu64;
+  a.sstar = s->sstar64;
+  a.mem = (const lsfft::Member<T> *)s->mem;
+  a.fref = (T *)s->fref;
+  a.part = s->rpart;
+  a.st = s->st;
+  for (int r = 0; r < 3; ++r) a.ih[r] = 1.0 / s->h[r];
+  if (s->scheme == LSFFT_FB)
+    hipLaunchKernelGGL((lsfft::k_refine_force<T, lsfft::SCHEME_FB>), dim3(s->nrb, s->B), dim3(256), 0, s->stream, a);
+  else
+    hipLaunchKernelGGL((lsfft::k_refine_force<T, lsfft::SCHEME_AFB>), dim3(s->nrb, s->B), dim3(256), 0, s->stream, a);
+  LSFFT_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(lsfft::k_refine_mean, dim3(s->B), dim3(64), 0, s->stream, s->rpart, s->nrb, s->sref, s->st,
+                     (double)s->d.N);
+  LSFFT_CHECK(hipGetLastError());
+  return LSFFT_OK;
+}
+
+// A solve with FP64 iterative refinement (F32 displacement form): cycles of
+// `refine` F32 iterations on delta, each opened by a fold and an FP64
+// residual evaluation whose stencil pass tests the folded iterate.  A system
+// that stops inside a cycle (tolerance, maxit or divergence judged on the
+// F32 sums) is resumed and re-tested at the next FP64 evaluation, so every
+// final status, residual and mean stress comes from one.  fresh: start from
+// u = 0; otherwise u holds an untested iterate (FP64 warm start).
+template <typename T> lsfft_status run_refined(lsfft_solver s, double tol, int maxit, bool fresh) {
+  const long long nu = 3 * s->d.N * s->B;
+  const unsigned zb = (unsigned)std::min<long long>((nu + 255) / 256, 65536);
+  if (fresh) {
+    hipLaunchKernelGGL(lsfft::k_state_init, dim3((s->B + 63) / 64), dim3(64), 0, s->stream, s->st, s->B);
+    LSFFT_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3(zb), dim3(256), 0, s->stream, (double *)s->u, nu);
+    LSFFT_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(lsfft::k_fill_zero<double>, dim3(zb), dim3(256), 0, s->stream, s->du, nu);
+  LSFFT_CHECK(hipGetLastError());
+  LSFFT_CHECK(hipMemcpyAsync(s->st_host, s->st, sizeof(State) * s->B, hipMemcpyDeviceToHost, s->stream));
+  LSFFT_CHECK(hipStreamSynchronize(s->stream));
+  std::vector<int> tested(s->B);
+  for (;;) {
+    if (all_done(s)) break;
+    // the iterate each system's FP64 evaluation tests
+    for (int b = 0; b < s->B; ++b) tested[b] = s->st_host[b].k;
+    lsfft_status rs = refine_rebase<T>(s);
+    if (rs != LSFFT_OK) return rs;
+    rs = run_phase<T>(s, tol, maxit, 0, s->refine, false);
+    if (rs != LSFFT_OK) return rs;
+    bool resume = false;
+    for (int b = 0; b < s->B; ++b) {
+      State &x = s->st_host[b];
+      if (x.done && x.iters != tested[b]) {
+        x.done = 0;
+        x.status = 1;
+        resume = true;
+      }
+    }
+    if (resume) {
+      LSFFT_CHECK(hipMemcpyAsync(s->st, s->st_host, sizeof(State) * s->B, hipMemcpyHostToDevice, s->stream));
+      LSFFT_CHECK(hipStreamSynchronize(s->stream));
+    }
+  }
+  return LSFFT_OK;
+}
+
 template <typename T>
 lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) {
   lsfft_status hs = ensure_hist(s, maxit);
@@ -495,7 +585,10 @@ lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) 
     lsfft_status ps = run_phase<double>(t, tol, maxit, 0, k0, true);
     if (ps != LSFFT_OK) return ps;
   }
-  if (k0 == 0 || (!all_done(s) && k0 <= maxit)) {
+  if (s->refine) {
+    lsfft_status ps = run_refined<T>(s, tol, maxit, k0 == 0);
+    if (ps != LSFFT_OK) return ps;
+  } else if (k0 == 0 || (!all_done(s) && k0 <= maxit)) {
     lsfft_status ps = run_phase<T>(s, tol, maxit, k0, maxit + 1, k0 == 0);
     if (ps != LSFFT_OK) return ps;
   }
@@ -679,7 +772,8 @@ void release(lsfft_solver s) {
   }
   void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm,
-                  s->sstar, s->fstar, s->smean, s->counter};
+                  s->sstar, s->fstar, s->smean, s->counter, s->du, s->sref, s->lam64, s->mu64, s->sstar64,
+                  s->rpart, s->fref, s->mem_ref};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -735,6 +829,7 @@ template <typename T> lsfft_status setup_eigenstrain(lsfft_solver s, const lsfft
   LSFFT_CHECK(hipMalloc(&s->sstar, B * 6 * (size_t)N * sizeof(T)));
   LSFFT_CHECK(hipMalloc(&s->smean, B * 6 * sizeof(double)));
   if (s->disp) LSFFT_CHECK(hipMalloc(&s->fstar, B * 3 * (size_t)N * sizeof(T)));
+  if (s->refine) LSFFT_CHECK(hipMalloc(&s->sstar64, B * 6 * (size_t)N * sizeof(double)));
   std::vector<double> sd(6 * (size_t)N), fd(s->disp ? 3 * (size_t)N : 0), mean(6 * B, 0.0);
   std::vector<T> tmp(6 * (size_t)N);
   s->estar_rms.assign(B, 0.0);
@@ -757,6 +852,8 @@ template <typename T> lsfft_status setup_eigenstrain(lsfft_solver s, const lsfft
     s->estar_rms[m] = std::sqrt(ss / (double)N);
     for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (T)sd[i];
     LSFFT_CHECK(hipMemcpy((T *)s->sstar + m * 6 * N, tmp.data(), 6 * N * sizeof(T), hipMemcpyHostToDevice));
+    if (s->refine)
+      LSFFT_CHECK(hipMemcpy(s->sstar64 + m * 6 * N, sd.data(), 6 * N * sizeof(double), hipMemcpyHostToDevice));
     if (!s->disp) continue;
     // f_i = sum_j d_j sigma_ij at node (x, y, z), the upper corner of cells
     // (x - a, y - b, z - d), a, b, d in {0, 1}.  AFB: each d_j averages the
@@ -976,7 +1073,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   if ((cfg->scheme == LSFFT_CD || cfg->scheme == LSFFT_ACD) && cfg->form == 2) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
   if (cfg->form < 0 || cfg->form > 2) return LSFFT_EINVAL;
-  if (cfg->f64_warmup < 0) return LSFFT_EINVAL;
+  if (cfg->f64_warmup < 0 || cfg->refine < 0) return LSFFT_EINVAL;
   if (cfg->scheme == LSFFT_DGO) {
     if (cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
     if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
@@ -991,7 +1088,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
       if (c->n[r] != cfg->n[r] || c->h[r] != cfg->h[r]) return LSFFT_EINVAL;
     if (c->disc != cfg->disc || c->scheme != cfg->scheme || c->prec != cfg->prec || c->form != cfg->form ||
         c->dgo_images != cfg->dgo_images || c->dgo_weight_power != cfg->dgo_weight_power ||
-        c->stream != cfg->stream || c->f64_warmup != cfg->f64_warmup)
+        c->stream != cfg->stream || c->f64_warmup != cfg->f64_warmup || c->refine != cfg->refine)
       return LSFFT_EINVAL;
     if (!ok_moduli(c->lambda0, c->mu0)) return LSFFT_EINVAL;
     // the DGO table depends on C0: one table, one reference medium
@@ -1080,6 +1177,28 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     s->sZ = Z;
     if (hipMalloc(&s->counter, B * sizeof(unsigned)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMemset(s->counter, 0, B * sizeof(unsigned)) != hipSuccess) return fail(LSFFT_EDEVICE);
+  }
+  if (cfg->refine > 0 && s->prec == LSFFT_F32) {
+    if (!s->disp) return fail(LSFFT_EINVAL);
+    s->refine = cfg->refine;
+    const size_t n3 = B * 3 * (size_t)N;
+    s->nrb = (int)std::min<long long>((N + 255) / 256, 2048);
+    if (hipMalloc(&s->du, n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->fref, n3 * sizeof(float)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->sref, B * 6 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->lam64, B * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->mu64, B * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->rpart, B * (size_t)s->nrb * 8 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->mem_ref, B * sizeof(lsfft::Member<float>)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    // defined contents for the schedule tuner, which times the sweeps alone
+    if (hipMemset(s->du, 0, n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_EDEVICE);
+    if (hipMemset(s->fref, 0, n3 * sizeof(float)) != hipSuccess) return fail(LSFFT_EDEVICE);
+    if (hipMemset(s->sref, 0, B * 6 * sizeof(double)) != hipSuccess) return fail(LSFFT_EDEVICE);
+    for (size_t m = 0; m < B; ++m) {
+      if (hipMemcpy(s->lam64 + m * N, cfgs[m].lambda, N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(s->mu64 + m * N, cfgs[m].mu, N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LSFFT_EDEVICE);
+    }
   }
   st = (s->prec == LSFFT_F32) ? set_grids<float>(s) : set_grids<double>(s);
   if (st != LSFFT_OK) return fail(st);

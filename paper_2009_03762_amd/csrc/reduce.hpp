@@ -39,6 +39,35 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   reduce_decide(a, sysb, vals);
 }
 
+// Iterative refinement of the F32 displacement form (see k_refine_force):
+// u_b += delta, delta = 0.
+__global__ __launch_bounds__(256) void k_refine_fold(double *u, double *du, const State *st, long long n) {
+  const int sysb = blockIdx.y;
+  if (st[sysb].done) return;
+  u += sysb * n;
+  du += sysb * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    u[i] += du[i];
+    du[i] = 0.0;
+  }
+}
+
+// smean of the refined sweeps: minus the mean of sigma_b (the stopping test
+// subtracts smean from the mean stress of delta).  Fixed summation order.
+__global__ __launch_bounds__(64) void k_refine_mean(const double *part, int rows, double *smean, const State *st,
+                                                    double N) {
+  const int sysb = blockIdx.x;
+  if (st[sysb].done) return;
+  part += (long long)sysb * rows * 8;
+  __shared__ double red[8];
+  double vals[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < rows; i += 64)
+    for (int c = 0; c < 6; ++c) vals[c] += part[i * 8 + c];
+  block_sum<64>(vals, 6, red);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 6; ++c) smean[6 * sysb + c] = -vals[c] / N;
+}
+
 __global__ void k_state_init(State *st, int count) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < count) {

@@ -42,6 +42,7 @@ class Config(C.Structure):
         ("form", C.c_int32),
         ("f64_warmup", C.c_int32),
         ("eigenstrain", C.POINTER(C.c_double)),
+        ("refine", C.c_int32),
     ]
 
 
@@ -167,7 +168,7 @@ def _eigenstrain(es, shape):
 
 
 def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form, f64_warmup,
-            eigenstrain=None):
+            eigenstrain=None, refine=0):
     if lam.ndim != 3 or lam.shape != mu.shape:
         raise ValueError("lam and mu must be 3D arrays of equal shape (n3, n2, n1)")
     n3, n2, n1 = lam.shape
@@ -187,18 +188,20 @@ def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight
     cfg.form = FORMS[form] if isinstance(form, str) else int(form)
     cfg.f64_warmup = int(f64_warmup)
     cfg.eigenstrain = _dptr(eigenstrain)  # the caller keeps the array alive through the call
+    cfg.refine = int(refine)
     return cfg
 
 
 def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, eigenstrain=None):
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, eigenstrain=None, refine=0):
     """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1);
-    eigenstrain: optional (6, n3, n2, n1) Voigt tensor components."""
+    eigenstrain: optional (6, n3, n2, n1) Voigt tensor components; refine:
+    cycle length of the FP64 iterative refinement (F32 displacement form)."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     es = _eigenstrain(eigenstrain, lam.shape)
     cfg = _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                  f64_warmup, es)
+                  f64_warmup, es, refine)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:
@@ -207,7 +210,7 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
 
 
 def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0), dgo_images=4,
-                 dgo_weight_power=1, stream=None, form="auto", f64_warmup=0):
+                 dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, refine=0):
     """lsfft_create_batch.  systems: sequence of (lam, mu, lambda0, mu0) or
     (lam, mu, lambda0, mu0, eigenstrain) with float64 host arrays of one shape
     (n3, n2, n1) (eigenstrain: (6, n3, n2, n1) or None)."""
@@ -220,7 +223,7 @@ def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0)
         es = _eigenstrain(sysm[4] if len(sysm) > 4 else None, lam.shape)
         arrays.append((lam, mu, es))   # keep the buffers alive through the call
         cfgs[m] = _config(lam, mu, l0, m0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                          f64_warmup, es)
+                          f64_warmup, es, refine)
     handle = C.c_void_p()
     st = _lib.lsfft_create_batch(cfgs, len(systems), C.byref(handle))
     if st != OK:

@@ -67,7 +67,8 @@ def test_bad_moduli_rejected(L, lam, mu):
                                 dict(scheme="dgo", disc="td"), dict(scheme="dgo", disc="pcd", dgo_images=-1),
                                 dict(scheme="dgo", disc="pcd", dgo_weight_power=3),
                                 dict(scheme=7), dict(prec=5), dict(disc=4), dict(h=(1.0, -1.0, 1.0)),
-                                dict(form=3), dict(f64_warmup=-1), dict(scheme=6), dict(scheme="cd", form=2),
+                                dict(form=3), dict(f64_warmup=-1), dict(refine=-1), dict(scheme=6),
+                                dict(scheme="cd", form=2),
                                 dict(scheme="acd", form="displacement")])
 def test_bad_config_rejected(L, kw):
     lam, mu = _mat((8, 8, 8))
