@@ -138,15 +138,22 @@ typedef struct {
                               beyond its iterate, so the iterates are the same
                               as without refinement up to rounding, but the
                               FP32 rounding is relative to the residual of the
-                              cycle: the residual floor of F32 (see
-                              lsfft_prec) goes away.  Every stop for r <= tol
-                              (or maxit) is confirmed at an FP64 evaluation:
-                              a stop found inside a cycle is re-tested on the
-                              FP64 force of the folded u, and the reported
-                              residual and mean stress are that evaluation's.
-                              Costs 3N FP64 + 3N T + 2N FP64 per system
-                              (+ 6N FP64 with an eigenstrain) and one FP64
-                              residual evaluation per cycle.                 */
+                              cycle: tolerances below the F32 residual floor
+                              (see lsfft_prec) are reached.  Every stop for
+                              r <= tol (or maxit) is confirmed at an FP64
+                              evaluation: a stop found inside a cycle is
+                              re-tested on the FP64 force of the folded u, and
+                              the reported residual and mean stress are that
+                              evaluation's.  Rounding of the first, large
+                              updates still lands in the slowest modes of the
+                              iteration (contraction about (chi-1)/(chi+1) at
+                              stiffness contrast chi), which refinement sees
+                              but does not remove faster than the iteration:
+                              at contrast >= 1e2 a refined solve takes more
+                              iterations than F64 unless f64_warmup covers
+                              those updates.  Costs 3N FP64 + 3N T + 2N FP64
+                              per system (+ 6N FP64 with an eigenstrain) and
+                              one FP64 residual evaluation per cycle.        */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda
