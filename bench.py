@@ -438,6 +438,51 @@ def config_report():
     return out
 
 
+def refine_study(n=256, tols=(1e-6, 1e-8), maxit=1500):
+    """Wall time and iterations to a certified residual tolerance on the
+    benchmark workload: F64, plain F32, F32 with the FP64 warm start, and
+    F32 with FP64 iterative refinement (with and without warm-start
+    iterations); each strain field is compared with a tight FP64 solution."""
+    import torch
+
+    from paper_2009_03762_amd import lsfft
+    lam, mu, l0, m0, Eb = workload(n)
+    shape = (6, n, n, n)
+    ref = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec="f64", form="displacement")
+    r = s.solve_device(Eb, tol=1e-10, maxit=3000, eps_dev=ref)
+    s.close()
+    rn = torch.linalg.vector_norm(ref).item()
+    out = {"reference": f"FP64 displacement form stopped at r = {r['residual']:.2e} after {r['iters']} iterations",
+           "maxit": maxit, "runs": []}
+    paths = (("f64", dict(prec="f64")), ("f32", dict(prec="f32")), ("f32_warm5", dict(prec="f32", f64_warmup=5)),
+             ("f32_refine32", dict(prec="f32", refine=32)),
+             ("f32_warm5_refine32", dict(prec="f32", refine=32, f64_warmup=5)),
+             ("f32_warm20_refine16", dict(prec="f32", refine=16, f64_warmup=20)),
+             ("f32_warm20_refine32", dict(prec="f32", refine=32, f64_warmup=20)))
+    for tol in tols:
+        for name, kw in paths:
+            dt = torch.float64 if kw["prec"] == "f64" else torch.float32
+            e = torch.zeros(shape, dtype=dt, device="cuda")
+            s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", form="displacement", **kw)
+            s.solve_device(Eb, tol=0.0, maxit=3, eps_dev=e)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = s.solve_device(Eb, tol=tol, maxit=maxit, eps_dev=e)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            err = (torch.linalg.vector_norm(e.double() - ref) / rn).item()
+            s.close()
+            del e
+            row = {"tol": tol, "path": name, "status": int(o["status"]), "iters": int(o["iters"]),
+                   "residual": float(o["residual"]), "ms": ms, "field_err": err}
+            out["runs"].append(row)
+            print(f"[bench] refine study {row}", file=sys.stderr, flush=True)
+    del ref
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(n=128, iters=8):
     """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
     full iterations after setup, single-threaded numpy."""
@@ -503,6 +548,8 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--refine-study", action="store_true",
+                    help="instead of the bench line: time to a certified tolerance with FP64 refinement")
     ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch schedule instead of the tuned one")
@@ -517,6 +564,9 @@ def main():
         return
     if args.configs:
         print(json.dumps(config_report()), flush=True)
+        return
+    if args.refine_study:
+        print(json.dumps(refine_study(args.size)), flush=True)
         return
     tune = not args.no_autotune
     res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form, tune) \

@@ -151,9 +151,9 @@ typedef struct {
                               but does not remove faster than the iteration:
                               at contrast >= 1e2 a refined solve takes more
                               iterations than F64 unless f64_warmup covers
-                              those updates.  Costs 3N FP64 + 3N T + 2N FP64
-                              per system (+ 6N FP64 with an eigenstrain) and
-                              one FP64 residual evaluation per cycle.        */
+                              those updates.  Costs 11N FP64 + 3N T per
+                              system (+ 6N FP64 with an eigenstrain) and one
+                              FP64 residual evaluation per cycle.            */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda

@@ -941,25 +941,26 @@ __global__ void k_strain_from_u(const double *__restrict__ u, T *__restrict__ ep
 // delta of u = u_b + delta, with the residual force of u_b as a fixed load,
 // continues the same iteration; its rounding errors are then relative to
 // the residual at the restart, not to the solution.  k_refine_fold moves
-// delta into u_b; k_refine_force evaluates, in FP64, the total stress
-// sigma_b = C : (Ebar + grad^a u_b) - C E_* at the cells and its divergence
-// F_b = div^b sigma_b at the nodes with the stencils' own operators, and
-// stores -F_b in T as the load of the next FP32 sweeps (they subtract it from
-// div^b C grad^a delta) together with block sums of sigma_b, whose mean the
-// stopping test adds to the mean stress of delta (k_refine_mean).
+// delta into u_b; k_refine_stress evaluates, in FP64, the total stress
+// sigma_b = C : (Ebar + grad^a u_b) - C E_* of every cell once, with block
+// sums for its mean (k_refine_mean); k_refine_div takes its divergence
+// F_b = div^b sigma_b at the nodes, both with the stencils' own operators,
+// and stores -F_b in T as the load of the next FP32 sweeps (they subtract it
+// from div^b C grad^a delta).
 template <typename T> struct RefineArgs {
   Dims d;
   const double *u;         // folded displacement [system][3][N]
   const double *lam, *mu;  // FP64 moduli [system][N]
   const double *sstar;     // FP64 eigenstress C E_* [system][6][N], or null
   const Member<T> *mem;    // macroscopic strain of each system
+  double *sig;             // cell stress sigma_b [system][6][N] (FP64 scratch)
   T *fref;                 // out: -F_b [system][3][N]
   double *part;            // out: stress sums [system][gridDim.x][8]
   const State *st;         // [system]
   double ih[3];            // 1 / h_r
 };
 
-template <typename T, int SCH> __global__ __launch_bounds__(256) void k_refine_force(RefineArgs<T> a) {
+template <typename T, int SCH> __global__ __launch_bounds__(256) void k_refine_stress(RefineArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st[sysb].done) return;
   const long long N = a.d.N;
@@ -967,56 +968,76 @@ template <typename T, int SCH> __global__ __launch_bounds__(256) void k_refine_f
   const double *u = a.u + sysb * 3 * N;
   const double *lam = a.lam + sysb * N, *mu = a.mu + sysb * N;
   const double *ss = a.sstar ? a.sstar + sysb * 6 * N : nullptr;
-  T *fref = a.fref + sysb * 3 * N;
+  double *sig = a.sig + sysb * 6 * N;
   const double *E = a.mem[sysb].Eb;
-  static constexpr int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
   __shared__ double red[4 * 8];
   double sums[6] = {0, 0, 0, 0, 0, 0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    // cell (x, y, z): corners (x..x+1, y..y+1, z..z+1)
     const int x = (int)(i % n1);
     const long long row = i / n1;
     const int y = (int)(row % n2), z = (int)(row / n2);
-    // sg[c][a][b][d]: stress component c of the cell (x - a, y - b, z - d)
-    double sg[6][2][2][2];
-    for (int o = 0; o < 8; ++o) {
-      const int oa = o & 1, ob = (o >> 1) & 1, od = o >> 2;
-      const int cx = (x - oa + n1) % n1, cy = (y - ob + n2) % n2, cz = (z - od + n3) % n3;
-      double gr[3][3];
-      for (int c = 0; c < 3; ++c) {
-        double cv[2][2][2];
-        for (int p = 0; p < 2; ++p)
-          for (int q = 0; q < 2; ++q)
-            for (int r = 0; r < 2; ++r)
-              cv[p][q][r] = u[c * N + ((long long)((cz + r) % n3) * n2 + (cy + q) % n2) * n1 + (cx + p) % n1];
-        Stencil<SCH>::grad(cv, a.ih, gr[c]);
-      }
-      double e[6];
-      e[0] = E[0] + gr[0][0];
-      e[1] = E[1] + gr[1][1];
-      e[2] = E[2] + gr[2][2];
-      e[3] = E[3] + 0.5 * (gr[1][2] + gr[2][1]);
-      e[4] = E[4] + 0.5 * (gr[0][2] + gr[2][0]);
-      e[5] = E[5] + 0.5 * (gr[0][1] + gr[1][0]);
-      const long long cell = ((long long)cz * n2 + cy) * n1 + cx;
-      const double l = lam[cell], m = mu[cell], tr = e[0] + e[1] + e[2];
-      for (int c = 0; c < 6; ++c) {
-        double v = (c < 3 ? l * tr : 0.0) + 2.0 * m * e[c];
-        if (ss) v -= ss[c * N + cell];
-        sg[c][oa][ob][od] = v;
-      }
+    const int xp = (x + 1) % n1;
+    const long long r00 = row * n1, r10 = ((long long)z * n2 + (y + 1) % n2) * n1;
+    const long long r01 = ((long long)((z + 1) % n3) * n2 + y) * n1;
+    const long long r11 = ((long long)((z + 1) % n3) * n2 + (y + 1) % n2) * n1;
+    double gr[3][3];
+    for (int c = 0; c < 3; ++c) {
+      const double *uc = u + c * N;
+      // cv[a][b][d]: corner offsets (x a, y b, z d)
+      const double cv[2][2][2] = {{{uc[r00 + x], uc[r01 + x]}, {uc[r10 + x], uc[r11 + x]}},
+                                  {{uc[r00 + xp], uc[r01 + xp]}, {uc[r10 + xp], uc[r11 + xp]}}};
+      Stencil<SCH>::grad(cv, a.ih, gr[c]);
     }
-    // the cell (x, y, z) is counted by its upper node (x, y, z) only
-    for (int c = 0; c < 6; ++c) sums[c] += sg[c][0][0][0];
-    for (int r = 0; r < 3; ++r) {
-      double f = 0.0;
-      for (int j = 0; j < 3; ++j) f += Stencil<SCH>::div(sg[vo[r][j]], j, a.ih);
-      fref[r * N + i] = (T)(-f);
+    double e[6];
+    e[0] = E[0] + gr[0][0];
+    e[1] = E[1] + gr[1][1];
+    e[2] = E[2] + gr[2][2];
+    e[3] = E[3] + 0.5 * (gr[1][2] + gr[2][1]);
+    e[4] = E[4] + 0.5 * (gr[0][2] + gr[2][0]);
+    e[5] = E[5] + 0.5 * (gr[0][1] + gr[1][0]);
+    const double l = lam[i], m = mu[i], tr = e[0] + e[1] + e[2];
+    for (int c = 0; c < 6; ++c) {
+      double v = (c < 3 ? l * tr : 0.0) + 2.0 * m * e[c];
+      if (ss) v -= ss[c * N + i];
+      sig[c * N + i] = v;
+      sums[c] += v;
     }
   }
   block_sum<256>(sums, 6, red);
   if (threadIdx.x == 0) {
     double *dst = a.part + ((long long)sysb * gridDim.x + blockIdx.x) * 8;
     for (int c = 0; c < 6; ++c) dst[c] = sums[c];
+  }
+}
+
+template <typename T, int SCH> __global__ __launch_bounds__(256) void k_refine_div(RefineArgs<T> a) {
+  const int sysb = blockIdx.y;
+  if (a.st[sysb].done) return;
+  const long long N = a.d.N;
+  const int n1 = a.d.n1, n2 = a.d.n2, n3 = a.d.n3;
+  const double *sig = a.sig + sysb * 6 * N;
+  T *fref = a.fref + sysb * 3 * N;
+  static constexpr int vo[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};  // Voigt index of (i, j)
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    // node (x, y, z) gathers the cells (x - a, y - b, z - d)
+    const int x = (int)(i % n1);
+    const long long row = i / n1;
+    const int y = (int)(row % n2), z = (int)(row / n2);
+    const int xm = (x + n1 - 1) % n1, ym = (y + n2 - 1) % n2, zm = (z + n3 - 1) % n3;
+    const long long r00 = row * n1, r10 = ((long long)z * n2 + ym) * n1;
+    const long long r01 = ((long long)zm * n2 + y) * n1, r11 = ((long long)zm * n2 + ym) * n1;
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 6; ++c) {
+      const double *sc = sig + c * N;
+      // s[a][b][d]: the cell node - (a, b, d)
+      const double sv[2][2][2] = {{{sc[r00 + x], sc[r01 + x]}, {sc[r10 + x], sc[r11 + x]}},
+                                  {{sc[r00 + xm], sc[r01 + xm]}, {sc[r10 + xm], sc[r11 + xm]}}};
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j)
+          if (vo[r][j] == c) f[r] += Stencil<SCH>::div(sv, j, a.ih);
+    }
+    for (int r = 0; r < 3; ++r) fref[r * N + i] = (T)(-f[r]);
   }
 }
 

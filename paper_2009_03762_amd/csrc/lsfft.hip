@@ -490,7 +490,7 @@ void drop_graph(lsfft_solver s) {
 }
 
 // Start of a refinement cycle (systems not done): fold delta into u, then
-// the FP64 residual force of u and its mean stress (k_refine_force).
+// the FP64 cell stress of u, its mean and its divergence at the nodes.
 template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
   const long long n3 = 3 * s->d.N;
   const unsigned fb = (unsigned)std::min<long long>((n3 + 255) / 256, 4096);
@@ -504,14 +504,21 @@ template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
   a.mu = s->mu64;
   a.sstar = s->sstar64;
   a.mem = (const lsfft::Member<T> *)s->mem;
+  a.sig = s->rsig;
   a.fref = (T *)s->fref;
   a.part = s->rpart;
   a.st = s->st;
   for (int r = 0; r < 3; ++r) a.ih[r] = 1.0 / s->h[r];
-  if (s->scheme == LSFFT_FB)
-    hipLaunchKernelGGL((lsfft::k_refine_force<T, lsfft::SCHEME_FB>), dim3(s->nrb, s->B), dim3(256), 0, s->stream, a);
-  else
-    hipLaunchKernelGGL((lsfft::k_refine_force<T, lsfft::SCHEME_AFB>), dim3(s->nrb, s->B), dim3(256), 0, s->stream, a);
+  const dim3 grid(s->nrb, s->B);
+  if (s->scheme == LSFFT_FB) {
+    hipLaunchKernelGGL((lsfft::k_refine_stress<T, lsfft::SCHEME_FB>), grid, dim3(256), 0, s->stream, a);
+    LSFFT_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((lsfft::k_refine_div<T, lsfft::SCHEME_FB>), grid, dim3(256), 0, s->stream, a);
+  } else {
+    hipLaunchKernelGGL((lsfft::k_refine_stress<T, lsfft::SCHEME_AFB>), grid, dim3(256), 0, s->stream, a);
+    LSFFT_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((lsfft::k_refine_div<T, lsfft::SCHEME_AFB>), grid, dim3(256), 0, s->stream, a);
+  }
   LSFFT_CHECK(hipGetLastError());
   hipLaunchKernelGGL(lsfft::k_refine_mean, dim3(s->B), dim3(64), 0, s->stream, s->rpart, s->nrb, s->sref, s->st,
                      (double)s->d.N);
@@ -773,7 +780,7 @@ void release(lsfft_solver s) {
   void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm,
                   s->sstar, s->fstar, s->smean, s->counter, s->du, s->sref, s->lam64, s->mu64, s->sstar64,
-                  s->rpart, s->fref, s->mem_ref};
+                  s->rpart, s->fref, s->mem_ref, s->rsig};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -1184,6 +1191,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     const size_t n3 = B * 3 * (size_t)N;
     s->nrb = (int)std::min<long long>((N + 255) / 256, 2048);
     if (hipMalloc(&s->du, n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (hipMalloc(&s->rsig, 2 * n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->fref, n3 * sizeof(float)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->sref, B * 6 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->lam64, B * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   reduce_decide(a, sysb, vals);
 }
 
-// Iterative refinement of the F32 displacement form (see k_refine_force):
+// Iterative refinement of the F32 displacement form (see k_refine_stress):
 // u_b += delta, delta = 0.
 __global__ __launch_bounds__(256) void k_refine_fold(double *u, double *du, const State *st, long long n) {
   const int sysb = blockIdx.y;

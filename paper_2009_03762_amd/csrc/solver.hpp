@@ -176,11 +176,12 @@ struct lsfft_solver_s {
   // iterations (0 = off).  u holds u_b, du the correction delta that the F32
   // sweeps iterate on; fref = -F_b [B][3][N] (T) and sref [B][6] are the
   // load and the mean-stress offset of those sweeps; lam64, mu64 (and
-  // sstar64 with an eigenstrain) the FP64 data of the residual evaluation;
-  // mem_ref the per-system constants with Ebar = 0; rpart the block sums of
-  // k_refine_force (nrb rows per system).
+  // sstar64 with an eigenstrain) the FP64 data of the residual evaluation,
+  // rsig its cell stress [B][6][N]; mem_ref the per-system constants with
+  // Ebar = 0; rpart the block sums of k_refine_stress (nrb rows per system).
   int refine = 0;
   double *du = nullptr, *sref = nullptr, *lam64 = nullptr, *mu64 = nullptr, *sstar64 = nullptr, *rpart = nullptr;
+  double *rsig = nullptr;
   void *fref = nullptr, *mem_ref = nullptr;
   int nrb = 0;
 };
