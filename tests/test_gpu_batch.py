@@ -167,3 +167,45 @@ def test_graph_replay_matches_eager(L, prec, form, monkeypatch):
         assert np.array_equal(ia, ib)
         assert np.array_equal(sa_, sb)
         assert np.array_equal(ea, eb)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_handles_on_streams_solve_concurrently(L, prec):
+    """Separate handles, each on its own stream, solved at the same time from
+    host threads (the library call releases the GIL): every result equals the
+    same handle's solve on its own, bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
+    print(f"\n[streams] {prec}", flush=True)
+    shapes = [(16, 16, 16), (24, 12, 32), (8, 8, 8)]
+    Eb = np.array([1e-3, 0.0, 0.0, 0.0, 0.0, 5e-4])
+    jobs = []
+    for k, shape in enumerate(shapes):
+        systems = _cells(shape, (10.0, 1e2))
+        stream = torch.cuda.Stream()
+        h = L.create_batch(systems, scheme="afb", prec=prec, stream=stream)
+        dev = torch.zeros((len(systems), 6) + shape, dtype=_dt(prec), device="cuda")
+        jobs.append((h, stream, np.tile(Eb, (len(systems), 1)), dev))
+
+    def run(job):
+        h, stream, Ebs, dev = job
+        return L.solve_batch(h, Ebs, 1e-9, 3000, eps_dev=dev)
+
+    try:
+        alone = []
+        for job in jobs:
+            out = run(job)
+            torch.cuda.synchronize()
+            alone.append((out, job[3].cpu().numpy()))
+        for job in jobs:
+            job[3].zero_()
+        torch.cuda.synchronize()
+        with ThreadPoolExecutor(max_workers=len(jobs)) as pool:
+            together = list(pool.map(run, jobs))
+        torch.cuda.synchronize()
+        for (a, eps_a), b, job in zip(alone, together, jobs):
+            assert np.array_equal(a[2], b[2])            # iterations per system
+            assert np.array_equal(a[1], b[1])            # mean stress
+            assert np.array_equal(eps_a, job[3].cpu().numpy())
+    finally:
+        for job in jobs:
+            L.destroy(job[0])
