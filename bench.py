@@ -554,19 +554,28 @@ print(json.dumps({{"seconds": ts[-1] - ts[0], "iters": {iters}}}))
     }
 
 
-def copy_probe(gib=1.0, reps=5):
-    """A plain device-to-device copy of known size (calibrates HBM byte counters)."""
+def copy_bandwidth(gib=1.0, reps=5):
+    """Read + write GB/s of a plain device-to-device copy of `gib` GiB (after
+    one untimed copy): the bandwidth a streaming kernel can reach here."""
     import torch
     n = int(gib * (1 << 30) // 4)
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    b.copy_(a)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         b.copy_(a)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GBps_read_plus_write": 2 * n * 4 / dt / 1e9}))
+    del a, b
+    return n * 4, 2 * n * 4 / dt / 1e9
+
+
+def copy_probe(gib=1.0, reps=5):
+    """A plain device-to-device copy of known size (calibrates HBM byte counters)."""
+    nbytes, gbs = copy_bandwidth(gib, reps)
+    print(json.dumps({"copy_bytes_each_way": nbytes, "reps": reps, "GBps_read_plus_write": gbs}))
 
 
 def main():
@@ -635,6 +644,12 @@ def main():
         "kernels": head["kernels"],
         "autotune": head["autotune"],
     }
+    # the same fractions against what a plain device copy reaches on this GPU
+    _, copy_gbs = copy_bandwidth()
+    line["copy_GBps"] = copy_gbs
+    line["whole_iteration_frac_of_copy"] = head["whole_iteration_hbm_frac"] * HBM_PEAK_GBS / copy_gbs
+    if head["roofline"] and head["roofline"].get("achieved"):
+        line["roofline_frac_of_copy"] = head["roofline"]["achieved"] / copy_gbs
     if res32 is not None and res64 is not None:
         line["fp64"] = {k: res64[k] for k in ("value", "ms_per_step", "roofline", "whole_iteration_hbm_frac",
                                                "whole_iteration_frac_fixed_balg",
