@@ -213,3 +213,20 @@ def test_f64_ignores_refine_and_strain_form_rejects_it(L):
         with pytest.raises(L.LsfftError) as e:
             L.create(lam, mu, l0, m0, prec="f32", refine=8, **kw)
         assert e.value.status == L.EINVAL
+
+
+def test_tuned_schedule_keeps_the_refined_solve(L):
+    """The schedule tuner times the refined sweeps of the handle; the solve
+    after tuning stops at the same iteration with the same fields (only the
+    order of FP64 partial sums may change)."""
+    print("\n[refine + autotune]", flush=True)
+    lam, mu, l0, m0 = _inclusion((16, 16, 32), (8, 8, 16), 10.0)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", refine=8)
+    a = s.solve(EB, tol=1e-10, maxit=2000)
+    sch, _, _ = L.autotune(s.handle, 8)
+    b = s.solve(EB, tol=1e-10, maxit=2000)
+    s.close()
+    assert a["status"] == b["status"] == L.OK
+    assert abs(a["iters"] - b["iters"]) <= 1
+    assert rel(b["eps"], a["eps"]) < 1e-6
+    assert set(sch) == {"stencil_planes", "y_cols", "z_cols", "xcd_order"}
