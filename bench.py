@@ -520,6 +520,37 @@ def refine_study(n=256, tols=(1e-6, 1e-8), maxit=1500):
     return out
 
 
+def size_sweep(sizes=(32, 64, 128, 192, 256, 384, 512)):
+    """Throughput of the benchmark workload (AFB, contrast 1e3, tol 0) across
+    grid sizes, both precisions, automatic form, tuned schedule, replayed
+    iteration graphs: where the path is launch-bound and where it streams."""
+    import torch
+
+    from paper_2009_03762_amd import lsfft
+    out = []
+    for n in sizes:
+        lam, mu, l0, m0, Eb = workload(n)
+        for prec in ("f32", "f64"):
+            s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec)
+            sched, ms0, ms1 = lsfft.autotune(s.handle, 16)
+            steps = int(max(20, min(800, 4e9 / n ** 3)))
+            s.solve_device(Eb, tol=0.0, maxit=10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve_device(Eb, tol=0.0, maxit=steps)
+            torch.cuda.synchronize()
+            T = time.perf_counter() - t0
+            # the strain form has no stencil (its schedule reports 0 planes)
+            form = "displacement" if sched["stencil_planes"] > 0 else "strain"
+            row = {"n": n, "prec": prec, "form": form, "steps": steps, "ms_per_iter": T / steps * 1e3,
+                   "GVoxel_iter_per_s": n ** 3 * steps / T / 1e9, "schedule": sched}
+            out.append(row)
+            print(f"[bench] size sweep {row}", file=sys.stderr, flush=True)
+            s.close()
+            torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n=128, iters=8):
     """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
     full iterations after setup, single-threaded numpy."""
@@ -594,6 +625,8 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the bench line: throughput from 32^3 to 512^3, both precisions")
     ap.add_argument("--refine-study", action="store_true",
                     help="instead of the bench line: time to a certified tolerance with FP64 refinement")
     ap.add_argument("--form", choices=["strain", "displacement"], default="displacement")
@@ -613,6 +646,9 @@ def main():
         return
     if args.refine_study:
         print(json.dumps(refine_study(args.size)), flush=True)
+        return
+    if args.size_sweep:
+        print(json.dumps(size_sweep()), flush=True)
         return
     tune = not args.no_autotune
     res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form, tune) \

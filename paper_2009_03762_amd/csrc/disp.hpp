@@ -499,20 +499,31 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   if (a.counter) last_block_reduce<WG>(a.red, a.counter, sysb, red);
 }
 
-// Register-resident variant for power-of-two n1: every thread owns fixed x
-// columns (XV of them) of one y-group and keeps its own displacement planes,
-// edge differences and sigma planes in registers; LDS only carries the column
-// exchange with the x +- 1 neighbours, the f lines and the transform scratch.
-// A workgroup holds G = 256 / n1 independent y-groups when n1 < 256.  The FP64
-// u exchange is single-buffered: each plane is published once and the x
-// differences it yields are kept for the next step.  The z-march is unrolled
-// by two so that the per-plane buffers alternate by name (index P = z & 1)
-// instead of being copied.
+// Register-resident variant for n1 = 2^a or 3 * 2^a: every thread owns fixed
+// x columns (XV of them) of one y-group and keeps its own displacement
+// planes, edge differences and sigma planes in registers; LDS only carries
+// the column exchange with the x +- 1 neighbours, the f lines and the
+// transform scratch.  The workgroup has WG = 256 threads for a power-of-two
+// n1 and 192 for 3 * 2^a, so that it splits evenly into x columns; it holds
+// G = WG / n1 independent y-groups when n1 < WG.  The FP64 u exchange is
+// single-buffered: each plane is published once and the x differences it
+// yields are kept for the next step.  The z-march is unrolled by two so that
+// the per-plane buffers alternate by name (index P = z & 1) instead of being
+// copied.
 #ifndef LSFFT_STENCIL_WAVES
 #define LSFFT_STENCIL_WAVES 1
 #endif
+constexpr bool pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
+constexpr int stencil_wg_of(int n1) { return pow2_len(n1) ? 256 : 192; }
+// Waves per SIMD the compiler must leave room for: two for the FP32
+// 192-thread kernels up to 192 columns (the 96-column AFB one would otherwise
+// take 269 registers and run one wave; two waves with a small spill are
+// faster), the compiler's own choice otherwise.
+template <typename T, int N1> constexpr int stencil_min_waves() {
+  return (sizeof(T) == 4 && !pow2_len(N1) && N1 <= 192) ? 2 : LSFFT_STENCIL_WAVES;
+}
 template <typename T, int N1, int E, int SCHEME, int T2>
-__global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<T> a) {
+__global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) void k_stencil_reg(SArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
   stencil_member(a, sysb);
@@ -523,7 +534,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
   for (int q1 = 0; q1 < 3; ++q1)
 #pragma unroll
     for (int q2 = 0; q2 < 3; ++q2) hE[q1][q2] = a.mem[sysb].hE[q1][q2];
-  constexpr int WG = 256;
+  constexpr int WG = stencil_wg_of(N1);
   constexpr int L = N1 / 2;
   constexpr int TPC = L / E;
   constexpr int G = N1 >= WG ? 1 : WG / N1;     // y-groups per workgroup
@@ -533,7 +544,7 @@ __global__ __launch_bounds__(256, LSFFT_STENCIL_WAVES) void k_stencil_reg(SArgs<
   constexpr int UX = G * NUL * 3 * N1;           // the exchanged u plane (FP64)
   constexpr int SX = G * NSL * 6 * N1;           // one exchanged sigma plane
   constexpr int NPEN = G * T2 * 3;
-  static_assert(G * NX == WG, "n1 must be a power of two");
+  static_assert(G * NX == WG, "the workgroup must split evenly into x columns");
   static_assert(NPEN * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
   static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
   static_assert((NPEN + 1) * 2 * L * 2 <= SX, "transform scratch must fit in one sigma plane");

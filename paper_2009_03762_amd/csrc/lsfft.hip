@@ -686,11 +686,11 @@ template <typename T> lsfft_status upload_moduli(lsfft_solver s, const lsfft_con
   return LSFFT_OK;
 }
 
-// y-blocks of a stencil plane: a power-of-two n1 < 256 packs 256/n1
-// independent y-groups per workgroup.
+// y-blocks of a stencil plane: the register stencil packs several
+// independent y-groups per workgroup when n1 is shorter than the workgroup.
 int stencil_yblocks(const lsfft_solver s) {
   const int n1 = s->n[0];
-  const int G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
+  const int G = stencil_groups(n1);
   return (s->n[1] + G * ST2 - 1) / (G * ST2);
 }
 

@@ -81,13 +81,21 @@ constexpr int es_of(int L) {
 #define LSFFT_ST2 2
 #endif
 constexpr int ST2 = LSFFT_ST2;
-constexpr bool stencil_reg_kernel(int n1) { return (n1 & (n1 - 1)) == 0 && n1 >= 8; }
+// The register-resident stencil takes n1 = 2^a >= 8 and 3 * 2^a in [12, 384]
+// (256- and 192-thread workgroups); other lengths use the LDS stencil.
+constexpr bool stencil_reg_kernel(int n1) {
+  return lsfft::pow2_len(n1) ? n1 >= 8 : (n1 % 3 == 0 && lsfft::pow2_len(n1 / 3) && n1 >= 12 && n1 <= 384);
+}
+// y-groups per register-stencil workgroup
+constexpr int stencil_groups(int n1) {
+  return (stencil_reg_kernel(n1) && n1 < lsfft::stencil_wg_of(n1)) ? lsfft::stencil_wg_of(n1) / n1 : 1;
+}
 // LDS of the stencil kernels (n1 values per line): the register-resident one
 // holds one FP64 u plane (T2+2 lines x 3) per y-group, two sigma planes
 // (T2+1 lines x 6), the f lines (T2 x 3) and the x twiddles; the other one
 // two u planes.
 template <typename T> constexpr long long stencil_lds(int n1) {
-  const long long G = (stencil_reg_kernel(n1) && n1 < 256) ? 256 / n1 : 1;
+  const long long G = stencil_groups(n1);
   const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
   const long long twiddles = stencil_reg_kernel(n1) ? 2LL * n1 * (long long)sizeof(T) : 0;
   return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + twiddles +

@@ -1,6 +1,6 @@
 """Edge cases of the 3D solver against the oracle, through the C ABI: the
 shortest (4) and longest (512) supported axis lengths and radix-3 lengths in
-every position, anisotropic grid spacing for every scheme and form (also with
+every position (x lengths 12 to 384 in both stencil kernels), anisotropic grid spacing for every scheme and form (also with
 an eigenstrain and for the DGO), a soft inclusion (contrast < 1), zero
 macroscopic strain, maxit = 0, and a tolerance met at the first pass."""
 import numpy as np
@@ -32,7 +32,10 @@ def _cell(n, chi, seed=0):
     return lam, mu, 0.5 * (lam.min() + lam.max()), 0.5 * (mu.min() + mu.max())
 
 
-SHAPES = [(4, 4, 4), (4, 6, 8), (6, 4, 4), (512, 4, 4), (4, 512, 4), (4, 4, 512), (384, 6, 4), (8, 384, 12)]
+# (n3, n2, n1); n1 = 12, 96, 192, 384 take the register stencil with
+# 192-thread workgroups (16, 2, 1 y-groups, and two columns per thread at 384)
+SHAPES = [(4, 4, 4), (4, 6, 8), (6, 4, 4), (512, 4, 4), (4, 512, 4), (4, 4, 512), (384, 6, 4), (8, 384, 12),
+          (4, 6, 96), (6, 4, 192), (4, 4, 384)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)

@@ -62,13 +62,15 @@ def _inclusion(shape, side, chi):
 
 @pytest.mark.parametrize("scheme,n", [("afb", 24), ("fb", 16)])
 def test_reaches_fp64_tolerance(L, scheme, n):
-    """Contrast 10, tol 1e-10 (three orders below the F32 floor): stop in the
+    """Contrast 10, tol 1e-9 (orders below the F32 floor): stop in the
     oracle's iteration count (+-2) with the oracle's iterate, where plain F32
-    does not converge in three times as many iterations."""
-    tol = 1e-10
+    does not converge in three times as many iterations.  Cycles of 8 keep the
+    FP32 rounding of the last cycle, relative to the residual at its start,
+    well below the final residual."""
+    tol = 1e-9
     print(f"\n[refine tol] {scheme} n={n} tol={tol}", flush=True)
     lam, mu, l0, m0 = _inclusion((n, n, n), (n // 2,) * 3, 10.0)
-    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=16)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=8)
     out = s.solve(EB, tol=tol, maxit=5000)
     hist = s.residual_history()
     s.close()
