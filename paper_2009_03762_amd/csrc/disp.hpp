@@ -504,7 +504,8 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 // planes, edge differences and sigma planes in registers; LDS only carries
 // the column exchange with the x +- 1 neighbours, the f lines and the
 // transform scratch.  The workgroup has WG = 256 threads for a power-of-two
-// n1 and 192 for 3 * 2^a, so that it splits evenly into x columns; it holds
+// n1 up to 256 and 192 for 3 * 2^a up to 192, n1 threads beyond: it splits
+// evenly into x columns, one per thread from 192 columns on, and holds
 // G = WG / n1 independent y-groups when n1 < WG.  The FP64 u exchange is
 // single-buffered: each plane is published once and the x differences it
 // yields are kept for the next step.  The z-march is unrolled by two so that
@@ -514,7 +515,10 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 #define LSFFT_STENCIL_WAVES 1
 #endif
 constexpr bool pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
-constexpr int stencil_wg_of(int n1) { return pow2_len(n1) ? 256 : 192; }
+constexpr int stencil_wg_of(int n1) {
+  const int base = pow2_len(n1) ? 256 : 192;
+  return n1 > base ? n1 : base;
+}
 // Waves per SIMD the compiler must leave room for: two for the FP32
 // 192-thread kernels up to 192 columns (the 96-column AFB one would otherwise
 // take 269 registers and run one wave; two waves with a small spill are

@@ -77,6 +77,10 @@ constexpr int XWG = 256;
 constexpr int es_of(int L) {
   return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
 }
+// Points per thread of the register stencil's x-transforms: four on
+// power-of-two lines (at most 64 threads per line, inside one wavefront),
+// es_of on 3 * 2^a.
+constexpr int esr_of(int L) { return (L % 3 == 0) ? es_of(L) : (L < 4 ? L : 4); }
 #ifndef LSFFT_ST2
 #define LSFFT_ST2 2
 #endif
