@@ -691,7 +691,8 @@ template <typename T> lsfft_status upload_moduli(lsfft_solver s, const lsfft_con
 int stencil_yblocks(const lsfft_solver s) {
   const int n1 = s->n[0];
   const int G = stencil_groups(n1);
-  return (s->n[1] + G * ST2 - 1) / (G * ST2);
+  const int t2 = (s->prec == LSFFT_F32) ? st2_of<float>(n1) : st2_of<double>(n1);
+  return (s->n[1] + G * t2 - 1) / (G * t2);
 }
 
 // Grids of the passes for the solver's schedule: planes per stencil

@@ -85,6 +85,9 @@ constexpr int esr_of(int L) { return (L % 3 == 0) ? es_of(L) : (L < 4 ? L : 4); 
 #define LSFFT_ST2 2
 #endif
 constexpr int ST2 = LSFFT_ST2;
+// Node lines owned per y-group of a stencil workgroup: ST2, and one for FP64
+// beyond 256 columns, where two would not fit in LDS.
+template <typename T> constexpr int st2_of(int n1) { return (sizeof(T) == 8 && n1 > 256) ? 1 : ST2; }
 // The register-resident stencil takes n1 = 2^a >= 8 and 3 * 2^a in [12, 384]
 // (256- and 192-thread workgroups); other lengths use the LDS stencil.
 constexpr bool stencil_reg_kernel(int n1) {
@@ -102,7 +105,8 @@ template <typename T> constexpr long long stencil_lds(int n1) {
   const long long G = stencil_groups(n1);
   const long long uplanes = stencil_reg_kernel(n1) ? 1 : 2;
   const long long twiddles = stencil_reg_kernel(n1) ? 2LL * n1 * (long long)sizeof(T) : 0;
-  return G * n1 * (uplanes * (ST2 + 2) * 3 * 8 + (2 * (ST2 + 1) * 6 + ST2 * 3) * (long long)sizeof(T)) + twiddles +
+  const long long t2 = st2_of<T>(n1);
+  return G * n1 * (uplanes * (t2 + 2) * 3 * 8 + (2 * (t2 + 1) * 6 + t2 * 3) * (long long)sizeof(T)) + twiddles +
          256;
 }
 template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
