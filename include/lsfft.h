@@ -106,7 +106,7 @@ typedef struct {
                               divergence applied as real-space stencils, three
                               transformed components; identical iterates).
                               Automatic picks 2 when its workgroup fits in LDS
-                              (every n1 in F32, n1 <= 256 in F64).           */
+                              (every n1 in F32, n1 <= 384 in F64).           */
   int32_t f64_warmup;      /* F32 displacement form with n1 <= 256 only (else
                               ignored): run the first f64_warmup iterations of
                               every solve in FP64 on the same displacement
