@@ -551,6 +551,22 @@ def size_sweep(sizes=(32, 64, 128, 192, 256, 384, 512)):
     return out
 
 
+def oracle_timing(plan=((16, 100), (64, 10), (128, 4), (256, 1))):
+    """The FP64 numpy oracle (its own FFT path) on one host core: seconds per
+    iteration and GVoxel-iter/s of the benchmark cell at several sizes,
+    `iters` full iterations each after setup."""
+    out = []
+    for n, iters in plan:
+        r = cpu_baseline(n, iters)
+        if "error" in r:
+            out.append({"n": n, "error": r["error"]})
+            continue
+        out.append({"n": n, "iters": iters, "s_per_iter": n ** 3 / (r["value"] * 1e9),
+                    "GVoxel_iter_per_s": r["value"], "cores": r["cores"]})
+        print(f"[bench] oracle timing {out[-1]}", file=sys.stderr, flush=True)
+    return {"host_cpus": os.cpu_count(), "runs": out}
+
+
 def cpu_baseline(n=128, iters=8):
     """Time the oracle (as it stands) on the host: same cell at n^3, `iters`
     full iterations after setup, single-threaded numpy."""
@@ -625,6 +641,8 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="instead of the bench line: the CPU oracle's speed at 16^3 to 256^3 (one core)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the bench line: throughput from 32^3 to 512^3, both precisions")
     ap.add_argument("--refine-study", action="store_true",
@@ -649,6 +667,9 @@ def main():
         return
     if args.size_sweep:
         print(json.dumps(size_sweep()), flush=True)
+        return
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
         return
     tune = not args.no_autotune
     res32 = run_gpu("f32", args.size, args.steps, args.warmup, not args.no_breakdown, args.form, tune) \
