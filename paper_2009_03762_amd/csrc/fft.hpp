@@ -128,7 +128,15 @@ template <typename T, bool FWD, int R> __device__ __forceinline__ void bfly(cplx
 // uniform counter `buf` carries the parity across calls), so one barrier per
 // exchange suffices: a buffer is rewritten only after the barrier of the
 // exchange in between, which every thread reaches after its last read of it.
-template <typename T, int L, int E, bool FWD, int P>
+// WAVE: every thread of the pencil lies in one wavefront and the scratch is
+// the pencil's own, so the exchange is ordered at wavefront scope (a wave's
+// LDS accesses complete in order) instead of by a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <typename T, int L, int E, bool FWD, int P, bool WAVE = false>
 struct StockhamPass {
   __device__ __forceinline__ static void run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
                                              const cplx<T> *__restrict__ tw, int ts, int &buf) {
@@ -170,21 +178,24 @@ struct StockhamPass {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = out[e];
     } else {
-      __syncthreads();
+      if constexpr (WAVE)
+        wave_sync();
+      else
+        __syncthreads();
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = sb[(t + TPC * e) * ms];
       buf ^= 1;
-      StockhamPass<T, L, E, FWD, P + 1>::run(v, t, lds, ms, tw, ts, buf);
+      StockhamPass<T, L, E, FWD, P + 1, WAVE>::run(v, t, lds, ms, tw, ts, buf);
     }
   }
 };
 
 // One transform of a pencil; `buf` is the workgroup-uniform buffer parity,
 // to be carried from one call to the next (start at 0).
-template <typename T, int L, int E, bool FWD>
+template <typename T, int L, int E, bool FWD, bool WAVE = false>
 __device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
                                            const cplx<T> *__restrict__ tw, int ts, int &buf) {
-  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0>::run(v, t, lds, ms, tw, ts, buf);
+  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0, WAVE>::run(v, t, lds, ms, tw, ts, buf);
 }
 
 // Copy a twiddle table of NT entries into LDS with all threads of the

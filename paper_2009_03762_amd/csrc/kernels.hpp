@@ -121,6 +121,10 @@ __device__ __forceinline__ void partner(const cplx<T> (&v)[E], cplx<T> (&pv)[E],
   }
 }
 
+// The line transforms below run on lines that lie in one wavefront with
+// scratch of their own (every caller asserts 64 % TPC == 0), so their radix
+// exchanges are ordered at wavefront scope.
+//
 // Inverse real transform of one x-line.  In: v[e] = X[k], k = t + TPC e,
 // k in [0, L), and xn = X[L] (meaningful in thread t = 0).  Out: v[e] =
 // (x[2m], x[2m+1]) for m = t + TPC e: the unnormalised inverse real DFT of
@@ -143,7 +147,7 @@ __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int
       v[e] = (v[e] + xp) + mul_i(w * (v[e] - xp));
     }
   }
-  fft_pencil<T, L, E, false>(v, t, lds, 1, tw, 2, buf);
+  fft_pencil<T, L, E, false, true>(v, t, lds, 1, tw, 2, buf);
 }
 
 // Forward real transform of one x-line.  In: v[e] = (x[2m], x[2m+1]).
@@ -153,7 +157,7 @@ template <typename T, int L, int E>
 __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cplx<T> *lds,
                                             const cplx<T> *__restrict__ tw, int &buf) {
   constexpr int TPC = L / E;
-  fft_pencil<T, L, E, true>(v, t, lds, 1, tw, 2, buf);
+  fft_pencil<T, L, E, true, true>(v, t, lds, 1, tw, 2, buf);
   cplx<T> pv[E];
   partner<T, E, TPC>(v, pv, t, lane);
   cplx<T> xn{T(0), T(0)};
