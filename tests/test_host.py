@@ -137,3 +137,14 @@ def test_1d_dgo_needs_a_macroscopic_strain(L):
     with pytest.raises(L.LsfftError) as e:
         L.solve_1d(np.ones(8), 1.0, 0.0, scheme="dgo", disc="pcd")
     assert e.value.status == L.EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py is a one-GPU measurement: --gpus above 1 exits with status 2
+    and says so, before touching any device."""
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
