@@ -60,6 +60,28 @@ def test_laminate_256_closed_form(L, prec, form):
     s.close()
 
 
+@pytest.mark.parametrize("n1", [192, 384, 512])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_laminate_wide_x_closed_form(L, n1, prec):
+    """Layers normal to x on 24 x 32 x n1 grids: the register stencil with
+    192-, 384- and 512-thread workgroups (FP64 at 512 columns: strain form)
+    against the laminate closed form."""
+    print(f"\n[laminate wide x] n1={n1} prec={prec}", flush=True)
+    lam, mu = inputs.laminate((n1, 32, 24), seed=n1, E_range=(1.0, 10.0))
+    lam1, mu1 = lam[0, 0], mu[0, 0]
+    l0 = 0.5 * (lam1.min() + lam1.max())
+    m0 = 0.5 * (mu1.min() + mu1.max())
+    Eb = np.array([1e-3, 2e-4, -3e-4, 1e-4, 5e-5, 2e-4])
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", prec=prec)
+    tol = 1e-11 if prec == "f64" else 5e-6
+    out = s.solve(Eb, tol=tol, maxit=3000)
+    s.close()
+    assert out["status"] == L.OK, out["residual"]
+    exact = bounds.laminate_strain(lam1, mu1, Eb)
+    exact = np.broadcast_to(exact[:, None, None, :], out["eps"].shape)
+    assert rel(out["eps"], exact) < (1e-9 if prec == "f64" else 1e-5)
+
+
 def test_homogeneous_256_exact(L):
     lam = np.full((N, N, N), 3.0)
     mu = np.full((N, N, N), 2.0)
