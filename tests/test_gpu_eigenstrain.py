@@ -166,6 +166,28 @@ def test_laminate_128_closed_form(L, prec, form):
     assert err < (1e-9 if prec == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("n1", [192, 384, 512])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_laminate_wide_x_closed_form(L, n1, prec):
+    """The same closed form on 16 x 24 x n1 grids: the register stencil with
+    192-, 384- and 512-thread workgroups subtracting the eigenstress force
+    (FP64 at 512 columns: strain form)."""
+    print(f"\n[eig laminate wide x] n1={n1} {prec}", flush=True)
+    lam, mu = inputs.laminate((n1, 24, 16), seed=n1 + 1, E_range=(1.0, 10.0))
+    lam1, mu1 = lam[0, 0], mu[0, 0]
+    e1 = 1e-3 * np.random.default_rng(n1).standard_normal((6, n1))
+    es = np.ascontiguousarray(np.broadcast_to(e1[:, None, None, :], (6,) + lam.shape))
+    l0, m0 = 0.5 * (lam1.min() + lam1.max()), 0.5 * (mu1.min() + mu1.max())
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec=prec, eigenstrain=es)
+    out = s.solve(EB, tol=1e-10 if prec == "f64" else 0.0, maxit=400)
+    s.close()
+    exact = bounds.laminate_strain_eig(lam1, mu1, EB, e1)
+    if prec == "f64":
+        assert out["status"] == L.OK
+    err = rel(out["eps"], np.broadcast_to(exact[:, None, None, :], out["eps"].shape))
+    assert err < (1e-9 if prec == "f64" else 1e-5)
+
+
 def test_batch_with_and_without_eigenstrain(L):
     shape = (16, 12, 8)
     cells = []
