@@ -107,7 +107,7 @@ typedef struct {
                               transformed components; identical iterates).
                               Automatic picks 2 when its workgroup fits in LDS
                               (every n1 in F32, n1 <= 384 in F64).           */
-  int32_t f64_warmup;      /* F32 displacement form with n1 <= 256 only (else
+  int32_t f64_warmup;      /* F32 displacement form with n1 <= 384 only (else
                               ignored): run the first f64_warmup iterations of
                               every solve in FP64 on the same displacement
                               (identical iterates up to rounding), then

@@ -155,3 +155,20 @@ def test_1d_anisotropic_spacing(L):
     for b in range(3):
         E = solve1d.solve_gfp_1d(C[b], 1e-3, CH[b], scheme="FD", tol=0.0, maxit=12, disc="PCD", h=0.25)[0]
         assert rel(out["E"][b], E) < 1e-12
+
+
+@pytest.mark.parametrize("n1", [192, 384])
+def test_f64_warmup_wide_x(L, n1):
+    """The FP64 warm start where the FP64 stencil runs with 192 threads (192)
+    and with one owned node line per y-group (384)."""
+    print(f"\n[warm wide x] n1={n1}", flush=True)
+    K, warm = 8, 3
+    lam, mu, l0, m0 = _cell((4, 6, n1), 10.0, seed=n1)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", f64_warmup=warm)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K)
+    assert out["iters"] == K
+    assert rel(hist[:warm], np.array(ref.history[:warm])) < 1e-9
+    assert rel(out["eps"], ref.eps) < 1e-5
