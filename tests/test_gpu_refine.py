@@ -248,3 +248,26 @@ def test_fixed_iterations_wide_x(L, n1):
     assert out["iters"] == K
     assert rel(out["eps"], ref.eps) < 1e-6
     assert rel(hist, np.array(ref.history)) < 1e-3
+
+
+def test_batch_mixing_eigenstrain(L):
+    """A refined batch in which one system has an eigenstrain and one has
+    none: each follows its own oracle solve."""
+    print("\n[refine batch eigenstrain]", flush=True)
+    lam, mu, l0, m0 = _inclusion((12, 16, 16), (6, 8, 8), 10.0)
+    es = 1e-3 * np.random.default_rng(21).standard_normal((6,) + lam.shape)
+    h = L.create_batch([(lam, mu, l0, m0, es), (lam, mu, l0, m0)], scheme="afb", prec="f32", form="displacement",
+                       refine=8)
+    try:
+        dev = torch.zeros((2, 6) + lam.shape, dtype=torch.float32, device="cuda")
+        st, sm, it, r, bst = L.solve_batch(h, np.stack([EB, 2 * EB]), 1e-9, 3000, eps_dev=dev)
+        torch.cuda.synchronize()
+        eps = dev.cpu().double().numpy()
+    finally:
+        L.destroy(h)
+    for b, (E, e_star) in enumerate(((EB, es), (2 * EB, None))):
+        assert bst[b] == L.OK and r[b] <= 1e-9
+        k_ref, _, got = _oracle_at(lam, mu, E, l0, m0, "AFB", 1e-9, int(it[b]), eigenstrain=e_star)
+        assert k_ref is not None and abs(int(it[b]) - k_ref) <= 2
+        assert rel(eps[b], got["eps"]) < 1e-6
+        assert rel(sm[b], got["sig_mean"]) < 1e-6
