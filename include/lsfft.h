@@ -224,8 +224,11 @@ int32_t lsfft_batch_size(lsfft_solver s);
  * (f64_warmup) keep their default one. */
 typedef struct {
   int32_t stencil_planes; /* z-planes per stencil workgroup in the displacement
-                             form: an even divisor of n3 (2 .. 32 are offered
-                             by lsfft_autotune); 0 in the strain form       */
+                             form: an even divisor of n3 (powers of two
+                             from 2 to 128 are offered by lsfft_autotune;
+                             the default is the largest of 4 .. 128 that
+                             keeps 512 workgroups over the batch); 0 in the
+                             strain form                                     */
   int32_t y_cols;         /* pencils (consecutive x columns) per y-pass
                              workgroup: the default or its alternative, one
                              of two values fixed by n2 and the precision    */

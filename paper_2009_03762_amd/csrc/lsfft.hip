@@ -1010,7 +1010,7 @@ lsfft_status autotune(lsfft_solver s, int iterations, lsfft_schedule *best, doub
   };
   if (st == LSFFT_OK && s->disp) {
     const int z0 = cur.stencil_planes;
-    for (int z = 2; z <= 32 && st == LSFFT_OK; z *= 2) {
+    for (int z = 2; z <= 128 && st == LSFFT_OK; z *= 2) {
       if (z == z0 || s->n[2] % z) continue;
       lsfft_schedule c = cur;
       c.stencil_planes = z;
@@ -1172,12 +1172,14 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   }
   if (s->disp) {
     if (hipMalloc(&s->u, B * 3 * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
-    // planes per stencil workgroup: as many as keep >= 1024 workgroups (over
-    // the whole batch), at least 2
+    // planes per stencil workgroup: as many as keep >= 512 workgroups (over
+    // the whole batch; one round of two per CU), at most 128, at least 2:
+    // every workgroup evaluates one extra cell plane and loads two extra u
+    // planes, so longer marches waste less
     const int ny = stencil_yblocks(s);
     int Z = 2;
-    for (int c : {32, 16, 8, 4}) {
-      if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) * count >= 1024) {
+    for (int c : {128, 64, 32, 16, 8, 4}) {
+      if (s->n[2] % c == 0 && (long long)ny * (s->n[2] / c) * count >= 512) {
         Z = c;
         break;
       }
