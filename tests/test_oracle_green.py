@@ -183,3 +183,41 @@ def test_dgo_pointwise_matches_table_and_is_even():
         for j2 in range(4):
             for j1 in range(6):
                 assert np.allclose(Gc[j3, j2, j1], Gc[(-j3) % 8, (-j2) % 4, (-j1) % 6], atol=1e-13)
+
+
+def _energy_form(G6):
+    """Symmetric part of the quadratic form -tau : Gamma tau in Voigt tensor
+    components (shear entries counted twice).  The operators carry the
+    paper's sign (Gamma_hat = -sym[G A k (x) k]), so -Gamma is the positive
+    one."""
+    W = np.diag([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+    A = -W @ G6
+    return 0.5 * (A + A.T)
+
+
+def test_dgo_squared_sinc_is_positive_semidefinite():
+    """With squared-sinc weights the DGO is a non-negative combination of the
+    continuous Gamma_0 at the image frequencies, each positive semidefinite
+    for the energy tau : Gamma tau; the table must keep that at every
+    frequency (a wrong sign in any image term or in Gamma_0 breaks it)."""
+    n = (6, 4, 8)
+    Gc = green.dgo_voigt(n, LAM0, MU0, 2, 2)
+    top = max(np.abs(_energy_form(Gc[j3, j2, j1])).max() for j3 in range(8) for j2 in range(4) for j1 in range(6))
+    for j3 in range(8):
+        for j2 in range(4):
+            for j1 in range(6):
+                ev = np.linalg.eigvalsh(_energy_form(Gc[j3, j2, j1]))
+                assert ev.min() >= -1e-12 * top
+    # the continuous operator itself, at a generic wavevector
+    ev = np.linalg.eigvalsh(_energy_form(green.gamma_iso_voigt(np.array([0.3, -1.2, 0.7]), LAM0, MU0)))
+    assert ev.min() >= -1e-12 and ev.max() > 0.0
+
+
+def test_dgo_single_sinc_weights_can_be_indefinite():
+    """The single-sinc weights of reading R14 are signed: at M = 3 some
+    frequency of a small grid has an indefinite DGO (why p = 1 may diverge)."""
+    n = (6, 4, 8)
+    Gc = green.dgo_voigt(n, LAM0, MU0, 3, 1)
+    mins = [np.linalg.eigvalsh(_energy_form(Gc[j3, j2, j1])).min()
+            for j3 in range(8) for j2 in range(4) for j1 in range(6)]
+    assert min(mins) < -1e-6
