@@ -79,7 +79,9 @@ typedef enum { LSFFT_F64 = 0, LSFFT_F32 = 1 } lsfft_prec;
 typedef enum {
   LSFFT_OK = 0,          /* converged: r <= tol                              */
   LSFFT_ENOTCONV = 1,    /* maxit reached; outputs hold the last iterate      */
-  LSFFT_EDIVERGED = 2,   /* residual non-finite or > 1e6 x the first residual */
+  LSFFT_EDIVERGED = 2,   /* residual non-finite, or the unnormalised equilibrium
+                            norm sqrt(sum |sigma_hat q^b|^2) > 1e6 x its first
+                            value (DGO: the residual > 1e6 x the first one) */
   LSFFT_EINVAL = -1,     /* invalid argument; nothing computed                */
   LSFFT_ENOMEM = -2,     /* device allocation failed                          */
   LSFFT_EDEVICE = -3     /* HIP runtime error                                 */
@@ -313,6 +315,17 @@ lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, con
 lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id);
 lsfft_status lsfft_get_timing(lsfft_solver s, double *mean_ms, int32_t *launches);
 const char *lsfft_kernel_name(int32_t kernel_id);
+
+/* The kernel instantiations one iteration of solver `s` launches, in launch
+ * order, written as a NUL-terminated string of space-separated names with
+ * their template arguments (e.g. "k_stencil_reg<float,256,4,AFB,2>
+ * k_ypass<float,256,8,32> ...": element type, transform length, points per
+ * thread, then the kernel's tile or scheme arguments).  It reflects the
+ * solver's lengths, form, scheme, precision and current launch schedule, so a
+ * caller can tell which compiled kernels a result came from.  `buf` is
+ * caller-owned host memory of `cap` bytes.  EINVAL: NULL s or buf, or cap too
+ * small for the string (nothing is written then).  Launches nothing. */
+lsfft_status lsfft_describe(lsfft_solver s, char *buf, int32_t cap);
 
 /* Release all device memory of the solver.  lsfft_destroy(NULL) is a no-op. */
 lsfft_status lsfft_destroy(lsfft_solver s);

@@ -16,6 +16,11 @@ the design notes of the repository):
     whose residual is reported, and `iters` counts the updates applied.  The
     paper's own test (an L1 norm of successive Green increments) is kept as
     stop="paper";
+  * divergence (the paper has no rule): stop with EDIVERGED when r_k is not
+    finite or the unnormalised equilibrium norm sqrt(sum |T_check q^b|^2) has
+    grown past DIVERGENCE_FACTOR times its value at k = 0 (r_k itself can
+    stay bounded in a diverging iteration, since the mean stress that
+    normalises it grows with the iterate);
   * DGO: polarisation form eps^(k+1) = Ebar + F^{c+}[Gamma^c F^{c-}((C - C_H) eps^(k))],
     stopped on |eps^(k+1) - eps^(k)| / (sqrt(N) |Ebar|_F).
 
@@ -70,10 +75,16 @@ def _transform(T, forward, disc):
     return from_voigt(np.moveaxis(out, 0, -1))
 
 
-def equilibrium_residual(That, qb):
-    """sqrt(sum |T_check q^b|^2) / |T_check(0)|_F (the reading above)."""
+def equilibrium_norm(That, qb):
+    """sqrt(sum |T_check q^b|^2): the unnormalised equilibrium norm."""
     div = np.einsum("...ij,...j->...i", That, qb)
-    num = np.sqrt(np.sum(np.abs(div) ** 2))
+    return float(np.sqrt(np.sum(np.abs(div) ** 2)))
+
+
+def equilibrium_residual(That, qb, num=None):
+    """sqrt(sum |T_check q^b|^2) / |T_check(0)|_F (the reading above)."""
+    if num is None:
+        num = equilibrium_norm(That, qb)
     den = frob(That[0, 0, 0])
     if num == 0.0:
         return 0.0
@@ -144,8 +155,11 @@ def solve_gfp(lam, mu, Ebar, lam0, mu0, scheme="AFB", tol=1e-8, maxit=1000,
         Et = _transform(sym_outer(u, qa), forward=False, disc=disc).real
         T = T0 + hooke(lam, mu, Et)
         That = _transform(T, forward=True, disc=disc)
-        r = equilibrium_residual(That, qb)
+        num = equilibrium_norm(That, qb)
+        r = equilibrium_residual(That, qb, num)
         history.append(r)
+        if k == 0:
+            num0 = num
         if callback is not None:
             callback(k, Eb + Et, T, r)
         if paper_done or (stop == "equilibrium" and r <= tol):
@@ -154,7 +168,7 @@ def solve_gfp(lam, mu, Ebar, lam0, mu0, scheme="AFB", tol=1e-8, maxit=1000,
         if k == maxit:
             status = ENOTCONV
             break
-        if not np.isfinite(r) or r > DIVERGENCE_FACTOR * max(history[0], 1e-300):
+        if not np.isfinite(r) or num > DIVERGENCE_FACTOR * max(num0, 1e-300):
             status = EDIVERGED
             break
         du = green_update(That, qa, qb, lam0, mu0, singular)

@@ -37,7 +37,7 @@ struct State {
   int status;
   int iters;
   int k;        // index of the next iteration to test (advanced by k_reduce)
-  double r0;
+  double r0;    // first value of the divergence test's quantity (see reduce_decide)
   double r;
   double sig_mean[6];
 };
@@ -613,20 +613,26 @@ __device__ inline void reduce_decide(const ReduceArgs &a, int sysb, const double
     mean[c] = vals[c] / a.N - (a.smean ? a.smean[6 * sysb + c] : 0.0);
     sn += (c < 3 ? 1.0 : 2.0) * mean[c] * mean[c];
   }
-  double r;
+  // r: the stopping test's residual; g: the quantity whose growth past
+  // div_factor times its first value means divergence (GFP: the unnormalised
+  // equilibrium norm, since r itself stays bounded while the mean stress
+  // grows with a diverging iterate; DGO: r, whose scale is fixed)
+  double r, g;
   if (a.dgo) {
     r = (k == 0) ? __builtin_huge_val() : sqrt(vals[6]) / (sqrt(a.N) * ebar_norm);
+    g = r;
   } else {
     const double num = a.disp ? sqrt(a.N * vals[6]) : sqrt(vals[7]);
     const double den = a.N * sqrt(sn);
     r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : __builtin_huge_val());
+    g = num;
   }
   hist[k] = r;
   s.r = r;
   for (int c = 0; c < 6; ++c) s.sig_mean[c] = mean[c];
   s.iters = k;
   const int first = a.dgo ? 1 : 0;
-  if (k == first) s.r0 = r;
+  if (k == first) s.r0 = g;
   int done = 0, status = 1;
   const bool finite = (r == r) && (r < __builtin_huge_val());
   if (a.dgo && k == 0) {
@@ -637,7 +643,7 @@ __device__ inline void reduce_decide(const ReduceArgs &a, int sysb, const double
   } else if (!a.dgo && k == a.maxit) {
     done = 1;
     status = 1;
-  } else if (!finite || r > a.div_factor * fmax(s.r0, 1e-300)) {
+  } else if (!finite || g > a.div_factor * fmax(s.r0, 1e-300)) {
     done = 1;
     status = 2;
   } else if (a.dgo && k == a.maxit) {

@@ -257,3 +257,56 @@ def test_planted_transpose_in_green_inverse_is_caught(monkeypatch):
     monkeypatch.setattr(green, "green_inverse", bad)
     planted = green.green_update(T, qa, qb, lam0, mu0, sing)
     assert not np.allclose(planted[~sing], -v[~sing], atol=1e-6)
+
+
+def _homogeneous_with_eigenstrain(shape, alpha, seed=5):
+    """Homogeneous C_1 = alpha C_0 loaded by a random eigenstrain (Sec. 7): the
+    error of every GFP iterate is a compatible fluctuation, and one pass maps
+    it to (1 - alpha) times itself (Gamma_0 C_0 is the projection onto
+    compatible fields, eq. (34) with C_1 = alpha C_0), so the equilibrium norm
+    is multiplied by exactly |1 - alpha| per iteration and the mean stress
+    C_1 (Ebar - <E_*>) never changes."""
+    n1, n2, n3 = shape
+    l0, m0 = 1.3, 0.9
+    lam = np.full((n3, n2, n1), alpha * l0)
+    mu = np.full((n3, n2, n1), alpha * m0)
+    es = 1e-3 * np.random.default_rng(seed).standard_normal((6, n3, n2, n1))
+    return lam, mu, l0, m0, es
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("alpha", [0.4, 1.7])
+def test_contraction_factor_closed_form(scheme, alpha):
+    lam, mu, l0, m0, es = _homogeneous_with_eigenstrain((8, 6, 4), alpha)
+    r = solve3d.solve_gfp(lam, mu, EBAR, l0, m0, scheme=scheme, tol=0.0, maxit=12, eigenstrain=es)
+    h = np.array(r.history)
+    assert r.status == solve3d.ENOTCONV and r.iters == 12
+    assert np.allclose(h[1:] / h[:-1], abs(1.0 - alpha), rtol=1e-9)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_divergence_detected_where_the_closed_form_says(scheme):
+    """C_0 = C_1 / 2.5 (below half the stiffness): the equilibrium norm grows
+    by exactly 1.5 per iteration and first exceeds 1e6 times its initial value
+    at k = ceil(log 1e6 / log 1.5) = 35, where the oracle must stop with
+    EDIVERGED; r_k grows the same way (constant mean stress)."""
+    alpha = 2.5
+    lam, mu, l0, m0, es = _homogeneous_with_eigenstrain((8, 6, 4), alpha)
+    r = solve3d.solve_gfp(lam, mu, EBAR, l0, m0, scheme=scheme, tol=1e-8, maxit=500, eigenstrain=es)
+    k_expected = int(np.ceil(np.log(solve3d.DIVERGENCE_FACTOR) / np.log(alpha - 1.0)))
+    assert k_expected == 35
+    assert r.status == solve3d.EDIVERGED and r.iters == k_expected
+    assert np.isclose(r.history[-1] / r.history[0], 1.5 ** k_expected, rtol=1e-8)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_reference_medium_below_half_the_stiffest_phase_diverges(scheme):
+    """Cubic inclusion, contrast 10: with C_0 = C_I / 5 the basic, FB and AFB
+    iterations diverge (detected within 20 iterations); with C_0 = 0.55 C_I
+    (above half the stiffest phase) they converge."""
+    lam, mu = inputs.cubic_inclusion(8, 4, 1.0, 10.0)
+    li, mi = inputs.lame_from_young(10.0, 0.3)
+    bad = solve3d.solve_gfp(lam, mu, EBAR, 0.2 * li, 0.2 * mi, scheme=scheme, tol=1e-10, maxit=300)
+    assert bad.status == solve3d.EDIVERGED and bad.iters <= 20
+    good = solve3d.solve_gfp(lam, mu, EBAR, 0.55 * li, 0.55 * mi, scheme=scheme, tol=1e-10, maxit=300)
+    assert good.status == solve3d.OK
