@@ -214,10 +214,136 @@ def test_dgo_squared_sinc_is_positive_semidefinite():
 
 
 def test_dgo_single_sinc_weights_can_be_indefinite():
-    """The single-sinc weights of reading R14 are signed: at M = 3 some
+    """The single-sinc weights of reading R9 are signed: at M = 3 some
     frequency of a small grid has an indefinite DGO (why p = 1 may diverge)."""
     n = (6, 4, 8)
     Gc = green.dgo_voigt(n, LAM0, MU0, 3, 1)
     mins = [np.linalg.eigvalsh(_energy_form(Gc[j3, j2, j1])).min()
             for j3 in range(8) for j2 in range(4) for j1 in range(6)]
     assert min(mins) < -1e-6
+
+
+# ---------------------------------------------------------------------------
+# Off-axis pin of the DGO image sum (Sec. 5.4, the DGO algorithm).  With
+# squared weights the DGO is the continuous Gamma_0 acting on a voxelwise
+# constant polarisation, averaged back over each voxel.  On a grid refined r
+# times per axis that composition is computed here directly: repeat each voxel
+# r^3 times, FFT, Gamma_0 at the plain continuum wavevector of every fine
+# frequency, inverse FFT, average each voxel's r^3 samples, transform back.
+# Exactly, this equals the image sum over the r^3 aliases kappa + nu n of each
+# coarse frequency (|nu_r| <= (r - 1)/2 on odd grids), with the box filter of
+# the r samples, D_r(m) = sin(pi m / n) / (r sin(pi m / (r n))), in place of
+# the sinc; D_r -> sinc as r grows.  So dgo_voigt with its weight function
+# replaced by D_r must reproduce the refined computation at every frequency,
+# off-axis included, which pins its image wavevectors and the axis each
+# weight applies to; with the sinc itself the two converge as r grows.
+
+
+def _refined_gamma0(tau, r, lam0, mu0, h):
+    """Voxel averages of Gamma_0 (paper's sign, eq. (48)) applied to the
+    voxelwise constant field `tau` (6, n3, n2, n1), computed on an r-times
+    refined grid; returned as the coarse DFT (6, n3, n2, n1), complex."""
+    n3, n2, n1 = tau.shape[1:]
+    fine = np.repeat(np.repeat(np.repeat(tau, r, axis=1), r, axis=2), r, axis=3)
+    F = np.fft.fftn(fine, axes=(1, 2, 3))
+    ks = []
+    for n, hr, ax in ((n1, h[0], 2), (n2, h[1], 1), (n3, h[2], 0)):
+        m = fourier.centred_index(r * n)
+        shape = [1, 1, 1]
+        shape[ax] = r * n
+        ks.append(np.broadcast_to((2 * np.pi * m / (n * hr)).reshape(shape), (r * n3, r * n2, r * n1)))
+    k = np.stack(ks, axis=-1)
+    live = np.einsum("...r,...r->...", k, k) > 0.0
+    T = green.from_voigt(np.moveaxis(F, 0, -1))
+    out = np.zeros_like(T)
+    out[live] = green.gamma_iso(k[live], lam0, mu0, T[live])
+    back = np.fft.ifftn(np.moveaxis(green.to_voigt(out), -1, 0), axes=(1, 2, 3))
+    avg = back.reshape(6, n3, r, n2, r, n1, r).mean(axis=(2, 4, 6))
+    return np.fft.fftn(avg, axes=(1, 2, 3))
+
+
+def _dirichlet(r, mirror=False, axis_len=None):
+    """Box-filter weight D_r at the image m = kappa + nu n (see above).
+    mirror: weight taken at kappa - nu n (a planted mistake); axis_len: a map
+    n -> another axis's length (a planted mistake)."""
+
+    def w(kappa, nu, n):
+        nn = axis_len[n] if axis_len else n
+        m = np.asarray(kappa - nu * nn if mirror else kappa + nu * nn, dtype=np.float64)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            val = np.sin(np.pi * m / nn) / (r * np.sin(np.pi * m / (r * nn)))
+        return np.where(m == 0, 1.0, val)
+
+    return w
+
+
+def _dgo_apply(Gc, tau):
+    th = np.fft.fftn(tau, axes=(1, 2, 3))
+    return np.einsum("...IJ,J...->I...", Gc, th)
+
+
+N_ODD = (3, 5, 7)
+H_ODD = (0.5, 1.0, 2.0)
+
+
+@pytest.mark.parametrize("r", [3, 5])
+def test_dgo_image_sum_equals_refined_grid_gamma0(monkeypatch, r):
+    tau = np.random.default_rng(r).standard_normal((6,) + N_ODD[::-1])
+    ref = _refined_gamma0(tau, r, LAM0, MU0, H_ODD)
+    monkeypatch.setattr(green, "sinc_weight", _dirichlet(r))
+    Gc = green.dgo_voigt(N_ODD, LAM0, MU0, (r - 1) // 2, 2, h=H_ODD)
+    got = _dgo_apply(Gc, tau)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-12 * scale
+    # most of the signal is off-axis: at least two nonzero indices
+    kap = [fourier.centred_index(n) for n in N_ODD]
+    off = ((kap[0][None, None, :] != 0).astype(int) + (kap[1][None, :, None] != 0) + (kap[2][:, None, None] != 0)) >= 2
+    assert np.abs(ref[:, off]).max() > 0.5 * scale
+
+
+@pytest.mark.parametrize("plant", ["mirrored image", "other axis length", "permuted wavevector"])
+def test_dgo_refined_grid_pin_catches_planted_mistakes(monkeypatch, plant):
+    r = 3
+    tau = np.random.default_rng(9).standard_normal((6,) + N_ODD[::-1])
+    ref = _refined_gamma0(tau, r, LAM0, MU0, H_ODD)
+    if plant == "mirrored image":
+        monkeypatch.setattr(green, "sinc_weight", _dirichlet(r, mirror=True))
+    elif plant == "other axis length":
+        monkeypatch.setattr(green, "sinc_weight", _dirichlet(r, axis_len={3: 5, 5: 7, 7: 3}))
+    else:
+        monkeypatch.setattr(green, "sinc_weight", _dirichlet(r))
+        orig = green.gamma_iso_voigt
+        monkeypatch.setattr(green, "gamma_iso_voigt", lambda k, l0, m0: orig(k[..., [1, 0, 2]], l0, m0))
+    Gc = green.dgo_voigt(N_ODD, LAM0, MU0, 1, 2, h=H_ODD)
+    got = _dgo_apply(Gc, tau)
+    assert np.abs(got - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_dgo_squared_sinc_is_the_limit_of_refined_grids():
+    """With the sinc itself, the refined-grid result approaches dgo_voigt
+    (p = 2, M = (r - 1)/2) as r grows: both tend to the full image sum (the
+    gap, of the truncated tails and of D_r against the sinc, closes about
+    like 1/r)."""
+    tau = np.random.default_rng(4).standard_normal((6,) + N_ODD[::-1])
+    errs = []
+    for r in (3, 5, 9):
+        ref = _refined_gamma0(tau, r, LAM0, MU0, H_ODD)
+        got = _dgo_apply(green.dgo_voigt(N_ODD, LAM0, MU0, (r - 1) // 2, 2, h=H_ODD), tau)
+        errs.append(np.abs(got - ref).max() / np.abs(ref).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.4 * errs[0]
+
+
+def test_dgo_even_grid_matches_refined_grid_off_nyquist(monkeypatch):
+    """Even axes: every frequency with no Nyquist index, off-axis included,
+    matches the refined computation (at a Nyquist index the refined grid's
+    alias set is one-sided while the table's window is the symmetric one of
+    reading R10)."""
+    n, r = (6, 4, 8), 3
+    tau = np.random.default_rng(2).standard_normal((6,) + n[::-1])
+    ref = _refined_gamma0(tau, r, LAM0, MU0, (1.0, 1.0, 1.0))
+    monkeypatch.setattr(green, "sinc_weight", _dirichlet(r))
+    got = _dgo_apply(green.dgo_voigt(n, LAM0, MU0, 1, 2), tau)
+    kap = [fourier.centred_index(v) for v in n]
+    keep = ((kap[0][None, None, :] != -n[0] // 2) & (kap[1][None, :, None] != -n[1] // 2)
+            & (kap[2][:, None, None] != -n[2] // 2))
+    assert np.abs(got[:, keep] - ref[:, keep]).max() < 1e-12 * np.abs(ref).max()
