@@ -1,6 +1,8 @@
 // Definitions of the pass-kernel launches, instantiated once per precision
 // by launch_f32.hip and launch_f64.hip.
 #pragma once
+#include <cstdio>
+
 #include "solver.hpp"
 
 namespace lsfft_host {
@@ -135,6 +137,83 @@ case Nv: {                                                                      
 template <typename T>
 hipError_t Launch<T>::zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) {
   return s->scheme == LSFFT_FB ? zpass_u_s<lsfft::SCHEME_FB>(s, a, grid) : zpass_u_s<lsfft::SCHEME_AFB>(s, a, grid);
+}
+
+template <typename T> std::string Launch<T>::describe(lsfft_solver s) {
+  const char *tn = sizeof(T) == 4 ? "float" : "double";
+  const char *sch = s->scheme == LSFFT_FB ? "FB" : "AFB";
+  char b[128];
+  std::string x, y, z, u;
+  if (s->disp) {
+    switch (s->n[0]) {
+#define SD(Lv)                                                                                          \
+case 2 * Lv:                                                                                           \
+  if (stencil_reg_kernel(2 * Lv))                                                                      \
+    snprintf(b, sizeof b, "k_stencil_reg<%s,%d,%d,%s,%d>", tn, 2 * Lv, esr_of(Lv), sch, st2_of<T>(2 * Lv)); \
+  else                                                                                                 \
+    snprintf(b, sizeof b, "k_stencil<%s,%d,%d,%s,%d>", tn, 2 * Lv, es_of(Lv), sch, st2_of<T>(2 * Lv)); \
+  x = b;                                                                                               \
+  snprintf(b, sizeof b, "k_uxpass<%s,%d,%d,%d>", tn, Lv, ex_of(Lv), XWG);                              \
+  u = b;                                                                                               \
+  break;
+      LSFFT_X_LENGTHS(SD)
+#undef SD
+      default:
+        break;
+    }
+    switch (s->d.n3) {
+#define ZUD(Nv)                                                                                         \
+case Nv: {                                                                                            \
+  constexpr int E = ezu_of<T>(Nv), P0 = pcols_zu<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                     \
+  snprintf(b, sizeof b, "k_zpass_u<%s,%d,%d,%d,%s>", tn, Nv, E, s->zv ? P1 : P0, sch);                    \
+  z = b;                                                                                              \
+  break;                                                                                              \
+}
+      LSFFT_YZ_LENGTHS(ZUD)
+#undef ZUD
+      default:
+        break;
+    }
+  } else {
+    switch (s->d.L) {
+#define XD(Lv)                                                                                \
+case Lv:                                                                                     \
+  snprintf(b, sizeof b, "k_xpass<%s,%d,%d,%d,%d>", tn, Lv, ex_of(Lv), XWG, s->eig ? 1 : 0); \
+  x = b;                                                                                     \
+  break;
+      LSFFT_X_LENGTHS(XD)
+#undef XD
+      default:
+        break;
+    }
+    switch (s->d.n3) {
+#define ZD(Nv)                                                                                    \
+case Nv: {                                                                                      \
+  constexpr int E = ez_of(Nv), P0 = pcols_z<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                   \
+  snprintf(b, sizeof b, "k_zpass<%s,%d,%d,%d>", tn, Nv, E, s->zv ? P1 : P0);                      \
+  z = b;                                                                                        \
+  break;                                                                                        \
+}
+      LSFFT_YZ_LENGTHS(ZD)
+#undef ZD
+      default:
+        break;
+    }
+  }
+  switch (s->d.n2) {
+#define YD(Nv)                                                                                  \
+case Nv: {                                                                                    \
+  constexpr int E = ey_of(Nv), P0 = pcols<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                 \
+  snprintf(b, sizeof b, "k_ypass<%s,%d,%d,%d>", tn, Nv, E, s->yv ? P1 : P0);                    \
+  y = b;                                                                                      \
+  break;                                                                                      \
+}
+    LSFFT_YZ_LENGTHS(YD)
+#undef YD
+    default:
+      break;
+  }
+  return s->disp ? x + " " + y + " " + z + " " + y + " " + u : x + " " + y + " " + z + " " + y;
 }
 
 }  // namespace lsfft_host

@@ -1370,6 +1370,14 @@ lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, con
   return LSFFT_OK;
 }
 
+lsfft_status lsfft_describe(lsfft_solver s, char *buf, int32_t cap) {
+  if (!s || !buf || cap < 1) return LSFFT_EINVAL;
+  const std::string d = s->prec == LSFFT_F32 ? Launch<float>::describe(s) : Launch<double>::describe(s);
+  if ((long long)d.size() + 1 > cap) return LSFFT_EINVAL;
+  memcpy(buf, d.c_str(), d.size() + 1);
+  return LSFFT_OK;
+}
+
 lsfft_status lsfft_set_timing(lsfft_solver s, int32_t kernel_id) {
   if (!s || kernel_id < -1 || kernel_id > 5) return LSFFT_EINVAL;
   s->timing_kernel = kernel_id;

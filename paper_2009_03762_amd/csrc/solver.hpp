@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "../../include/lsfft.h"
@@ -305,6 +306,9 @@ template <typename T> struct Launch : Tiles<T> {
   static hipError_t stencil(lsfft_solver s, const lsfft::SArgs<T> &a, int grid);
   template <int SCH> static hipError_t zpass_u_s(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
   static hipError_t zpass_u(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid);
+  // The kernel instantiations (template arguments) one iteration launches,
+  // in launch order, for the solver's lengths, form, scheme and schedule.
+  static std::string describe(lsfft_solver s);
 };
 
 }  // namespace lsfft_host

@@ -104,6 +104,7 @@ def _load():
         "lsfft_set_timing": (C.c_int, [h, C.c_int32]),
         "lsfft_get_timing": (C.c_int, [h, dp, C.POINTER(C.c_int32)]),
         "lsfft_kernel_name": (C.c_char_p, [C.c_int32]),
+        "lsfft_describe": (C.c_int, [h, C.c_char_p, C.c_int32]),
         "lsfft_destroy": (C.c_int, [h]),
         "lsfft_status_string": (C.c_char_p, [C.c_int]),
         "lsfft_version": (C.c_char_p, []),
@@ -121,7 +122,7 @@ EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_dev
            "lsfft_residual_history",
            "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
            "lsfft_get_timing",
-           "lsfft_kernel_name", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
+           "lsfft_kernel_name", "lsfft_describe", "lsfft_destroy", "lsfft_status_string", "lsfft_version")
 
 
 class LsfftError(RuntimeError):
@@ -399,6 +400,15 @@ def stiffness_gradient(handle, eps_a_dev, eps_b_dev, dj_dlambda=None, dj_dmu=Non
         raise LsfftError(st, "lsfft_stiffness_gradient")
 
 
+def describe(handle):
+    """The kernel instantiations one iteration of this handle launches."""
+    buf = C.create_string_buffer(1024)
+    st = _lib.lsfft_describe(handle, buf, len(buf))
+    if st != OK:
+        raise LsfftError(st, "lsfft_describe")
+    return buf.value.decode()
+
+
 def set_timing(handle, kernel_id):
     st = _lib.lsfft_set_timing(handle, int(kernel_id))
     if st != OK:
@@ -435,6 +445,9 @@ class Solver:
 
     def residual_history(self):
         return residual_history(self.handle)
+
+    def describe(self):
+        return describe(self.handle)
 
     def close(self):
         if self.handle is not None:

@@ -66,3 +66,34 @@ def rel(a, b):
     b = np.asarray(b)
     nb = np.linalg.norm(b.ravel())
     return float(np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0))
+
+
+def plane_errors(a, b):
+    """Relative L2 errors of the strain spectrum of `a` against that of `b`
+    ((..., n3, n2, n1) fields) on the planes and lines a global norm could
+    hide: the Nyquist plane of each even axis and the three zero-frequency
+    axis lines (the mean, index (0, 0, 0), excluded).  A plane whose
+    reference content is below 1e-12 of the whole fluctuation spectrum is
+    compared against that instead."""
+    A = np.fft.fftn(np.asarray(a, dtype=np.float64), axes=(-3, -2, -1))
+    Bf = np.fft.fftn(np.asarray(b, dtype=np.float64), axes=(-3, -2, -1))
+    n3, n2, n1 = Bf.shape[-3:]
+    fluct = Bf.copy()
+    fluct[..., 0, 0, 0] = 0.0
+    scale = np.linalg.norm(fluct.ravel())
+    sel = {}
+    if n1 % 2 == 0:
+        sel["x_nyquist"] = (Ellipsis, slice(None), slice(None), n1 // 2)
+    if n2 % 2 == 0:
+        sel["y_nyquist"] = (Ellipsis, slice(None), n2 // 2, slice(None))
+    if n3 % 2 == 0:
+        sel["z_nyquist"] = (Ellipsis, n3 // 2, slice(None), slice(None))
+    sel["x_line"] = (Ellipsis, 0, 0, slice(1, None))
+    sel["y_line"] = (Ellipsis, 0, slice(1, None), 0)
+    sel["z_line"] = (Ellipsis, slice(1, None), 0, 0)
+    out = {}
+    for name, ix in sel.items():
+        d = np.linalg.norm((A[ix] - Bf[ix]).ravel())
+        r = np.linalg.norm(Bf[ix].ravel())
+        out[name] = float(d / max(r, 1e-12 * scale, 1e-300))
+    return out

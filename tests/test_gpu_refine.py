@@ -234,22 +234,6 @@ def test_tuned_schedule_keeps_the_refined_solve(L):
     assert set(sch) == {"stencil_planes", "y_cols", "z_cols", "xcd_order"}
 
 
-@pytest.mark.parametrize("n1", [192, 384, 512])
-def test_fixed_iterations_wide_x(L, n1):
-    """Refined sweeps with the 192-, 384- and 512-thread register stencils."""
-    print(f"\n[refine wide x] n1={n1}", flush=True)
-    K = 10
-    lam, mu, l0, m0 = _inclusion((8, 12, n1), (4, 6, n1 // 2), 10.0)
-    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", refine=4)
-    out = s.solve(EB, tol=0.0, maxit=K)
-    hist = s.residual_history()
-    s.close()
-    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K)
-    assert out["iters"] == K
-    assert rel(out["eps"], ref.eps) < 1e-6
-    assert rel(hist, np.array(ref.history)) < 1e-3
-
-
 def test_batch_mixing_eigenstrain(L):
     """A refined batch in which one system has an eigenstrain and one has
     none: each follows its own oracle solve."""
