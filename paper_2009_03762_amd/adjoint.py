@@ -27,7 +27,10 @@ class _EffectiveStiffness(torch.autograd.Function):
         E = young.detach().to("cpu", torch.float64).numpy()
         lam, mu = inputs.lame_from_young(E, nu)
         if lambda0 is None or mu0 is None:
-            # reference medium: mean of the Lame moduli of the extreme Young's moduli
+            # reference medium: mean of the Lame moduli of the extreme Young's
+            # moduli.  The converged BASIC / FB / AFB solution does not depend
+            # on C0, so letting it follow E changes no derivative; the DGO's
+            # does, and there the caller fixes C0 (checked in the wrapper).
             l_lo, m_lo = inputs.lame_from_young(E.min(), nu)
             l_hi, m_hi = inputs.lame_from_young(E.max(), nu)
             lambda0, mu0 = 0.5 * (float(l_lo) + float(l_hi)), 0.5 * (float(m_lo) + float(m_hi))
@@ -39,12 +42,15 @@ class _EffectiveStiffness(torch.autograd.Function):
         rb = s.solve_device(B, tol=tol, maxit=maxit, eps_dev=eps_b)
         if rb["status"] < 0 or rb["status"] == lsfft.EDIVERGED:
             s.close()
-            raise lsfft.LsfftError(rb["status"], "effective_stiffness")
+            raise lsfft.LsfftError(rb["status"], "effective_stiffness (load B)")
         if np.array_equal(A, B):
             eps_a, ra = eps_b, rb
         else:
             eps_a = torch.empty(shape, dtype=dt, device="cuda")
             ra = s.solve_device(A, tol=tol, maxit=maxit, eps_dev=eps_a)
+            if ra["status"] < 0 or ra["status"] == lsfft.EDIVERGED:
+                s.close()
+                raise lsfft.LsfftError(ra["status"], "effective_stiffness (load A)")
         ctx.solver = s
         ctx.eps = (eps_a, eps_b)
         ctx.young_meta = (young.dtype, young.device)
@@ -71,7 +77,13 @@ def effective_stiffness(young, nu, A, B=None, lambda0=None, mu0=None, scheme="af
     """J = A : C_eff : B (A, B Voigt tensor-component 6-vectors; B = A by
     default) for Young's modulus field `young` and Poisson ratio `nu`.
     Differentiable with respect to `young` for every scheme (the DGO runs on
-    the PCD grid with the given image window and weight power)."""
+    the PCD grid with the given image window and weight power, and needs an
+    explicit reference medium, which the gradient holds fixed).  Raises
+    LsfftError when either solve fails or diverges."""
+    if scheme.lower() == "dgo" and (lambda0 is None or mu0 is None):
+        # the DGO's discrete solution depends on C0 (Sec. 5.4); the gradient
+        # returned holds C0 fixed, so it must not be derived from E
+        raise ValueError("scheme='dgo' needs an explicit reference medium (lambda0, mu0)")
     A = np.asarray(A, dtype=np.float64)
     B = A if B is None else np.asarray(B, dtype=np.float64)
     if A.shape != (6,) or B.shape != (6,):
