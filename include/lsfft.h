@@ -372,6 +372,28 @@ lsfft_status lsfft_solve_1d(const lsfft_config_1d *cfg, int32_t count, const dou
                             const double *Ebar, double tol, int32_t maxit, double *E, double *T, int32_t *iters,
                             double *residual, int32_t *status);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lsfft_solve_1d with every
+ * array in DEVICE memory and no allocation of any kind.  Same algorithms,
+ * configuration and results as lsfft_solve_1d (C, C_H, Ebar as FP64; E and T
+ * written as FP64 [count][n]; iters, residual, status [count]; E_dev, T_dev,
+ * iters_dev and residual_dev may be NULL, status_dev may not).  Asynchronous
+ * on cfg->stream, which must belong to the current device: returns LSFFT_OK
+ * once the work is enqueued; each bar's outcome is in status_dev (OK,
+ * ENOTCONV, or LSFFT_EINVAL for a bar whose data the kernel rejects: C or C_H
+ * not positive and finite, Ebar not finite, Ebar = 0 for the DGO).  The
+ * per-frequency tables live in a fixed device array of 40 KB (n <= 512),
+ * one per GPU, held until the process ends; the first call on a device looks
+ * up its address.  Calls that overlap on one GPU share that array and race:
+ * serialise them (one stream, or events).  EINVAL (nothing enqueued): NULL
+ * cfg, C_dev, CH_dev, Ebar_dev or status_dev, count outside 1..65535, n above
+ * the scratch limit of 512 (reported on stderr) or otherwise unsupported, and
+ * the configuration errors of lsfft_solve_1d.  EDEVICE: a launch failed. */
+lsfft_status lsfft_solve_1d_noalloc(const lsfft_config_1d *cfg, int32_t count, const double *C_dev,
+                                    const double *CH_dev, const double *Ebar_dev, double tol, int32_t maxit,
+                                    double *E_dev, double *T_dev, int32_t *iters_dev, double *residual_dev,
+                                    int32_t *status_dev);
+
 /* Static string for a status code. */
 const char *lsfft_status_string(lsfft_status st);
 

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "solver.hpp"
@@ -29,6 +30,14 @@ template <typename T> struct Bar1dArgs {
   int *status;
   double tol;
   int maxit;
+  // Allocation-free entry point: stiffness read as FP64 (Cd instead of C),
+  // strain and stress written as FP64 (Ed, Sd instead of E, S; either may be
+  // null), per-bar outputs may be null, and each bar checks its own data
+  // (check = 1): C and C_H positive and finite, Ebar finite (nonzero for the
+  // DGO); a bar that fails gets status LSFFT_EINVAL and no other output.
+  const double *Cd = nullptr;
+  double *Ed = nullptr, *Sd = nullptr;
+  int check = 0;
 };
 
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
@@ -66,14 +75,32 @@ __global__ __launch_bounds__(N / E) void k_bar_1d(Bar1dArgs<T> a) {
   const int bar = blockIdx.x;
   const int t = threadIdx.x;
   const double CH = a.CH[bar], Eb = a.Ebar[bar];
-  const T *C = a.C + (long long)bar * N;
   T c[E];
   cplx<T> ph[E], G[E], qa[E], qb[E];
   T gd[E];
+  if (a.check) {
+    double bad = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double v = a.Cd[(long long)bar * N + t + TPC * e];
+      if (!(v > 0.0) || !(v < __builtin_huge_val())) bad = 1.0;
+    }
+    if (t == 0 && (!(CH > 0.0) || !(CH < __builtin_huge_val()) || !(fabs(Eb) < __builtin_huge_val()) ||
+                   (a.dgo && Eb == 0.0)))
+      bad = 1.0;
+    if (bar_sum<TPC>(bad, red) != 0.0) {
+      if (t == 0) {
+        if (a.iters) a.iters[bar] = 0;
+        if (a.res) a.res[bar] = __builtin_nan("");
+        if (a.status) a.status[bar] = -1;  // LSFFT_EINVAL
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = t + TPC * e;
-    c[e] = C[j];
+    c[e] = a.Cd ? (T)a.Cd[(long long)bar * N + j] : a.C[(long long)bar * N + j];
     ph[e] = a.ph ? a.ph[j] : cplx<T>{T(1), T(0)};
     qa[e] = cplx<T>{(T)a.qa[j].x, (T)a.qa[j].y};
     qb[e] = cplx<T>{(T)a.qb[j].x, (T)a.qb[j].y};
@@ -168,15 +195,105 @@ __global__ __launch_bounds__(N / E) void k_bar_1d(Bar1dArgs<T> a) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const long long o = (long long)bar * N + t + TPC * e;
-    a.E[o] = Ecur[e];
-    a.S[o] = Scur[e];
+    if (a.E) a.E[o] = Ecur[e];
+    if (a.S) a.S[o] = Scur[e];
+    if (a.Ed) a.Ed[o] = (double)Ecur[e];
+    if (a.Sd) a.Sd[o] = (double)Scur[e];
   }
   if (t == 0) {
-    a.iters[bar] = k;
-    a.res[bar] = r;
-    a.status[bar] = status;
+    if (a.iters) a.iters[bar] = k;
+    if (a.res) a.res[bar] = r;
+    if (a.status) a.status[bar] = status;
   }
 }
+
+// ---------------------------------------------------------------- tables on the device
+// The per-frequency tables of a 1D call computed on the device, for the
+// allocation-free entry point (the host path forms the same tables in long
+// double): e^{i 2 pi num / den} with exact values at quarter turns, the
+// symbols of eqs. (12)-(14), the PCD phase, the DGO image factor and the
+// transform twiddles.
+__device__ inline void cis_exact_dev(long long num, long long den, double &c, double &s) {
+  const long long q = ((num % den) + den) % den;
+  if ((4 * q) % den == 0) {
+    const int k = (int)((4 * q) / den) % 4;
+    c = (k == 0) ? 1.0 : (k == 2 ? -1.0 : 0.0);
+    s = (k == 1) ? 1.0 : (k == 3 ? -1.0 : 0.0);
+    return;
+  }
+  sincospi(2.0 * (double)q / (double)den, &s, &c);
+}
+
+struct BarTables {
+  int n, scheme, pcd, dgo, M, p;
+  double h;
+  cplx<double> *qa, *qb;
+  void *ph, *tw;  // cplx<T>
+  double *gd;
+};
+
+template <typename T> __global__ void k_bar_tables(BarTables b) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= b.n) return;
+  const int n = b.n;
+  const double h = b.h;
+  const int kappa = (2 * j < n) ? j : j - n;  // Nyquist index read as -n/2
+  double c, s, ch, sh;
+  cis_exact_dev(kappa, n, c, s);
+  cis_exact_dev(kappa, 2LL * n, ch, sh);
+  const cplx<double> fd{(c - 1.0) / h, s / h};
+  cplx<double> qa, qb;
+  switch (b.scheme) {
+    case LSFFT_1D_F:
+      qa = {0.0, 2.0 * M_PI * kappa / (n * h)};
+      qb = {0.0, -qa.y};
+      break;
+    case LSFFT_1D_CD:
+      qa = {0.0, s / h};
+      qb = {0.0, -qa.y};
+      break;
+    case LSFFT_1D_FD_HC:
+      qa = fd;
+      qb = {0.0, 2.0 * sh / h};
+      break;
+    default:  // LSFFT_1D_FD (and the DGO's unused symbols) with its conjugate
+      qa = fd;
+      qb = {fd.x, -fd.y};
+      break;
+  }
+  b.qa[j] = qa;
+  b.qb[j] = qb;
+  double pc, ps;
+  cis_exact_dev(-kappa, 2LL * n, pc, ps);  // exp(-i pi kappa / n)
+  reinterpret_cast<cplx<T> *>(b.ph)[j] = cplx<T>{(T)pc, (T)ps};
+  double tc, ts;
+  cis_exact_dev(-j, n, tc, ts);  // exp(-2 pi i j / n)
+  reinterpret_cast<cplx<T> *>(b.tw)[j] = cplx<T>{(T)tc, (T)ts};
+  double g = 0.0;
+  if (b.dgo && kappa != 0) {
+    const int hi = (kappa == -n / 2) ? b.M + 1 : b.M;
+    for (int nu = -b.M; nu <= hi; ++nu) {
+      const long long m = (long long)kappa + (long long)nu * n;  // never 0 for kappa != 0
+      double cn, sn;
+      cis_exact_dev(m, 2LL * n, cn, sn);  // sin(pi m / n) with exact zeros
+      const double w = sn / (M_PI * (double)m / (double)n);
+      g += (b.p == 2) ? w * w : w;
+    }
+  }
+  b.gd[j] = g;
+}
+
+// Scratch of the allocation-free entry point: one call's tables, at most
+// 512 frequencies (qa, qb and the phase and twiddles as complex FP64 at most,
+// the DGO factor as FP64).  Every GPU the library runs on holds one copy for
+// the life of the process; in host code the name is only a stand-in for the
+// device symbol, whose address each device's copy has (see
+// noalloc_scratch below).
+constexpr int NOALLOC_MAX_N = 512;
+constexpr size_t NOALLOC_QA = 0, NOALLOC_QB = NOALLOC_QA + NOALLOC_MAX_N * 16, NOALLOC_PH = NOALLOC_QB + NOALLOC_MAX_N * 16,
+                 NOALLOC_TW = NOALLOC_PH + NOALLOC_MAX_N * 16, NOALLOC_GD = NOALLOC_TW + NOALLOC_MAX_N * 16,
+                 NOALLOC_BYTES = NOALLOC_GD + NOALLOC_MAX_N * 8;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 
 }  // namespace lsfft
 
@@ -354,6 +471,104 @@ lsfft_status solve_bars(const lsfft_config_1d *cfg, int count, const double *C, 
 }
 
 }  // namespace
+
+namespace {
+
+// Device address of this device's copy of the scratch array: looked up once
+// per device, on the entry point's first call with that device current.
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+lsfft_status noalloc_scratch(void *&ptr) {
+  int dev = -1;
+  BAR_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return LSFFT_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    BAR_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(lsfft::scratch)));
+    if (!p) return LSFFT_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  ptr = g_scratch_ptr[dev];
+  return LSFFT_OK;
+}
+
+template <typename T>
+lsfft_status solve_bars_noalloc(const lsfft_config_1d *cfg, int count, const double *C, const double *CH,
+                                const double *Ebar, double tol, int maxit, double *E_out, double *S_out,
+                                int32_t *iters, double *residual, int32_t *status) {
+  void *base = nullptr;
+  lsfft_status ss = noalloc_scratch(base);
+  if (ss != LSFFT_OK) return ss;
+  char *scr = (char *)base;
+  const int n = cfg->n;
+  const bool dgo = cfg->scheme == LSFFT_1D_DGO;
+  hipStream_t st = (hipStream_t)cfg->stream;
+  lsfft::BarTables tb;
+  tb.n = n;
+  tb.scheme = cfg->scheme;
+  tb.pcd = cfg->disc == LSFFT_PCD;
+  tb.dgo = dgo;
+  tb.M = cfg->dgo_images;
+  tb.p = cfg->dgo_weight_power;
+  tb.h = cfg->h > 0.0 ? cfg->h : 1.0;
+  tb.qa = (lsfft::cplx<double> *)(scr + lsfft::NOALLOC_QA);
+  tb.qb = (lsfft::cplx<double> *)(scr + lsfft::NOALLOC_QB);
+  tb.ph = scr + lsfft::NOALLOC_PH;
+  tb.tw = scr + lsfft::NOALLOC_TW;
+  tb.gd = (double *)(scr + lsfft::NOALLOC_GD);
+  hipLaunchKernelGGL(lsfft::k_bar_tables<T>, dim3((n + 63) / 64), dim3(64), 0, st, tb);
+  BAR_CHECK(hipGetLastError());
+  lsfft::Bar1dArgs<T> a;
+  a.C = nullptr;
+  a.Cd = C;
+  a.CH = CH;
+  a.Ebar = Ebar;
+  a.qa = tb.qa;
+  a.qb = tb.qb;
+  a.ph = tb.pcd ? (const lsfft::cplx<T> *)tb.ph : nullptr;
+  a.dgo = dgo ? tb.gd : nullptr;
+  a.tw = (const lsfft::cplx<T> *)tb.tw;
+  a.E = a.S = nullptr;
+  a.Ed = E_out;
+  a.Sd = S_out;
+  a.iters = iters;
+  a.res = residual;
+  a.status = status;
+  a.tol = tol;
+  a.maxit = maxit;
+  a.check = 1;
+  if (launch_bars<T>(n, count, a, st) != hipSuccess) return LSFFT_EDEVICE;
+  return LSFFT_OK;
+}
+
+}  // namespace
+
+extern "C" lsfft_status lsfft_solve_1d_noalloc(const lsfft_config_1d *cfg, int32_t count, const double *C_dev,
+                                               const double *CH_dev, const double *Ebar_dev, double tol,
+                                               int32_t maxit, double *E_dev, double *T_dev, int32_t *iters_dev,
+                                               double *residual_dev, int32_t *status_dev) {
+  if (!cfg || !C_dev || !CH_dev || !Ebar_dev || !status_dev || count < 1 || count > 65535) return LSFFT_EINVAL;
+  if (cfg->n > lsfft::NOALLOC_MAX_N) {
+    fprintf(stderr, "lsfft_solve_1d_noalloc: n = %d exceeds the scratch limit of %d samples per bar\n", cfg->n,
+            lsfft::NOALLOC_MAX_N);
+    return LSFFT_EINVAL;
+  }
+  if (!lsfft_host::supported_len(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
+  if (cfg->scheme < LSFFT_1D_F || cfg->scheme > LSFFT_1D_DGO) return LSFFT_EINVAL;
+  if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
+  if (cfg->prec != LSFFT_F32 && cfg->prec != LSFFT_F64) return LSFFT_EINVAL;
+  if (cfg->scheme == LSFFT_1D_DGO) {
+    if (cfg->disc != LSFFT_PCD || cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
+    if (cfg->dgo_weight_power != 1 && cfg->dgo_weight_power != 2) return LSFFT_EINVAL;
+  }
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0 || maxit > 10000000) return LSFFT_EINVAL;
+  return cfg->prec == LSFFT_F32 ? solve_bars_noalloc<float>(cfg, count, C_dev, CH_dev, Ebar_dev, tol, maxit, E_dev,
+                                                            T_dev, iters_dev, residual_dev, status_dev)
+                                : solve_bars_noalloc<double>(cfg, count, C_dev, CH_dev, Ebar_dev, tol, maxit, E_dev,
+                                                             T_dev, iters_dev, residual_dev, status_dev);
+}
 
 extern "C" lsfft_status lsfft_solve_1d(const lsfft_config_1d *cfg, int32_t count, const double *C, const double *CH,
                                        const double *Ebar, double tol, int32_t maxit, double *E_out, double *S_out,

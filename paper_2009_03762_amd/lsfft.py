@@ -94,6 +94,9 @@ def _load():
         "lsfft_autotune": (C.c_int, [h, C.c_int32, C.POINTER(Schedule), dp, dp]),
         "lsfft_solve_1d": (C.c_int, [C.POINTER(Config1d), C.c_int32, dp, dp, dp, C.c_double, C.c_int32, dp, dp,
                                      C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
+        "lsfft_solve_1d_noalloc": (C.c_int, [C.POINTER(Config1d), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_void_p]),
         "lsfft_solve": (C.c_int, [h, dp, C.c_double, C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), dp]),
         "lsfft_solve_device": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                          C.POINTER(C.c_int32), dp]),
@@ -119,6 +122,7 @@ def _load():
 _lib = _load()
 EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_device", "lsfft_solve_batch",
            "lsfft_batch_size", "lsfft_get_schedule", "lsfft_set_schedule", "lsfft_autotune", "lsfft_solve_1d",
+           "lsfft_solve_1d_noalloc",
            "lsfft_residual_history",
            "lsfft_stress_spectrum", "lsfft_green_apply", "lsfft_stiffness_gradient", "lsfft_set_timing",
            "lsfft_get_timing",
@@ -268,6 +272,41 @@ def solve_1d(stiffness, CH, Ebar, scheme="f", disc="td", prec="f64", h=1.0, dgo_
     shape = Cin.shape
     return {"status": st, "E": E.reshape(shape), "T": T.reshape(shape), "iters": np.array(list(it)),
             "residual": r, "bar_status": np.array(list(sts))}
+
+
+def solve_1d_noalloc(C_dev, CH_dev, Ebar_dev, E_dev, T_dev, iters_dev, residual_dev, status_dev, scheme="f",
+                     disc="td", prec="f64", h=1.0, dgo_images=4, dgo_weight_power=1, tol=1e-12, maxit=10000,
+                     stream=None):
+    """lsfft_solve_1d_noalloc on device tensors: C_dev (count, n) float64,
+    CH_dev and Ebar_dev (count,) float64; outputs E_dev, T_dev (count, n)
+    float64, iters_dev and status_dev (count,) int32, residual_dev (count,)
+    float64 (any output but status_dev may be None).  Enqueues the work on
+    `stream` (default: torch's current stream) and returns at once; raises
+    LsfftError when nothing was enqueued."""
+    import torch
+    count, n = C_dev.shape
+    for t, dt in ((C_dev, torch.float64), (CH_dev, torch.float64), (Ebar_dev, torch.float64),
+                  (status_dev, torch.int32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device tensors of the documented dtype, contiguous, are required")
+    cfg = Config1d()
+    cfg.n = n
+    cfg.h = float(h)
+    cfg.scheme = SCHEMES_1D[scheme.lower()] if isinstance(scheme, str) else int(scheme)
+    cfg.disc = DISCS[disc.lower()] if isinstance(disc, str) else int(disc)
+    cfg.prec = PRECS[prec.lower()] if isinstance(prec, str) else int(prec)
+    cfg.dgo_images = int(dgo_images)
+    cfg.dgo_weight_power = int(dgo_weight_power)
+    cfg.stream = _stream_handle(stream if stream is not None else torch.cuda.current_stream())
+
+    def ptr(t):
+        return None if t is None else t.data_ptr()
+
+    st = _lib.lsfft_solve_1d_noalloc(C.byref(cfg), count, ptr(C_dev), ptr(CH_dev), ptr(Ebar_dev), float(tol),
+                                     int(maxit), ptr(E_dev), ptr(T_dev), ptr(iters_dev), ptr(residual_dev),
+                                     ptr(status_dev))
+    if st != OK:
+        raise LsfftError(st, "lsfft_solve_1d_noalloc")
 
 
 def get_schedule(handle):

@@ -1,0 +1,95 @@
+"""The allocation-free 1D entry point (lsfft_solve_1d_noalloc) against the
+allocating one (lsfft_solve_1d), through the C ABI: every pair and the DGO of
+Sec. 3, TD and PCD, both precisions, two calls in a row on one GPU (the
+second with fewer, shorter bars, so stale tables of the first call in the
+shared scratch array would show), and bars whose data the kernel rejects.
+Bars: FP64 1e-12, FP32 1e-5 relative L2 (the tables differ from the
+allocating path's long-double ones by rounding only)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _bars(count, n, seed):
+    rng = np.random.default_rng(seed)
+    C = np.exp(rng.uniform(0.0, np.log(50.0), (count, n)))
+    CH = 0.5 * (C.min(axis=1) + C.max(axis=1))
+    Eb = 1e-3 * (1.0 + rng.uniform(0.0, 1.0, count))
+    return C, CH, Eb
+
+
+def _noalloc(L, C, CH, Eb, **kw):
+    count, n = C.shape
+    dev = "cuda"
+    Cd = torch.tensor(C, dtype=torch.float64, device=dev)
+    CHd = torch.tensor(CH, dtype=torch.float64, device=dev)
+    Ebd = torch.tensor(Eb, dtype=torch.float64, device=dev)
+    E = torch.zeros((count, n), dtype=torch.float64, device=dev)
+    T = torch.zeros((count, n), dtype=torch.float64, device=dev)
+    it = torch.zeros(count, dtype=torch.int32, device=dev)
+    r = torch.zeros(count, dtype=torch.float64, device=dev)
+    st = torch.full((count,), 99, dtype=torch.int32, device=dev)
+    L.solve_1d_noalloc(Cd, CHd, Ebd, E, T, it, r, st, **kw)
+    torch.cuda.synchronize()
+    return {"E": E.cpu().numpy(), "T": T.cpu().numpy(), "iters": it.cpu().numpy(), "residual": r.cpu().numpy(),
+            "bar_status": st.cpu().numpy()}
+
+
+CASES = [("f", "td"), ("fd", "td"), ("cd", "td"), ("fd_hc", "td"), ("f", "pcd"), ("fd", "pcd"), ("dgo", "pcd")]
+
+
+@pytest.mark.parametrize("scheme,disc", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_noalloc_matches_allocating_entry_point(L, scheme, disc, prec):
+    print(f"\n[noalloc 1d] {scheme} {disc} {prec}", flush=True)
+    f64 = prec == "f64"
+    kw = dict(scheme=scheme, disc=disc, prec=prec, dgo_images=3, dgo_weight_power=2)
+    # two calls in a row: the second with fewer and shorter bars, a
+    # converged solve, and the first a fixed iteration count
+    for count, n, tol, maxit, seed in ((40, 96, 0.0, 25, 1), (7, 24, 1e-10 if f64 else 1e-5, 4000, 2)):
+        C, CH, Eb = _bars(count, n, seed)
+        ref = L.solve_1d(C, CH, Eb, tol=tol, maxit=maxit, **kw)
+        got = _noalloc(L, C, CH, Eb, tol=tol, maxit=maxit, **kw)
+        bar = 1e-12 if f64 else 1e-5
+        assert np.array_equal(got["bar_status"], ref["bar_status"])
+        assert np.array_equal(got["iters"], ref["iters"])
+        assert _rel(got["E"], ref["E"]) < bar and _rel(got["T"], ref["T"]) < bar
+        # a residual near convergence is a difference of nearly equal sums:
+        # its rounding is absolute (relative to the stress), not relative
+        assert np.allclose(got["residual"], ref["residual"], rtol=1e-6 if f64 else 1e-2,
+                           atol=1e-14 if f64 else 1e-6)
+
+
+def test_noalloc_rejects_bad_bars_and_sizes(L):
+    print("\n[noalloc 1d] rejections", flush=True)
+    C, CH, Eb = _bars(4, 16, 3)
+    C[1, 5] = -1.0
+    CH[2] = 0.0
+    got = _noalloc(L, C, CH, Eb, scheme="fd", disc="td", prec="f64", tol=0.0, maxit=10)
+    ref = L.solve_1d(C[[0, 3]], CH[[0, 3]], Eb[[0, 3]], scheme="fd", disc="td", prec="f64", tol=0.0, maxit=10)
+    assert list(got["bar_status"]) == [L.ENOTCONV, L.EINVAL, L.EINVAL, L.ENOTCONV]
+    assert _rel(got["E"][[0, 3]], ref["E"]) < 1e-12
+    assert np.all(got["E"][[1, 2]] == 0.0)
+    # n beyond the scratch limit (and beyond every supported length): nothing enqueued
+    big = torch.ones((1, 768), dtype=torch.float64, device="cuda")
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(L.LsfftError) as e:
+        L.solve_1d_noalloc(big, one, one, None, None, None, None, st, scheme="fd", disc="td", prec="f64")
+    assert e.value.status == L.EINVAL
