@@ -127,7 +127,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   constexpr int TPC = L / E;
   constexpr int P = WG / TPC;
   static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
-  __shared__ cplx<T> lds[2 * P * L];
+  __shared__ cplx<T> lds[P * line_scratch<L>()];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int p = tid / TPC, t = tid % TPC;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   const bool valid = row < a.d.rows;
   const int n1 = 2 * L;
   const long long N = a.d.N;
-  cplx<T> *sl = lds + p * 2 * L;
+  cplx<T> *sl = lds + p * line_scratch<L>();
   int buf = 0;
   const cplx<T> zero{T(0), T(0)};
   cplx<T> w[3][E];
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   constexpr int SPL = NSL * 6 * N1;
   static_assert(6 * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
   static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
-  static_assert(7 * 2 * L * 2 <= SPL, "transform scratch must fit in one sigma plane");
+  static_assert(7 * line_scratch<L>() * 2 <= SPL, "transform scratch must fit in one sigma plane");
   __shared__ double U[2 * UPL];
   __shared__ T S[2 * SPL];
   __shared__ T F[T2 * 3 * N1];
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
         v[e] = act ? cplx<T>{F[(m * 3 + c) * N1 + xx], F[(m * 3 + c) * N1 + xx + 1]} : cplx<T>{T(0), T(0)};
       }
       // idle threads (pid >= 6) share one dummy scratch area
-      cplx<T> *scr = reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : 6) * 2 * L;
+      cplx<T> *scr = reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : 6) * line_scratch<L>();
       int buf = 0;
       const cplx<T> xnq = r2c_line<T, L, E>(v, t, tid & 63, scr, a.tw, buf);
       if (act) {
@@ -546,14 +546,17 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   constexpr int NX = N1 / XV;                    // threads per group
   constexpr int NUL = T2 + 2, NSL = T2 + 1;
   constexpr int UX = G * NUL * 3 * N1;           // the exchanged u plane (FP64)
-  constexpr int SX = G * NSL * 6 * N1;           // one exchanged sigma plane
   constexpr int NPEN = G * T2 * 3;
+  constexpr int UE = NPEN * N1;                  // the exchanged divergence parts (T)
+  constexpr int SCR = (NPEN + 1) * line_scratch<L>();  // transform scratch (complex T)
   static_assert(G * NX == WG, "the workgroup must split evenly into x columns");
   static_assert(NPEN * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
   static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
-  static_assert((NPEN + 1) * 2 * L * 2 <= SX, "transform scratch must fit in one sigma plane");
+  static_assert(UE <= 2 * SCR, "the divergence exchange must fit in the transform scratch");
   __shared__ double Ux[UX];
-  __shared__ T Sx[2 * SX];
+  // the divergence exchange and, once f is in F, the transform scratch
+  __shared__ cplx<T> Scr[SCR];
+  T *const Ue = reinterpret_cast<T *>(Scr);
   __shared__ T F[G * T2 * 3 * N1];
   __shared__ cplx<T> twl[N1];   // the x twiddles, read by every transform below
   __shared__ double red[(WG / 64) * 8];
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
       }
   };
   auto ux_at = [&](int l, int c, int x) -> double & { return Ux[((g * NUL + l) * 3 + c) * N1 + x]; };
-  auto sx_at = [&](int pb, int l, int c, int x) -> T & { return Sx[pb * SX + ((g * NSL + l) * 6 + c) * N1 + x]; };
+  auto ue_at = [&](int m, int i, int x) -> T & { return Ue[((g * T2 + m) * 3 + i) * N1 + x]; };
   // y differences of plane `src`, publish it, take its x differences
   auto take_plane = [&](const double (&src)[XV][NUL][3], T (&ddx)[XV][NUL][3], T (&ddy)[XV][NSL][3]) {
 #pragma unroll
@@ -700,7 +703,6 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           sg[P][v][l][c] = s6[c];
-          sx_at(P, l, c, x) = s6[c];
           if (l >= 1) acc[c] += s6[c];
         }
       }
@@ -710,73 +712,92 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         for (int c = 0; c < 6; ++c) sums[c] += (double)acc[c];
       }
     }
-    __syncthreads();
-    if constexpr (FIRST) return;
+    if constexpr (FIRST) {
+      __syncthreads();  // the exchange reads above precede the next publish
+      return;
+    }
     // ---- f = div sigma at the nodes (x, lines 0..T2-1, plane z).  Node line
-    // m gathers cell lines m+1 (b = 0) and m (b = 1), cell planes z (d = 0) and
-    // z-1 (d = 1), columns x (a = 0) and x-1 (a = 1).
+    // m gathers cell lines m+1 and m, cell planes z (sg[P]) and z-1 (sg[Q]),
+    // columns x and x-1.  Each difference operator is separable, so the part
+    // of f_i that the own column contributes and the part the column x+1
+    // takes from it are formed here (fv, and fu published to LDS), and
+    // f_i(x) = fv_i(x) - fu_i(x-1): three values per node cross the column
+    // boundary instead of the six stress components of two cell planes.
+    T fv[XV][T2][3];
+#pragma unroll
+    for (int v = 0; v < XV; ++v) {
+      const int x = xt + NX * v;
+#pragma unroll
+      for (int m = 0; m < T2; ++m) {
+        T xp[3], w[3];  // x-derivative part and (y, z)-derivative part of f_i
+        if constexpr (SCHEME == SCHEME_AFB) {
+          // z-pair sums and differences of cell lines m, m+1, then the
+          // 2 x 2 averages: S (x part), Y (y part), Z (z part)
+          T S[6], Y[6], Zd[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const T a0 = sg[P][v][m][c] + sg[Q][v][m][c], a1 = sg[P][v][m + 1][c] + sg[Q][v][m + 1][c];
+            const T d0 = sg[P][v][m][c] - sg[Q][v][m][c], d1 = sg[P][v][m + 1][c] - sg[Q][v][m + 1][c];
+            S[c] = a1 + a0;
+            Y[c] = a1 - a0;
+            Zd[c] = d1 + d0;
+          }
+          // f_0 = d1 s11 + d2 s12 + d3 s13, f_1 = d1 s12 + d2 s22 + d3 s23,
+          // f_2 = d1 s13 + d2 s23 + d3 s33 (Voigt 11,22,33,23,13,12)
+          xp[0] = S[0];
+          xp[1] = S[5];
+          xp[2] = S[4];
+          w[0] = q[1] * Y[5] + q[2] * Zd[4];
+          w[1] = q[1] * Y[1] + q[2] * Zd[3];
+          w[2] = q[1] * Y[3] + q[2] * Zd[2];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            fv[v][m][i] = q[0] * xp[i] + w[i];
+            ue_at(m, i, x) = q[0] * xp[i] - w[i];
+          }
+        } else {
+          // backward differences: cell (x, m+1, z) minus its neighbour in x, y, z
+          const T(&o)[6] = sg[P][v][m + 1];
+          const T(&ym)[6] = sg[P][v][m];
+          const T(&zm)[6] = sg[Q][v][m + 1];
+          xp[0] = o[0];
+          xp[1] = o[5];
+          xp[2] = o[4];
+          w[0] = ih[1] * (o[5] - ym[5]) + ih[2] * (o[4] - zm[4]);
+          w[1] = ih[1] * (o[1] - ym[1]) + ih[2] * (o[3] - zm[3]);
+          w[2] = ih[1] * (o[3] - ym[3]) + ih[2] * (o[2] - zm[2]);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            fv[v][m][i] = ih[0] * xp[i] + w[i];
+            ue_at(m, i, x) = ih[0] * xp[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int x = xt + NX * v;
       const int xm = (x + N1 - 1) % N1;
-      T f[T2][3];
-#pragma unroll
-      for (int m = 0; m < T2; ++m)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) f[m][i] = T(0);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const int ci = vi(c), cj = vj(c);  // sigma_{ci cj}, ci <= cj
-        if constexpr (SCHEME == SCHEME_AFB) {
-          // z-pair sums and z differences per cell line, own and neighbour
-          T A[NSL], D[NSL], An[NSL], Dn[NSL];
-#pragma unroll
-          for (int l = 0; l < NSL; ++l) {
-            const T s0 = sg[P][v][l][c], s1 = sg[Q][v][l][c];
-            const T n0 = sx_at(P, l, c, xm), n1 = sx_at(Q, l, c, xm);
-            A[l] = s0 + s1;
-            D[l] = s0 - s1;
-            An[l] = n0 + n1;
-            Dn[l] = n0 - n1;
-          }
-#pragma unroll
-          for (int m = 0; m < T2; ++m) {
-            T dd[3];
-            dd[0] = q[0] * ((A[m + 1] + A[m]) - (An[m + 1] + An[m]));
-            dd[1] = q[1] * ((A[m + 1] + An[m + 1]) - (A[m] + An[m]));
-            dd[2] = q[2] * ((D[m + 1] + D[m]) + (Dn[m + 1] + Dn[m]));
-            // f_i += d_j sigma_ij over the (i, j) pairs this component serves
-            f[m][ci] += dd[cj];
-            if (ci != cj) f[m][cj] += dd[ci];
-          }
-        } else {
-#pragma unroll
-          for (int m = 0; m < T2; ++m) {
-            const T own = sg[P][v][m + 1][c];
-            T dd[3];
-            dd[0] = ih[0] * (own - sx_at(P, m + 1, c, xm));
-            dd[1] = ih[1] * (own - sg[P][v][m][c]);
-            dd[2] = ih[2] * (own - sg[Q][v][m + 1][c]);
-            f[m][ci] += dd[cj];
-            if (ci != cj) f[m][cj] += dd[ci];
-          }
-        }
-      }
 #pragma unroll
       for (int m = 0; m < T2; ++m) {
+        T f[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[i] = fv[v][m][i] - ue_at(m, i, xm);
         if (a.fstar) {  // eigenstrain: the force of the eigenstress, T = C [E - E_*]
           const int yg = (yg0 + m) % n2;  // groups past n2 work on wrapped rows
           const long long gi = ((long long)(z % n3) * n2 + yg) * N1 + x;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) f[m][i] -= a.fstar[i * N + gi];
+          for (int i = 0; i < 3; ++i) f[i] -= a.fstar[i * N + gi];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) F[((g * T2 + m) * 3 + i) * N1 + x] = f[m][i];
-        if (gvalid) sums[6] += (double)(f[m][0] * f[m][0] + f[m][1] * f[m][1] + f[m][2] * f[m][2]);
+        for (int i = 0; i < 3; ++i) F[((g * T2 + m) * 3 + i) * N1 + x] = f[i];
+        if (gvalid) sums[6] += (double)(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
       }
     }
     __syncthreads();
-    // ---- forward x transforms of the G x T2 x 3 f lines; scratch in the free sigma plane
+    // ---- forward x transforms of the G x T2 x 3 f lines (scratch over the
+    // exchange buffer, whose reads precede the barrier above)
     {
       const int pid = tid / TPC, t = tid % TPC;
       const bool act = pid < NPEN;
@@ -789,7 +810,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         const int o = ((pg * T2 + m) * 3 + c) * N1 + xx;
         vv[e] = act ? cplx<T>{F[o], F[o + 1]} : cplx<T>{T(0), T(0)};
       }
-      cplx<T> *scr = reinterpret_cast<cplx<T> *>(Sx + Q * SX) + (act ? pid : NPEN) * 2 * L;
+      cplx<T> *scr = Scr + (act ? pid : NPEN) * line_scratch<L>();
       int buf = 0;
       const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, twl, buf);
       const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;

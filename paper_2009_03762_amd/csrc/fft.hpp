@@ -136,8 +136,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-template <typename T, int L, int E, bool FWD, int P, bool WAVE = false>
+// PAD: point m of a buffer sits at slot m + m / 16 (buffers of L + L / 16
+// slots), which spreads the strided writes of the early radix passes over
+// the LDS banks; only for power-of-two lines with ms = 1 (see line_pad).
+template <typename T, int L, int E, bool FWD, int P, bool WAVE = false, bool PAD = false>
 struct StockhamPass {
+  __device__ __forceinline__ static int slot(int m) { return PAD ? m + (m >> 4) : m; }
   __device__ __forceinline__ static void run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
                                              const cplx<T> *__restrict__ tw, int ts, int &buf) {
     using PL = Plan<L, E>;
@@ -147,8 +151,9 @@ struct StockhamPass {
     constexpr int NB = E / R;
     constexpr int TPC = L / E;
     constexpr bool LAST = (P + 1 == NP);
+    constexpr int LP = PAD ? L + L / 16 : L;
     cplx<T> out[E];
-    cplx<T> *sb = lds + (buf ? L * ms : 0);
+    cplx<T> *sb = lds + (buf ? LP * ms : 0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + TPC * b;
@@ -171,7 +176,7 @@ struct StockhamPass {
       } else {
         const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) sb[(base + r * Ns) * ms] = a[r];
+        for (int r = 0; r < R; ++r) sb[slot(base + r * Ns) * ms] = a[r];
       }
     }
     if constexpr (LAST) {
@@ -183,20 +188,28 @@ struct StockhamPass {
       else
         __syncthreads();
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = sb[(t + TPC * e) * ms];
+      for (int e = 0; e < E; ++e) v[e] = sb[slot(t + TPC * e) * ms];
       buf ^= 1;
-      StockhamPass<T, L, E, FWD, P + 1, WAVE>::run(v, t, lds, ms, tw, ts, buf);
+      StockhamPass<T, L, E, FWD, P + 1, WAVE, PAD>::run(v, t, lds, ms, tw, ts, buf);
     }
   }
 };
 
 // One transform of a pencil; `buf` is the workgroup-uniform buffer parity,
 // to be carried from one call to the next (start at 0).
-template <typename T, int L, int E, bool FWD, bool WAVE = false>
+template <typename T, int L, int E, bool FWD, bool WAVE = false, bool PAD = false>
 __device__ __forceinline__ void fft_pencil(cplx<T> (&v)[E], int t, cplx<T> *lds, int ms,
                                            const cplx<T> *__restrict__ tw, int ts, int &buf) {
-  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0, WAVE>::run(v, t, lds, ms, tw, ts, buf);
+  if constexpr (L > 1) StockhamPass<T, L, E, FWD, 0, WAVE, PAD>::run(v, t, lds, ms, tw, ts, buf);
 }
+
+// Line transforms (one pencil per line, ms = 1): pad the exchange buffers of
+// power-of-two lines of 16 points or more; their scratch is line_scratch<L>()
+// points per line (two buffers).
+constexpr bool line_pad_of(int L) { return L % 3 != 0 && L >= 16; }
+constexpr int line_scratch_of(int L) { return 2 * (line_pad_of(L) ? L + L / 16 : L); }
+template <int L> constexpr bool line_pad() { return line_pad_of(L); }
+template <int L> constexpr int line_scratch() { return line_scratch_of(L); }
 
 // Copy a twiddle table of NT entries into LDS with all threads of the
 // workgroup, then synchronise.  Each radix pass reads its twiddles right

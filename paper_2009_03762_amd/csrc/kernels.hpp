@@ -122,8 +122,9 @@ __device__ __forceinline__ void partner(const cplx<T> (&v)[E], cplx<T> (&pv)[E],
 }
 
 // The line transforms below run on lines that lie in one wavefront with
-// scratch of their own (every caller asserts 64 % TPC == 0), so their radix
-// exchanges are ordered at wavefront scope.
+// scratch of their own, line_scratch<L>() points per line (every caller
+// asserts 64 % TPC == 0), so their radix exchanges are ordered at wavefront
+// scope.
 //
 // Inverse real transform of one x-line.  In: v[e] = X[k], k = t + TPC e,
 // k in [0, L), and xn = X[L] (meaningful in thread t = 0).  Out: v[e] =
@@ -147,7 +148,7 @@ __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int
       v[e] = (v[e] + xp) + mul_i(w * (v[e] - xp));
     }
   }
-  fft_pencil<T, L, E, false, true>(v, t, lds, 1, tw, 2, buf);
+  fft_pencil<T, L, E, false, true, line_pad<L>()>(v, t, lds, 1, tw, 2, buf);
 }
 
 // Forward real transform of one x-line.  In: v[e] = (x[2m], x[2m+1]).
@@ -157,7 +158,7 @@ template <typename T, int L, int E>
 __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cplx<T> *lds,
                                             const cplx<T> *__restrict__ tw, int &buf) {
   constexpr int TPC = L / E;
-  fft_pencil<T, L, E, true, true>(v, t, lds, 1, tw, 2, buf);
+  fft_pencil<T, L, E, true, true, line_pad<L>()>(v, t, lds, 1, tw, 2, buf);
   cplx<T> pv[E];
   partner<T, E, TPC>(v, pv, t, lane);
   cplx<T> xn{T(0), T(0)};
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
   constexpr int P = WG / TPC;
   constexpr bool PRELOAD_EPS = (sizeof(T) == 4) && LSFFT_X_PRELOAD;
   static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
-  __shared__ cplx<T> lds[2 * P * L];
+  __shared__ cplx<T> lds[P * line_scratch<L>()];
   __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
   const bool valid = row < a.d.rows;
   const int n1 = 2 * L;
   const long long N = a.d.N;
-  cplx<T> *sl = lds + p * 2 * L;
+  cplx<T> *sl = lds + p * line_scratch<L>();
   int buf = 0;
   const bool need_delta = (a.mode == XMODE_UPDATE || a.mode == XMODE_DGO);
   const bool need_old = (a.mode != XMODE_INIT);
