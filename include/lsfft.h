@@ -156,6 +156,22 @@ typedef struct {
                               those updates.  Costs 11N FP64 + 3N T per
                               system (+ 6N FP64 with an eigenstrain) and one
                               FP64 residual evaluation per cycle.            */
+  double f64_until;        /* F32 displacement form, where f64_warmup applies:
+                              run the iterations of every solve in FP64 (after
+                              the f64_warmup ones, if any) until the system's
+                              residual is at most f64_until, then continue in
+                              F32 from that iterate; 0 = off, < 0 or not finite
+                              is EINVAL.  With refine > 0 this is the F32 route
+                              to a certified tolerance at high contrast: the
+                              FP32 rounding of each refinement cycle is then
+                              relative to a residual already small, and every
+                              final status comes from an FP64 evaluation.
+                              Measured (AFB, 256^3, contrast 1e3, tol 1e-6):
+                              f64_until = 3e-4 with refine = 8 stops at r <=
+                              tol in the FP64 iteration count, about 10 %
+                              faster than F64; a switch at a residual much
+                              above 300 x tol leaves FP32 rounding in the
+                              slowest modes and costs many more iterations. */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda
@@ -214,6 +230,31 @@ lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol
 lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, int32_t maxit,
                                void *eps_dev, void *sig_dev, double *sig_mean, int32_t *iters,
                                double *residual, int32_t *status);
+
+/* Solve the systems of `count` solvers (1..64 distinct handles, e.g. one
+ * batch handle per cell size of a set of microstructures, each holding its
+ * cells' load cases) together (Sec. 5.2 for every system; the batched
+ * effective-stiffness setting of six unit loads per cell).  Each solver
+ * opens its solve as lsfft_solve_batch would, then the captured chunk of
+ * iterations of every solver becomes one independent child of a single
+ * graph, launched once per chunk for all sizes at once until every system
+ * has stopped on its own device-side test (a finished system's kernels
+ * return at once).  Solvers with an FP64 warm start (f64_warmup,
+ * f64_until) first run their FP64 phase the same way, as one group.
+ * Results equal those of lsfft_solve_batch on each handle (the same
+ * kernels, in the same order per solver).  Ebar: [sum of batch sizes][6]
+ * HOST, in handle order; maxit_each: NULL (every solver gets maxit) or
+ * `count` iteration limits, one per solver (maxit is then unused but must be
+ * valid); eps_dev: NULL or `count` pointers, each NULL or a
+ * DEVICE array [B][6][N] of that solver's precision; sig_mean [sum B][6],
+ * iters, residual, status [sum B] HOST, each may be NULL.  Synchronous.
+ * Returns the largest per-system status.  EINVAL: NULL handles or Ebar,
+ * count outside 1..64, a NULL or repeated handle, a handle with refine > 0,
+ * tol < 0, a negative iteration limit, non-finite Ebar.  Per-kernel timing is
+ * not recorded during a group solve. */
+lsfft_status lsfft_solve_group(const lsfft_solver *handles, int32_t count, const double *Ebar, double tol,
+                               int32_t maxit, const int32_t *maxit_each, void *const *eps_dev, double *sig_mean,
+                               int32_t *iters, double *residual, int32_t *status);
 
 /* Number of systems of a handle (0 for NULL). */
 int32_t lsfft_batch_size(lsfft_solver s);

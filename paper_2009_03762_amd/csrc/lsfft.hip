@@ -295,6 +295,10 @@ template <typename F> lsfft_status ensure_graph(lsfft_solver s, double tol, int 
     (void)hipGraphExecDestroy(s->gexec);
     s->gexec = nullptr;
   }
+  if (s->graph) {
+    (void)hipGraphDestroy(s->graph);
+    s->graph = nullptr;
+  }
   hipStream_t user = s->stream;
   s->stream = s->gstream;
   hipGraph_t g = nullptr;
@@ -308,12 +312,13 @@ template <typename F> lsfft_status ensure_graph(lsfft_solver s, double tol, int 
     return LSFFT_EDEVICE;
   }
   e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
     s->gexec = nullptr;
     fprintf(stderr, "lsfft: graph instantiation failed: %s\n", hipGetErrorString(e));
     return LSFFT_EDEVICE;
   }
+  s->graph = g;
   s->g_tol = tol;
   s->g_maxit = maxit;
   return LSFFT_OK;
@@ -325,8 +330,12 @@ template <typename F> lsfft_status ensure_graph(lsfft_solver s, double tol, int 
 // state, history and u left by an earlier phase are continued (displacement
 // form), after re-evaluating the stencil on that u in this precision.
 // Returns LSFFT_OK when the iterations ran, even if not every system is done.
+// prepare_only: enqueue the phase's opening work (state reset, first stencil
+// or x-pass with its test) and capture the chunk graph, but run no chunk: a
+// group solve replays the chunks of several solvers in one graph.
 template <typename T>
-lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k_end, bool fresh) {
+lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k_end, bool fresh,
+                       bool prepare_only = false) {
   using L = Launch<T>;
   const bool dgo = (s->scheme == LSFFT_DGO);
   const bool disp = s->disp != 0;
@@ -431,6 +440,7 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
     LSFFT_CHECK(hipStreamSynchronize(st));
     return LSFFT_OK;
   };
+  if (prepare_only) return ensure_graph(s, tol, maxit, iteration);
   int k = k_begin;
   // The final phase of a solve replays captured chunks of iterations (its
   // iterations run to the stopping test, so a chunk may overrun: kernels of
@@ -485,6 +495,8 @@ lsfft_status ensure_hist(lsfft_solver s, int maxit) {
 void drop_graph(lsfft_solver s) {
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
   s->gexec = nullptr;
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->graph = nullptr;
   s->g_tol = -1.0;
   s->g_maxit = -1;
 }
@@ -580,17 +592,45 @@ lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) 
   lsfft_status us = upload_members<T>(s, Eb);
   if (us != LSFFT_OK) return us;
   int k0 = 0;
-  if (s->twin && s->warm > 0) {
-    // FP64 iterations 0 .. k0-1 on the shared u, state and history
+  if (s->twin && (s->warm > 0 || s->until > 0.0)) {
+    // FP64 iterations on the shared u, state and history: 0 .. warm-1, then
+    // (f64_until) on until each system's residual is at most the switch
+    // level; the F32 phase below continues every system that is not done
     lsfft_solver t = s->twin;
     t->hist = s->hist;
     t->hist_cap = s->hist_cap;
     t->timing_kernel = -1;
     us = upload_members<double>(t, Eb);
     if (us != LSFFT_OK) return us;
-    k0 = std::min(s->warm, maxit + 1);
-    lsfft_status ps = run_phase<double>(t, tol, maxit, 0, k0, true);
-    if (ps != LSFFT_OK) return ps;
+    bool fresh = true;
+    if (s->warm > 0) {
+      k0 = std::min(s->warm, maxit + 1);
+      lsfft_status ps = run_phase<double>(t, tol, maxit, 0, k0, true);
+      if (ps != LSFFT_OK) return ps;
+      fresh = false;
+    }
+    if (s->until > 0.0 && (fresh || (!all_done(s) && k0 <= maxit))) {
+      lsfft_status ps = run_phase<double>(t, std::max(tol, s->until), maxit, k0, maxit + 1, fresh);
+      if (ps != LSFFT_OK) return ps;
+      // a system that stopped on the switch level rather than on tol goes on
+      // in F32 from the iterate it stopped at (tested again there)
+      bool resume = false;
+      int kmin = maxit + 1;
+      for (int b = 0; b < s->B; ++b) {
+        State &x = s->st_host[b];
+        if (x.done && x.status == 0 && x.r > tol) {
+          x.done = 0;
+          x.status = 1;
+          resume = true;
+        }
+        if (!x.done) kmin = std::min(kmin, x.k);
+      }
+      if (resume) {
+        LSFFT_CHECK(hipMemcpyAsync(s->st, s->st_host, sizeof(State) * s->B, hipMemcpyHostToDevice, s->stream));
+        LSFFT_CHECK(hipStreamSynchronize(s->stream));
+      }
+      k0 = std::max(kmin, 1);
+    }
   }
   if (s->refine) {
     lsfft_status ps = run_refined<T>(s, tol, maxit, k0 == 0);
@@ -620,6 +660,181 @@ lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) 
   int worst = 0;
   for (int b = 0; b < s->B; ++b) worst = std::max(worst, s->st_host[b].status);
   return (lsfft_status)worst;
+}
+
+// ------------------------------------------------------------------ group solve
+// Replay the captured chunks of several solvers together: one graph holding
+// each solver's chunk as an independent child node, launched on `gs` until
+// every system of every solver is done (a finished system's kernels return
+// at once, so the chunk of a solver that is done costs launches only).  The
+// opening work of each phase ran on the solvers' own streams; their later
+// work waits for the group.
+lsfft_status group_loop(const std::vector<lsfft_solver> &hs, hipStream_t gs, hipEvent_t ev, int max_chunks) {
+  hipGraph_t g = nullptr;
+  LSFFT_CHECK(hipGraphCreate(&g, 0));
+  for (lsfft_solver h : hs) {
+    hipGraphNode_t node;
+    const hipError_t e = hipGraphAddChildGraphNode(&node, g, nullptr, 0, h->graph);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      fprintf(stderr, "lsfft: group graph: %s\n", hipGetErrorString(e));
+      return LSFFT_EDEVICE;
+    }
+  }
+  hipGraphExec_t gx = nullptr;
+  hipError_t e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    fprintf(stderr, "lsfft: group graph instantiation failed: %s\n", hipGetErrorString(e));
+    return LSFFT_EDEVICE;
+  }
+  auto fail = [&](hipError_t err) {
+    (void)hipGraphExecDestroy(gx);
+    fprintf(stderr, "lsfft: group solve: %s\n", hipGetErrorString(err));
+    return LSFFT_EDEVICE;
+  };
+  for (lsfft_solver h : hs) {
+    if ((e = hipEventRecord(h->gevent, h->stream)) != hipSuccess) return fail(e);
+    if ((e = hipStreamWaitEvent(gs, h->gevent, 0)) != hipSuccess) return fail(e);
+  }
+  int launched = 0, per_sync = 1;
+  for (;;) {
+    for (int j = 0; j < per_sync && launched < max_chunks; ++j, ++launched)
+      if ((e = hipGraphLaunch(gx, gs)) != hipSuccess) return fail(e);
+    for (lsfft_solver h : hs)
+      if ((e = hipMemcpyAsync(h->st_host, h->st, sizeof(State) * h->B, hipMemcpyDeviceToHost, gs)) != hipSuccess)
+        return fail(e);
+    if ((e = hipStreamSynchronize(gs)) != hipSuccess) return fail(e);
+    bool all = true;
+    for (lsfft_solver h : hs) all = all && all_done(h);
+    if (all || launched >= max_chunks) break;
+    per_sync = std::min(per_sync * 2, 8);
+  }
+  (void)hipGraphExecDestroy(gx);
+  LSFFT_CHECK(hipEventRecord(ev, gs));
+  for (lsfft_solver h : hs) LSFFT_CHECK(hipStreamWaitEvent(h->stream, ev, 0));
+  return LSFFT_OK;
+}
+
+template <typename T> lsfft_status prepare_phase(lsfft_solver s, double tol, int maxit, int k0, bool fresh) {
+  return run_phase<T>(s, tol, maxit, k0, maxit + 1, fresh, true);
+}
+
+// Solve every system of several solvers (cells of different sizes, each a
+// batch of load cases) together: the FP64 phase of the solvers with an FP64
+// warm start (f64_until), then every solver's own phase, each as one group
+// graph per chunk of iterations.  Eb: [sum B][6] in solver order.
+lsfft_status solve_group(const std::vector<lsfft_solver> &hs, const double *Eb, double tol,
+                         const std::vector<int> &maxits) {
+  const int n = (int)hs.size();
+  int maxit_all = 0;
+  for (int m : maxits) maxit_all = std::max(maxit_all, m);
+  std::vector<int> k0(n, 0);
+  std::vector<char> fresh(n, 1);
+  long long off = 0;
+  for (int i = 0; i < n; ++i) {
+    lsfft_solver s = hs[i];
+    const int maxit = maxits[i];
+    lsfft_status st = ensure_hist(s, maxit);
+    if (st != LSFFT_OK) return st;
+    s->ev_used = 0;
+    st = (s->prec == LSFFT_F32) ? upload_members<float>(s, Eb + 6 * off) : upload_members<double>(s, Eb + 6 * off);
+    if (st != LSFFT_OK) return st;
+    if (s->twin && (s->warm > 0 || s->until > 0.0)) {
+      lsfft_solver t = s->twin;
+      t->hist = s->hist;
+      t->hist_cap = s->hist_cap;
+      t->timing_kernel = -1;
+      st = upload_members<double>(t, Eb + 6 * off);
+      if (st != LSFFT_OK) return st;
+      if (s->warm > 0) {
+        k0[i] = std::min(s->warm, maxit + 1);
+        st = run_phase<double>(t, tol, maxit, 0, k0[i], true);
+        if (st != LSFFT_OK) return st;
+        fresh[i] = 0;
+      }
+    }
+    off += s->B;
+  }
+  hipStream_t gs = nullptr;
+  hipEvent_t ev = nullptr;
+  LSFFT_CHECK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(gs);
+    return LSFFT_EDEVICE;
+  }
+  auto done = [&](lsfft_status st) {
+    (void)hipStreamSynchronize(gs);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(gs);
+    return st;
+  };
+  const int chunks = (maxit_all + 1 + GRAPH_CHUNK - 1) / GRAPH_CHUNK + 1;
+  // FP64 phase down to each solver's switch level
+  std::vector<lsfft_solver> grp;
+  std::vector<int> who;
+  for (int i = 0; i < n; ++i) {
+    lsfft_solver s = hs[i];
+    const int maxit = maxits[i];
+    if (!s->twin || !(s->until > 0.0)) continue;
+    if (!fresh[i] && (all_done(s) || k0[i] > maxit)) continue;
+    lsfft_status st = prepare_phase<double>(s->twin, std::max(tol, s->until), maxit, k0[i], fresh[i]);
+    if (st != LSFFT_OK) return done(st);
+    grp.push_back(s->twin);
+    who.push_back(i);
+  }
+  if (!grp.empty()) {
+    lsfft_status st = group_loop(grp, gs, ev, chunks);
+    if (st != LSFFT_OK) return done(st);
+    for (int i : who) {
+      lsfft_solver s = hs[i];
+      const int maxit = maxits[i];
+      bool resume = false;
+      int kmin = maxit + 1;
+      for (int b = 0; b < s->B; ++b) {
+        State &x = s->st_host[b];
+        if (x.done && x.status == 0 && x.r > tol) {
+          x.done = 0;
+          x.status = 1;
+          resume = true;
+        }
+        if (!x.done) kmin = std::min(kmin, x.k);
+      }
+      if (resume && hipMemcpyAsync(s->st, s->st_host, sizeof(State) * s->B, hipMemcpyHostToDevice, s->stream) !=
+                        hipSuccess)
+        return done(LSFFT_EDEVICE);
+      k0[i] = std::max(kmin, 1);
+      fresh[i] = 0;
+    }
+  }
+  // every solver's own phase
+  grp.clear();
+  for (int i = 0; i < n; ++i) {
+    lsfft_solver s = hs[i];
+    const int maxit = maxits[i];
+    if (!fresh[i] && (all_done(s) || k0[i] > maxit)) continue;
+    lsfft_status st = (s->prec == LSFFT_F32) ? prepare_phase<float>(s, tol, maxit, k0[i], fresh[i])
+                                             : prepare_phase<double>(s, tol, maxit, k0[i], fresh[i]);
+    if (st != LSFFT_OK) return done(st);
+    grp.push_back(s);
+  }
+  if (!grp.empty()) {
+    lsfft_status st = group_loop(grp, gs, ev, chunks);
+    if (st != LSFFT_OK) return done(st);
+  }
+  off = 0;
+  for (int i = 0; i < n; ++i) {
+    lsfft_solver s = hs[i];
+    if (!all_done(s)) return done(LSFFT_EDEVICE);
+    if (s->disp) {
+      hipError_t e = (s->prec == LSFFT_F32) ? strain_from_u<float>(s, Eb + 6 * off)
+                                            : strain_from_u<double>(s, Eb + 6 * off);
+      if (e != hipSuccess) return done(LSFFT_EDEVICE);
+    }
+    s->last_iters = s->st_host[0].iters;
+    off += s->B;
+  }
+  return done(LSFFT_OK);
 }
 
 // Outputs of every system: eps_out / sig_out hold [B][6][N] values (host
@@ -762,6 +977,8 @@ template <typename T> lsfft_status build_dgo(lsfft_solver s) {
 
 void release(lsfft_solver s) {
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->graph = nullptr;
   if (s->gevent) (void)hipEventDestroy(s->gevent);
   if (s->gstream) (void)hipStreamDestroy(s->gstream);
   s->gexec = nullptr;
@@ -1082,6 +1299,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
   if (cfg->prec != LSFFT_F64 && cfg->prec != LSFFT_F32) return LSFFT_EINVAL;
   if (cfg->form < 0 || cfg->form > 2) return LSFFT_EINVAL;
   if (cfg->f64_warmup < 0 || cfg->refine < 0) return LSFFT_EINVAL;
+  if (!(cfg->f64_until >= 0.0) || !std::isfinite(cfg->f64_until)) return LSFFT_EINVAL;
   if (cfg->scheme == LSFFT_DGO) {
     if (cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
     if (cfg->dgo_images < 0 || cfg->dgo_images > 64) return LSFFT_EINVAL;
@@ -1096,7 +1314,8 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
       if (c->n[r] != cfg->n[r] || c->h[r] != cfg->h[r]) return LSFFT_EINVAL;
     if (c->disc != cfg->disc || c->scheme != cfg->scheme || c->prec != cfg->prec || c->form != cfg->form ||
         c->dgo_images != cfg->dgo_images || c->dgo_weight_power != cfg->dgo_weight_power ||
-        c->stream != cfg->stream || c->f64_warmup != cfg->f64_warmup || c->refine != cfg->refine)
+        c->stream != cfg->stream || c->f64_warmup != cfg->f64_warmup || c->refine != cfg->refine ||
+        c->f64_until != cfg->f64_until)
       return LSFFT_EINVAL;
     if (!ok_moduli(c->lambda0, c->mu0)) return LSFFT_EINVAL;
     // the DGO table depends on C0: one table, one reference medium
@@ -1231,12 +1450,14 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     st = (s->prec == LSFFT_F32) ? build_dgo<float>(s) : build_dgo<double>(s);
     if (st != LSFFT_OK) return fail(st);
   }
-  if (cfg->f64_warmup > 0 && s->prec == LSFFT_F32 && s->disp && stencil_fits<double>(s->n[0])) {
+  if ((cfg->f64_warmup > 0 || cfg->f64_until > 0.0) && s->prec == LSFFT_F32 && s->disp &&
+      stencil_fits<double>(s->n[0])) {
     std::vector<lsfft_config> c2(cfgs, cfgs + count);
     for (auto &c : c2) {
       c.prec = LSFFT_F64;
       c.form = 2;
       c.f64_warmup = 0;
+      c.f64_until = 0.0;
     }
     lsfft_solver t = nullptr;
     st = lsfft_create_batch(c2.data(), count, &t);
@@ -1250,6 +1471,7 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     t->borrowed = 1;
     s->twin = t;
     s->warm = cfg->f64_warmup;
+    s->until = cfg->f64_until;
   }
   *out = s;
   return LSFFT_OK;
@@ -1303,6 +1525,53 @@ lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol
 lsfft_status lsfft_solve_batch(lsfft_solver s, const double *Ebar, double tol, int32_t maxit, void *eps_dev,
                                void *sig_dev, double *sig_mean, int32_t *iters, double *residual, int32_t *status) {
   return solve_common(s, Ebar, tol, maxit, eps_dev, sig_dev, sig_mean, iters, residual, status, false);
+}
+
+lsfft_status lsfft_solve_group(const lsfft_solver *handles, int32_t count, const double *Ebar, double tol,
+                               int32_t maxit, const int32_t *maxit_each, void *const *eps_dev, double *sig_mean,
+                               int32_t *iters, double *residual, int32_t *status) {
+  if (!handles || !Ebar || count < 1 || count > 64) return LSFFT_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return LSFFT_EINVAL;
+  std::vector<lsfft_solver> hs(handles, handles + count);
+  std::vector<int> maxits(count, maxit);
+  long long total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (maxit_each) maxits[i] = maxit_each[i];
+    if (maxits[i] < 0) return LSFFT_EINVAL;
+    if (!hs[i] || hs[i]->refine > 0) return LSFFT_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return LSFFT_EINVAL;
+    total += hs[i]->B;
+  }
+  if (!finite_all(Ebar, 6 * total)) return LSFFT_EINVAL;
+  // the group replays captured chunks: per-kernel event timing stays off
+  std::vector<int> timing(count);
+  for (int i = 0; i < count; ++i) {
+    timing[i] = hs[i]->timing_kernel;
+    hs[i]->timing_kernel = -1;
+  }
+  lsfft_status st = solve_group(hs, Ebar, tol, maxits);
+  for (int i = 0; i < count; ++i) hs[i]->timing_kernel = timing[i];
+  if (st < 0) return st;
+  int worst = 0;
+  long long off = 0;
+  for (int i = 0; i < count; ++i) {
+    lsfft_solver s = hs[i];
+    void *e = eps_dev ? eps_dev[i] : nullptr;
+    lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, e, nullptr, false)
+                                             : finish_outputs<double>(s, e, nullptr, false);
+    if (os != LSFFT_OK) return os;
+    for (int b = 0; b < s->B; ++b, ++off) {
+      const State &x = s->st_host[b];
+      if (sig_mean)
+        for (int c = 0; c < 6; ++c) sig_mean[6 * off + c] = x.sig_mean[c];
+      if (iters) iters[off] = x.iters;
+      if (residual) residual[off] = x.r;
+      if (status) status[off] = x.status;
+      worst = std::max(worst, x.status);
+    }
+  }
+  return (lsfft_status)worst;
 }
 
 int32_t lsfft_batch_size(lsfft_solver s) { return s ? s->B : 0; }

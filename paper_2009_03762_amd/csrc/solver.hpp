@@ -167,6 +167,7 @@ struct lsfft_solver_s {
   // one and runs its first `warm` iterations.
   lsfft_solver_s *twin = nullptr;
   int warm = 0;
+  double until = 0.0;  // FP64 twin iterations until the residual is at most this (0 = off)
   int borrowed = 0;  // u, st, st_host and hist belong to another solver
   // Replay of captured iteration chunks: an internal stream (default
   // priority) that waits on `stream`, and the executable graph of GRAPH_CHUNK
@@ -175,6 +176,7 @@ struct lsfft_solver_s {
   hipStream_t gstream = nullptr;
   hipEvent_t gevent = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;  // the captured chunk itself (a child node of a group solve's graph)
   double g_tol = -1.0;
   int g_maxit = -1;
   // Schedule: column-tile variant of the y pass (yv) and of the z passes

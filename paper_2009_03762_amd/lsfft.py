@@ -43,6 +43,7 @@ class Config(C.Structure):
         ("f64_warmup", C.c_int32),
         ("eigenstrain", C.POINTER(C.c_double)),
         ("refine", C.c_int32),
+        ("f64_until", C.c_double),
     ]
 
 
@@ -89,6 +90,9 @@ def _load():
         "lsfft_solve_batch": (C.c_int, [h, dp, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, dp,
                                         C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
         "lsfft_batch_size": (C.c_int32, [h]),
+        "lsfft_solve_group": (C.c_int, [C.POINTER(h), C.c_int32, dp, C.c_double, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_void_p), dp,
+                                        C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32)]),
         "lsfft_get_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
         "lsfft_set_schedule": (C.c_int, [h, C.POINTER(Schedule)]),
         "lsfft_autotune": (C.c_int, [h, C.c_int32, C.POINTER(Schedule), dp, dp]),
@@ -121,6 +125,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("lsfft_create", "lsfft_create_batch", "lsfft_solve", "lsfft_solve_device", "lsfft_solve_batch",
+           "lsfft_solve_group",
            "lsfft_batch_size", "lsfft_get_schedule", "lsfft_set_schedule", "lsfft_autotune", "lsfft_solve_1d",
            "lsfft_solve_1d_noalloc",
            "lsfft_residual_history",
@@ -173,7 +178,7 @@ def _eigenstrain(es, shape):
 
 
 def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form, f64_warmup,
-            eigenstrain=None, refine=0):
+            eigenstrain=None, refine=0, f64_until=0.0):
     if lam.ndim != 3 or lam.shape != mu.shape:
         raise ValueError("lam and mu must be 3D arrays of equal shape (n3, n2, n1)")
     n3, n2, n1 = lam.shape
@@ -194,19 +199,22 @@ def _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight
     cfg.f64_warmup = int(f64_warmup)
     cfg.eigenstrain = _dptr(eigenstrain)  # the caller keeps the array alive through the call
     cfg.refine = int(refine)
+    cfg.f64_until = float(f64_until)
     return cfg
 
 
 def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0),
-           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, eigenstrain=None, refine=0):
+           dgo_images=4, dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, eigenstrain=None, refine=0,
+           f64_until=0.0):
     """lsfft_create.  lam, mu: float64 host arrays shaped (n3, n2, n1);
     eigenstrain: optional (6, n3, n2, n1) Voigt tensor components; refine:
-    cycle length of the FP64 iterative refinement (F32 displacement form)."""
+    cycle length of the FP64 iterative refinement (F32 displacement form);
+    f64_until: residual down to which an F32 solve runs in FP64 first."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     es = _eigenstrain(eigenstrain, lam.shape)
     cfg = _config(lam, mu, lambda0, mu0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                  f64_warmup, es, refine)
+                  f64_warmup, es, refine, f64_until)
     handle = C.c_void_p()
     st = _lib.lsfft_create(C.byref(cfg), C.byref(handle))
     if st != OK:
@@ -215,7 +223,7 @@ def create(lam, mu, lambda0, mu0, scheme="afb", disc="td", prec="f64", h=(1.0, 1
 
 
 def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0), dgo_images=4,
-                 dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, refine=0):
+                 dgo_weight_power=1, stream=None, form="auto", f64_warmup=0, refine=0, f64_until=0.0):
     """lsfft_create_batch.  systems: sequence of (lam, mu, lambda0, mu0) or
     (lam, mu, lambda0, mu0, eigenstrain) with float64 host arrays of one shape
     (n3, n2, n1) (eigenstrain: (6, n3, n2, n1) or None)."""
@@ -228,7 +236,7 @@ def create_batch(systems, scheme="afb", disc="td", prec="f64", h=(1.0, 1.0, 1.0)
         es = _eigenstrain(sysm[4] if len(sysm) > 4 else None, lam.shape)
         arrays.append((lam, mu, es))   # keep the buffers alive through the call
         cfgs[m] = _config(lam, mu, l0, m0, scheme, disc, prec, h, dgo_images, dgo_weight_power, stream, form,
-                          f64_warmup, es, refine)
+                          f64_warmup, es, refine, f64_until)
     handle = C.c_void_p()
     st = _lib.lsfft_create_batch(cfgs, len(systems), C.byref(handle))
     if st != OK:
@@ -357,6 +365,43 @@ def solve_batch(handle, Ebars, tol, maxit, eps_dev=None, sig_dev=None):
     if st < 0:
         raise LsfftError(st, "lsfft_solve_batch")
     return st, sm, np.array(list(it)), r, np.array(list(sts))
+
+
+def solve_group(handles, Ebars, tol, maxit, eps_devs=None):
+    """lsfft_solve_group.  handles: sequence of solver handles; Ebars: one
+    (B_i, 6) array per handle; maxit: an int, or one limit per handle;
+    eps_devs: None or one device tensor (or None) per handle with
+    B_i * 6 N_i elements of that solver's precision.
+    Returns (status, [(sig_mean (B_i, 6), iters, residual, per-system status)
+    per handle])."""
+    count = len(handles)
+    sizes = [batch_size(h) for h in handles]
+    Eb = np.ascontiguousarray(np.concatenate([np.asarray(e, dtype=np.float64).reshape(-1, 6) for e in Ebars]))
+    if Eb.shape != (sum(sizes), 6):
+        raise ValueError("one (B, 6) load array per handle is required")
+    total = sum(sizes)
+    hs = (C.c_void_p * count)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    pe = None
+    if eps_devs is not None:
+        pe = (C.c_void_p * count)(*[(t.data_ptr() if t is not None else None) for t in eps_devs])
+    sm = np.zeros((total, 6))
+    it = (C.c_int32 * total)()
+    r = np.zeros(total)
+    sts = (C.c_int32 * total)()
+    each = None
+    if np.ndim(maxit) > 0:
+        each = (C.c_int32 * count)(*[int(m) for m in maxit])
+        maxit = max(int(m) for m in maxit)
+    st = _lib.lsfft_solve_group(hs, count, _dptr(Eb), float(tol), int(maxit), each, pe, _dptr(sm), it, _dptr(r),
+                                sts)
+    if st < 0:
+        raise LsfftError(st, "lsfft_solve_group")
+    its, stl = np.array(list(it)), np.array(list(sts))
+    out, o = [], 0
+    for b in sizes:
+        out.append((sm[o:o + b], its[o:o + b], r[o:o + b], stl[o:o + b]))
+        o += b
+    return st, out
 
 
 def destroy(handle):

@@ -60,30 +60,34 @@ def _inclusion(shape, side, chi):
     return lam, mu, l0, m0
 
 
-@pytest.mark.parametrize("scheme,n", [("afb", 24), ("fb", 16)])
-def test_reaches_fp64_tolerance(L, scheme, n):
-    """Contrast 10, tol 1e-9 (orders below the F32 floor): stop in the
+@pytest.mark.parametrize("scheme,n,cycle,slack", [("afb", 24, 8, 2), ("afb", 32, 8, 2), ("fb", 16, 16, 2),
+                                                  ("afb", 24, 16, 4)])
+def test_reaches_fp64_tolerance(L, scheme, n, cycle, slack):
+    """Contrast 10, tol 1e-10 (orders below the F32 floor): stop in the
     oracle's iteration count (+-2) with the oracle's iterate, where plain F32
-    does not converge in three times as many iterations.  Cycles of 8 keep the
-    FP32 rounding of the last cycle, relative to the residual at its start,
-    well below the final residual."""
-    tol = 1e-9
-    print(f"\n[refine tol] {scheme} n={n} tol={tol}", flush=True)
+    does not converge in three times as many iterations.  AFB cycles longer
+    than 8 iterations reach the tolerance too, but a cycle whose residual
+    reduction exceeds about 1e-3 meets the F32 floor of the sweeps on delta
+    (measured: 59 iterations against the oracle's 56 with cycles of 16 at
+    24^3 and 32^3, 74 with cycles of 32; FB loses none)."""
+    tol = 1e-10
+    print(f"\n[refine tol] {scheme} n={n} cycle={cycle} tol={tol}", flush=True)
     lam, mu, l0, m0 = _inclusion((n, n, n), (n // 2,) * 3, 10.0)
-    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=8)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=cycle)
     out = s.solve(EB, tol=tol, maxit=5000)
     hist = s.residual_history()
     s.close()
     k = out["iters"]
     assert out["status"] == L.OK and out["residual"] <= tol
     k_ref, h_ref, it = _oracle_at(lam, mu, EB, l0, m0, NAMES[scheme], tol, k)
-    assert k_ref is not None and abs(k - k_ref) <= 2
+    assert k_ref is not None and abs(k - k_ref) <= slack
     # eps is stored in FP32: its rounding (6e-8) is the floor of the field bar
     assert rel(out["eps"], it["eps"]) < 1e-6
     assert rel(out["sig_mean"], it["sig_mean"]) < 1e-6
     # the reported residual is an FP64 evaluation of the final iterate, whose
     # FP32 rounding (relative to the residual of its cycle) it also sees
-    assert abs(out["residual"] - h_ref[k]) <= 0.2 * h_ref[k]
+    if slack <= 2:
+        assert abs(out["residual"] - h_ref[k]) <= 0.2 * h_ref[k]
     assert hist[-1] == out["residual"]
     plain = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement")
     p = plain.solve(EB, tol=tol, maxit=3 * k, fields=False)
@@ -255,3 +259,85 @@ def test_batch_mixing_eigenstrain(L):
         assert k_ref is not None and abs(int(it[b]) - k_ref) <= 2
         assert rel(eps[b], got["eps"]) < 1e-6
         assert rel(sm[b], got["sig_mean"]) < 1e-6
+
+
+@pytest.mark.parametrize("scheme", ["afb", "fb"])
+def test_f64_until_certifies_tolerance_at_high_contrast(L, scheme):
+    """Contrast 1e3, tol 1e-7: FP64 iterations until r <= 300 tol (the same
+    residuals as the oracle's), then refined F32 cycles of 8 whose stop is an
+    FP64 evaluation; the solve stops OK at r <= tol within 3 iterations of the
+    oracle's count, with the oracle's iterate."""
+    tol = 1e-7
+    print(f"\n[f64_until] {scheme} tol={tol}", flush=True)
+    lam, mu, l0, m0 = _inclusion((24, 24, 24), (12, 12, 12), 1e3)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=8, f64_until=300 * tol)
+    out = s.solve(EB, tol=tol, maxit=5000)
+    hist = s.residual_history()
+    s.close()
+    k = out["iters"]
+    assert out["status"] == L.OK and out["residual"] <= tol
+    k_ref, h_ref, it = _oracle_at(lam, mu, EB, l0, m0, NAMES[scheme], tol, k)
+    assert k_ref is not None and abs(k - k_ref) <= 3
+    # the FP64 phase: the oracle's residuals until the switch
+    ksw = int(np.nonzero(h_ref <= 300 * tol)[0][0])
+    assert rel(hist[:ksw + 1], h_ref[:ksw + 1]) < 1e-9
+    assert rel(out["eps"], it["eps"]) < 1e-6
+    assert rel(out["sig_mean"], it["sig_mean"]) < 1e-6
+
+
+def test_f64_until_batch_switches_each_system_on_its_own(L):
+    """Four load cases of one cell, contrast 1e2: each system leaves its FP64
+    phase at its own iteration and stops on its own FP64-confirmed test; a
+    zero load stops at once."""
+    print("\n[f64_until batch]", flush=True)
+    tol = 1e-8
+    lam, mu, l0, m0 = _inclusion((16, 16, 16), (8, 8, 8), 1e2)
+    loads = [EB, np.array([0, 0, 0, 0, 0, 1e-3]), np.zeros(6), np.array([2e-3, 0, 0, 0, 0, 0])]
+    h = L.create_batch([(lam, mu, l0, m0)] * len(loads), scheme="afb", prec="f32", form="displacement", refine=8,
+                       f64_until=300 * tol)
+    try:
+        dev = torch.zeros((len(loads), 6) + lam.shape, dtype=torch.float32, device="cuda")
+        st, sm, it, r, bst = L.solve_batch(h, np.stack(loads), tol, 5000, eps_dev=dev)
+        torch.cuda.synchronize()
+        eps = dev.cpu().double().numpy()
+    finally:
+        L.destroy(h)
+    for b, E in enumerate(loads):
+        if not np.any(E):
+            assert it[b] == 0 and bst[b] == L.OK and np.abs(eps[b]).max() == 0.0
+            continue
+        assert bst[b] == L.OK and r[b] <= tol
+        k_ref, _, got = _oracle_at(lam, mu, E, l0, m0, "AFB", tol, int(it[b]))
+        assert k_ref is not None and abs(int(it[b]) - k_ref) <= 3
+        assert rel(eps[b], got["eps"]) < 1e-6
+        assert rel(sm[b], got["sig_mean"]) < 1e-6
+
+
+def test_f64_until_edge_cases(L):
+    """A switch level above r_0 (no FP64 iteration is needed: the F32 phase
+    starts at k = 0), a switch level below tol (the solve stays in FP64
+    throughout and matches F64), together with f64_warmup (at least that
+    many FP64 iterations), and invalid levels."""
+    print("\n[f64_until edges]", flush=True)
+    lam, mu, l0, m0 = _inclusion((16, 12, 8), (8, 6, 4), 10.0)
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=1e-9, maxit=2000)
+    a = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", refine=8, f64_until=1e3)
+    oa = a.solve(EB, tol=1e-9, maxit=2000)
+    a.close()
+    assert oa["status"] == L.OK and abs(oa["iters"] - ref.iters) <= 2 and rel(oa["eps"], ref.eps) < 1e-6
+    b = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", f64_until=1e-12)
+    ob = b.solve(EB, tol=1e-9, maxit=2000)
+    hb = b.residual_history()
+    b.close()
+    assert ob["status"] == L.OK and ob["iters"] == ref.iters
+    assert rel(hb, np.array(ref.history)) < 1e-9
+    c = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", refine=8, f64_warmup=20,
+                 f64_until=1e3)
+    oc = c.solve(EB, tol=1e-9, maxit=2000)
+    hc = c.residual_history()
+    c.close()
+    assert oc["status"] == L.OK and rel(hc[:20], np.array(ref.history[:20])) < 1e-9
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(L.LsfftError) as e:
+            L.create(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", f64_until=bad)
+        assert e.value.status == L.EINVAL
