@@ -1,0 +1,131 @@
+"""One graph over cells of different sizes (lsfft_solve_group) against each
+solver's own batched solve and the oracle: the batched effective-stiffness
+setting of Sec. 6 (six unit loads per cell, the loads of the cubic-inclusion
+benchmark generalised to random sphere microstructures), with every size's
+chunk of iterations a child of one graph and each system stopping on its own
+device-side test."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import solve3d  # noqa: E402
+from paper_2009_03762_amd import inputs  # noqa: E402
+
+from oracle_ref import rel  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _cell(n, seed, log10_E=(0.0, 3.0)):
+    E = inputs.poisson_spheres(n, seed, log10_E=log10_E)
+    lam, mu = inputs.lame_from_young(E, 0.3)
+    lo, hi = inputs.lame_from_young(E.min(), 0.3), inputs.lame_from_young(E.max(), 0.3)
+    return lam, mu, 0.5 * float(lo[0] + hi[0]), 0.5 * float(lo[1] + hi[1])
+
+
+def _handles(L, specs, **kw):
+    """specs: [(n, seeds)] -> one batch handle per size holding every seed's
+    cell under the six unit loads."""
+    units = inputs.mandel_unit_strains()
+    hs, loads, shapes = [], [], []
+    for n, seeds in specs:
+        cells = [_cell(n, sd) for sd in seeds]
+        hs.append(L.create_batch([c for c in cells for _ in range(6)], scheme="afb", **kw))
+        loads.append(np.tile(units, (len(seeds), 1)))
+        shapes.append((6 * len(seeds), 6, n, n, n))
+    return hs, loads, shapes
+
+
+def _run_group(L, hs, loads, shapes, dt, tol, maxit):
+    devs = [torch.zeros(sh, dtype=dt, device="cuda") for sh in shapes]
+    st, res = L.solve_group(hs, loads, tol, maxit, eps_devs=devs)
+    torch.cuda.synchronize()
+    return st, res, [d.cpu().numpy() for d in devs]
+
+
+def _run_each(L, hs, loads, shapes, dt, tol, maxit):
+    out = []
+    for h, E, sh in zip(hs, loads, shapes):
+        d = torch.zeros(sh, dtype=dt, device="cuda")
+        st, sm, it, r, sts = L.solve_batch(h, E, tol, maxit, eps_dev=d)
+        torch.cuda.synchronize()
+        out.append((sm, it, r, sts, d.cpu().numpy()))
+    return out
+
+
+SPECS = [(32, (1001, 1002)), (48, (1003,)), (64, (1004,))]
+
+
+@pytest.mark.parametrize("prec,kw,tol", [("f64", {}, 1e-8), ("f32", {}, 1e-4),
+                                         ("f32", {"f64_warmup": 5}, 1e-4),
+                                         ("f32", {"f64_until": 3e-4}, 1e-5)])
+def test_group_equals_each_batch(L, prec, kw, tol):
+    """Every system's iterate, mean stress, iteration count and status equal
+    those of its solver's own lsfft_solve_batch: the same kernels per solver
+    (sphere contrasts up to 1e3: some systems stop on tol, others at maxit)."""
+    print(f"\n[group] {prec} {kw} tol={tol}", flush=True)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    hs, loads, shapes = _handles(L, SPECS, prec=prec, **kw)
+    try:
+        st, res, eps = _run_group(L, hs, loads, shapes, dt, tol, 800)
+        each = _run_each(L, hs, loads, shapes, dt, tol, 800)
+    finally:
+        for h in hs:
+            L.destroy(h)
+    for (sm, it, r, sts), e, (sm1, it1, r1, sts1, e1) in zip(res, eps, each):
+        assert np.array_equal(it, it1) and np.array_equal(sts, sts1)
+        assert np.array_equal(sm, sm1) and np.array_equal(r, r1)
+        assert np.array_equal(e, e1)
+
+
+def test_group_matches_oracle(L):
+    """Converged FP64 group solve of a 16^3 and a 24^3 sphere cell (sphere
+    contrast up to 10) under two loads against the oracle (iteration counts
+    equal, fields 1e-11)."""
+    print("\n[group oracle]", flush=True)
+    tol = 1e-9
+    loads = np.array([[1e-3, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 1e-3]])
+    hs, cells = [], []
+    for n, sd in ((16, 7), (24, 8)):
+        c = _cell(n, sd, log10_E=(0.0, 1.0))
+        cells.append(c)
+        hs.append(L.create_batch([c, c], scheme="afb", prec="f64"))
+    try:
+        devs = [torch.zeros((2, 6, n, n, n), dtype=torch.float64, device="cuda") for n in (16, 24)]
+        st, res = L.solve_group(hs, [loads, loads], tol, 3000, eps_devs=devs)
+        torch.cuda.synchronize()
+        eps = [d.cpu().numpy() for d in devs]
+    finally:
+        for h in hs:
+            L.destroy(h)
+    assert st == L.OK
+    for (lam, mu, l0, m0), (sm, it, r, sts), e in zip(cells, res, eps):
+        for b in range(2):
+            ref = solve3d.solve_gfp(lam, mu, loads[b], l0, m0, scheme="AFB", tol=tol, maxit=3000)
+            assert sts[b] == L.OK and it[b] == ref.iters
+            assert rel(e[b], ref.eps) < 1e-11
+            assert rel(sm[b], ref.sig_mean) < 1e-11
+
+
+def test_group_rejects_refined_and_repeated_handles(L):
+    lam, mu, l0, m0 = _cell(16, 9)
+    a = L.create_batch([(lam, mu, l0, m0)], scheme="afb", prec="f64")
+    b = L.create_batch([(lam, mu, l0, m0)], scheme="afb", prec="f32", form="displacement", refine=8)
+    try:
+        E = [np.array([[1e-3, 0, 0, 0, 0, 0]])]
+        for hs, loads in (([a, a], E * 2), ([a, b], E * 2)):
+            with pytest.raises(L.LsfftError) as e:
+                L.solve_group(hs, loads, 1e-6, 100)
+            assert e.value.status == L.EINVAL
+    finally:
+        L.destroy(a)
+        L.destroy(b)
