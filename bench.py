@@ -19,11 +19,13 @@ solver's stream inside the timed region.  "equal_accuracy" gives, for the
 FP64 path and the FP32 paths (displacement form, the same with five FP64
 warm-start iterations, strain form), the iterations and wall time needed to bring
 the strain field within a relative L2 error of 1e-5 and 1e-6 of a tight FP64
-solution, and the FP32 speedups at equal accuracy.  "batched_ceff" times the
-effective stiffness (six load cases) of random cells of five sizes (12 by
-default, `--batched-cells 48` for the full set) as plain FP64 solves, as
-batched FP64 solves, and as batched FP32 solves, one size group after the
-other and with every size group on its own stream.
+solution, and the FP32 speedups at equal accuracy; its "certified_stop" rows
+solve to r <= 1e-6 with the stopping test itself: FP64, and FP32 with FP64
+iterations down to r = 3e-4 followed by FP64-refined F32 cycles of 8 (every
+reported residual an FP64 evaluation).  "batched_ceff" times the effective
+stiffness (six load cases) of 48 random cells of five sizes: plain FP64
+solves (timed on a quarter of the cells, same size mix), all sizes in one
+group graph in FP64 and in FP32, and FP32 with one stream per size group.
 """
 from __future__ import annotations
 
@@ -256,25 +258,55 @@ def equal_accuracy(n, targets=(1e-5, 1e-6), kmax=500, kstep=10):
             if base and got:
                 speed[f"{name}@{key}"] = base["ms"] / got["ms"]
     out["speedup_over_f64"] = speed
+    # solves stopped by the stopping test at r <= 1e-6 (reading R2): F64, and
+    # F32 certified by FP64 evaluations (FP64 iterations until r <= 3e-4,
+    # then refinement cycles of 8)
+    tol = 1e-6
+    rows = {}
+    for name, kw in (("f64", dict(prec="f64")),
+                     ("f32_until3e-4_refine8", dict(prec="f32", f64_until=3e-4, refine=8))):
+        dt = torch.float64 if kw["prec"] == "f64" else torch.float32
+        e = torch.zeros(shape, dtype=dt, device="cuda")
+        s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", disc="pcd", form="displacement", **kw)
+        s.solve_device(Eb, tol=tol, maxit=1000, eps_dev=e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = s.solve_device(Eb, tol=tol, maxit=1000, eps_dev=e)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        err = (torch.linalg.vector_norm(e.double() - ref) / rn).item()
+        s.close()
+        del e
+        rows[name] = {"status": lsfft.status_string(o["status"]), "iters": int(o["iters"]),
+                      "residual": float(o["residual"]), "ms": ms, "field_err": err}
+        print(f"[bench] certified stop {name}: {rows[name]}", file=sys.stderr, flush=True)
+    rows["f32_speedup_over_f64"] = rows["f64"]["ms"] / rows["f32_until3e-4_refine8"]["ms"]
+    out["certified_stop"] = {"tol": tol, "rows": rows}
     del ref
     torch.cuda.synchronize()
     return out
 
 
-def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
+def batched_ceff(ncells=48, seed0=1000, tol=1e-6, plain_stride=4):
     """Effective stiffness (six unit load cases) of `ncells` random cells:
     sizes drawn from {32, 48, 64, 96, 128}^3, Poisson(20) spheres of radius
     U[3, 8] voxels, log10 E uniform in [0, 3] per sphere, matrix E = 1,
-    nu = 0.3, C0 = mean of the Lame moduli of the extreme E, AFB.  Three
-    paths, solve time only (handles created beforehand):
-      plain   FP64, one solve per load case and cell (tol);
-      batched FP64, one batch handle per cell size holding every cell and load
-              case, replayed iteration graphs (tol);
-      batched FP32 with five FP64 warm-start iterations, run for the largest
-              FP64 iteration count of its size group (the FP32 residual
-              cannot certify tol at these contrasts);
-    with the error of each path's C_eff against the plain FP64 one."""
+    nu = 0.3, C0 = mean of the Lame moduli of the extreme E, AFB.  Paths,
+    solve time only (handles created beforehand):
+      plain   FP64, one solve per load case and cell (tol), timed on every
+              `plain_stride`-th cell (the same size mix): its rate in
+              GVoxel-iter/s prices the whole set;
+      group   one batch handle per cell size holding every cell and load case,
+              all sizes solved by lsfft_solve_group (one graph launch per
+              chunk of iterations over every size): FP64 to tol (the
+              reference C_eff), and FP32 with five FP64 warm-start iterations
+              run for the largest FP64 iteration count of each size group
+              (the FP32 residual cannot certify tol at these contrasts);
+      streams the same FP32 handles, each size group solved by its own host
+              thread on its own stream (the previous way to overlap sizes);
+    with each path's C_eff error against the FP64 group reference."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
 
     from paper_2009_03762_amd import inputs, lsfft
     rng = np.random.default_rng(seed0)
@@ -289,6 +321,10 @@ def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
     units = inputs.mandel_unit_strains()
     mandel = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
     maxit = 20000
+    groups = {}
+    for i, c in enumerate(cells):
+        groups.setdefault(c[0], []).append(i)
+    order = sorted(groups.items())
 
     def sync_time(f):
         torch.cuda.synchronize()
@@ -297,93 +333,93 @@ def batched_ceff(ncells=48, seed0=1000, tol=1e-6):
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    # plain FP64
-    ref, iters64, t_plain, vox_it = [], [], 0.0, 0
-    for (n, lam, mu, l0, m0) in cells:
+    def ceff(sm, q):
+        return np.stack([mandel * sm[6 * q + J] for J in range(6)], axis=1)
+
+    def make(prec, warm, stream=None):
+        hs = []
+        for n, ix in order:
+            systems = [(cells[i][1], cells[i][2], cells[i][3], cells[i][4]) for i in ix for J in range(6)]
+            hs.append(lsfft.create_batch(systems, scheme="afb", prec=prec, f64_warmup=warm,
+                                         stream=stream[n] if stream else None))
+        return hs
+
+    loads = [np.tile(units, (len(ix), 1)) for n, ix in order]
+    out = {"cells": ncells, "sizes": {str(n): len(ix) for n, ix in order}}
+    # FP64 group: the reference effective stiffness and iteration counts
+    hs = make("f64", 0)
+    (st, res), t64 = sync_time(lambda: lsfft.solve_group(hs, loads, tol, maxit))
+    for h in hs:
+        lsfft.destroy(h)
+    ref, its64, vit64 = {}, {}, 0
+    for (n, ix), (sm, it, r, sts) in zip(order, res):
+        for q, i in enumerate(ix):
+            ref[i] = ceff(sm, q)
+            its64[i] = [int(v) for v in it[6 * q:6 * q + 6]]
+            vit64 += n ** 3 * int(np.sum(it[6 * q:6 * q + 6]))
+    converged = all(int(v) == lsfft.OK for (_, _, _, sts) in res for v in sts)
+    out["group_f64"] = {"seconds": t64, "GVoxel_iter_per_s": vit64 / t64 / 1e9, "all_converged": converged,
+                        "iters_mean": float(np.mean(list(its64.values()))),
+                        "iters_max": int(np.max(list(its64.values())))}
+    print(f"[bench] batched: FP64 group done ({t64:.2f} s)", file=sys.stderr, flush=True)
+    # plain FP64 on a stratified subset of the cells
+    t_plain, vit_plain, err_plain = 0.0, 0, 0.0
+    subset = list(range(0, ncells, plain_stride))
+    for i in subset:
+        n, lam, mu, l0, m0 = cells[i]
         s = lsfft.Solver(lam, mu, l0, m0, scheme="afb", prec="f64")
         M = np.zeros((6, 6))
-        its = []
         for J in range(6):
             r, dt = sync_time(lambda: s.solve_device(units[J], tol=tol, maxit=maxit))
             t_plain += dt
             M[:, J] = mandel * r["sig_mean"]
-            its.append(r["iters"])
-            vox_it += n ** 3 * r["iters"]
+            vit_plain += n ** 3 * r["iters"]
         s.close()
-        ref.append(M)
-        iters64.append(its)
-    print(f"[bench] batched: plain FP64 done ({t_plain:.2f} s)", file=sys.stderr, flush=True)
-    groups = {}
-    for i, c in enumerate(cells):
-        groups.setdefault(c[0], []).append(i)
-    out = {"cells": ncells, "sizes": {str(n): len(ix) for n, ix in sorted(groups.items())},
-           "plain_f64": {"seconds": t_plain, "GVoxel_iter_per_s": vox_it / t_plain / 1e9,
-                         "iters_mean": float(np.mean(iters64)), "iters_max": int(np.max(iters64))}}
-    for name, prec, warm, tune in (("batched_f64", "f64", 0, False), ("batched_f32_warm5", "f32", 5, False),
-                                   ("batched_f32_warm5_tuned", "f32", 5, True)):
-        t_tot, err, vit, t_tune, scheds = 0.0, 0.0, 0, 0.0, {}
-        for n, ix in sorted(groups.items()):
-            systems = [(cells[i][1], cells[i][2], cells[i][3], cells[i][4]) for i in ix for J in range(6)]
-            h = lsfft.create_batch(systems, scheme="afb", prec=prec, f64_warmup=warm)
-            if tune:
-                (sch, ms0, ms1), dt = sync_time(lambda: lsfft.autotune(h, 16))
-                t_tune += dt
-                scheds[str(n)] = {"schedule": sch, "default_ms_per_iter": ms0, "tuned_ms_per_iter": ms1}
-            Ebs = np.tile(units, (len(ix), 1))
-            if prec == "f64":
-                (st, sm, it, r, sts), dt = sync_time(lambda: lsfft.solve_batch(h, Ebs, tol, maxit))
-            else:
-                K = int(max(max(iters64[i]) for i in ix))
-                (st, sm, it, r, sts), dt = sync_time(lambda: lsfft.solve_batch(h, Ebs, 0.0, K))
-            lsfft.destroy(h)
-            t_tot += dt
-            vit += n ** 3 * int(np.sum(it))
-            for q, i in enumerate(ix):
-                M = np.stack([mandel * sm[6 * q + J] for J in range(6)], axis=1)
-                err = max(err, float(np.linalg.norm(M - ref[i]) / np.linalg.norm(ref[i])))
-        out[name] = {"seconds": t_tot, "GVoxel_iter_per_s": vit / t_tot / 1e9, "speedup_over_plain_f64": t_plain / t_tot,
-                     "max_rel_err_ceff_vs_plain_f64": err}
-        if tune:
-            out[name]["tune_seconds"] = t_tune
-            out[name]["schedules"] = scheds
-        print(f"[bench] batched: {name} done ({t_tot:.2f} s)", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-    # the same batches with every size group on its own stream, issued from
-    # one host thread per group (the library call releases the GIL), so that
-    # the small groups' launches fill the GPU beside the large ones
-    from concurrent.futures import ThreadPoolExecutor
-    for name, prec, warm in (("batched_f64_streams", "f64", 0), ("batched_f32_warm5_streams", "f32", 5)):
-        handles = []
-        for n, ix in sorted(groups.items()):
-            systems = [(cells[i][1], cells[i][2], cells[i][3], cells[i][4]) for i in ix for J in range(6)]
-            stream = torch.cuda.Stream()
-            h = lsfft.create_batch(systems, scheme="afb", prec=prec, f64_warmup=warm, stream=stream)
-            K = int(max(max(iters64[i]) for i in ix))
-            handles.append((n, ix, h, stream, np.tile(units, (len(ix), 1)), K))
+        err_plain = max(err_plain, float(np.linalg.norm(M - ref[i]) / np.linalg.norm(ref[i])))
+    rate_plain = vit_plain / t_plain / 1e9
+    t_plain_all = vit64 / (rate_plain * 1e9)
+    out["plain_f64"] = {"cells_timed": len(subset), "seconds_timed": t_plain, "GVoxel_iter_per_s": rate_plain,
+                        "seconds_for_all_cells": t_plain_all, "max_rel_err_ceff_vs_group_f64": err_plain}
+    out["group_f64"]["speedup_over_plain_f64"] = t_plain_all / t64
+    print(f"[bench] batched: plain FP64 on {len(subset)} cells done ({t_plain:.2f} s)", file=sys.stderr, flush=True)
+    K = [int(max(max(its64[i]) for i in ix)) for n, ix in order]
 
-        def run(item):
-            n, ix, h, stream, Ebs, K = item
-            if prec == "f64":
-                return lsfft.solve_batch(h, Ebs, tol, maxit)
-            return lsfft.solve_batch(h, Ebs, 0.0, K)
-
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=len(handles)) as pool:
-            results = list(pool.map(run, handles))
-        torch.cuda.synchronize()
-        t_tot = time.perf_counter() - t0
+    def score(res_list):
         err, vit = 0.0, 0
-        for (n, ix, h, stream, Ebs, K), (st, sm, it, r, sts) in zip(handles, results):
+        for (n, ix), (sm, it, r, sts) in zip(order, res_list):
             vit += n ** 3 * int(np.sum(it))
             for q, i in enumerate(ix):
-                M = np.stack([mandel * sm[6 * q + J] for J in range(6)], axis=1)
-                err = max(err, float(np.linalg.norm(M - ref[i]) / np.linalg.norm(ref[i])))
-            lsfft.destroy(h)
-        out[name] = {"seconds": t_tot, "GVoxel_iter_per_s": vit / t_tot / 1e9, "speedup_over_plain_f64": t_plain / t_tot,
-                     "max_rel_err_ceff_vs_plain_f64": err, "streams": len(handles)}
-        print(f"[bench] batched: {name} done ({t_tot:.2f} s)", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
+                err = max(err, float(np.linalg.norm(ceff(sm, q) - ref[i]) / np.linalg.norm(ref[i])))
+        return err, vit
+
+    # FP32 + warm start, one group graph over every size
+    hs = make("f32", 5)
+    (st, res), t32 = sync_time(lambda: lsfft.solve_group(hs, loads, 0.0, K))
+    for h in hs:
+        lsfft.destroy(h)
+    err, vit = score(res)
+    out["group_f32_warm5"] = {"seconds": t32, "GVoxel_iter_per_s": vit / t32 / 1e9,
+                              "speedup_over_plain_f64": t_plain_all / t32, "speedup_over_group_f64": t64 / t32,
+                              "max_rel_err_ceff_vs_group_f64": err}
+    print(f"[bench] batched: FP32 group done ({t32:.2f} s)", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    # the same FP32 handles, one host thread and stream per size group
+    streams = {n: torch.cuda.Stream() for n, ix in order}
+    hs = make("f32", 5, streams)
+    items = list(zip(hs, loads, K))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=len(items)) as pool:
+        rs = list(pool.map(lambda it: lsfft.solve_batch(it[0], it[1], 0.0, it[2]), items))
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for h in hs:
+        lsfft.destroy(h)
+    err, vit = score([(sm, it, r, sts) for (st, sm, it, r, sts) in rs])
+    out["streams_f32_warm5"] = {"seconds": ts, "GVoxel_iter_per_s": vit / ts / 1e9, "streams": len(items),
+                                "speedup_over_plain_f64": t_plain_all / ts, "max_rel_err_ceff_vs_group_f64": err}
+    print(f"[bench] batched: FP32 streams done ({ts:.2f} s)", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
     return out
 
 
@@ -636,8 +672,8 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-cells", type=int, default=12,
-                    help="cells of the batched effective-stiffness measurement (48 for the full set)")
+    ap.add_argument("--batched-cells", type=int, default=48,
+                    help="cells of the batched effective-stiffness measurement (48: the full set)")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the bench line: iterations to tolerance for every configuration")
     ap.add_argument("--copy-probe", action="store_true")
