@@ -70,10 +70,15 @@ typedef enum { LSFFT_BASIC = 0, LSFFT_FB = 1, LSFFT_AFB = 2, LSFFT_DGO = 3, LSFF
 
 /* F64: all arithmetic in FP64.  F32: strain, stress, FFTs and the Green step
  * in FP32; the displacement of the displacement form, the residual, mean
- * stress and convergence reductions in FP64.  With a stiffness contrast chi
- * the FP32 equilibrium residual has a floor of roughly chi x 1e-8 (about 2e-5
- * at chi = 1e3): a tolerance below it is not reached (LSFFT_ENOTCONV after
- * maxit), although the fields reach FP64 accuracy well before. */
+ * stress and convergence reductions in FP64.  The F32 equilibrium residual
+ * has a floor that depends on the form and the size: in the strain form
+ * roughly chi x 1e-8 at stiffness contrast chi (about 2e-5 at chi = 1e3); in
+ * the displacement form about (n/2)^2 x 2^-24 (about 1e-3 at 256^3), from
+ * FP32 rounding of the displacement updates, which the discrete divergence
+ * of the stiffness amplifies at high frequencies.  A tolerance below the
+ * floor is not reached (LSFFT_ENOTCONV after maxit), although the fields
+ * reach FP64 accuracy well before; f64_until with refine (see lsfft_config)
+ * certifies such tolerances in F32 from FP64 evaluations of the residual. */
 typedef enum { LSFFT_F64 = 0, LSFFT_F32 = 1 } lsfft_prec;
 
 typedef enum {
@@ -197,9 +202,12 @@ lsfft_status lsfft_create(const lsfft_config *cfg, lsfft_solver *out);
  * entry points and lsfft_residual_history act on system 0. */
 lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_solver *out);
 
-/* Solve for macroscopic strain Ebar[6] (Voigt tensor components).  Stops at
- * the first k with r_k <= tol (returns LSFFT_OK) or at k = maxit
- * (LSFFT_ENOTCONV).  r_k is the relative equilibrium norm
+/* Solve for macroscopic strain Ebar[6] (Voigt tensor components): the
+ * fixed point of Sec. 5.2 (TD algorithm, displacement form; the PCD
+ * algorithm of Sec. 5.4 has the same iterates for BASIC, FB and AFB) or the
+ * DGO algorithm of Sec. 5.4 (polarisation form), from u = 0 (eps = Ebar).
+ * Stops at the first k with r_k <= tol (returns LSFFT_OK), at k = maxit
+ * (LSFFT_ENOTCONV), or on divergence (LSFFT_EDIVERGED, see lsfft_status).  r_k is the relative equilibrium norm
  * sqrt(sum_xi |sigma_hat(xi) q^b(xi)|^2) / |sigma_hat(0)|_F evaluated before
  * the k-th update (BASIC, FB, AFB), or |eps^k - eps^{k-1}| / (sqrt(N)|Ebar|_F)
  * (DGO; with an eigenstrain and Ebar = 0 the RMS over the voxels of
@@ -213,9 +221,11 @@ lsfft_status lsfft_solve(lsfft_solver s, const double Ebar[6], double tol, int32
                          double *eps, double *sig, double sig_mean[6], int32_t *iters,
                          double *residual);
 
-/* Same as lsfft_solve with DEVICE output pointers of the solver's precision
- * (float for F32, double for F64), 6N elements each, field layout; either may
- * be NULL.  No host copies of fields are made. */
+/* Same as lsfft_solve (Sec. 5.2 / 5.4, same stopping rule) with DEVICE output
+ * pointers of the solver's precision (float for F32, double for F64), 6N
+ * elements each, field layout, caller-owned; either may be NULL.  No host
+ * copies of fields are made; sig_mean, iters and residual are HOST.  Errors
+ * as lsfft_solve (EINVAL on a batch handle with count > 1). */
 lsfft_status lsfft_solve_device(lsfft_solver s, const double Ebar[6], double tol, int32_t maxit,
                                 void *eps_dev, void *sig_dev, double sig_mean[6],
                                 int32_t *iters, double *residual);
@@ -368,7 +378,11 @@ const char *lsfft_kernel_name(int32_t kernel_id);
  * small for the string (nothing is written then).  Launches nothing. */
 lsfft_status lsfft_describe(lsfft_solver s, char *buf, int32_t cap);
 
-/* Release all device memory of the solver.  lsfft_destroy(NULL) is a no-op. */
+/* Release all device memory and streams of the solver created by
+ * lsfft_create or lsfft_create_batch (the data of the problem statement of
+ * Sec. 5.2: moduli, tables, the DGO table of Sec. 5.4, iterate buffers);
+ * the handle is invalid afterwards.  Waits for the solver's work to finish.
+ * lsfft_destroy(NULL) is a no-op and returns LSFFT_OK. */
 lsfft_status lsfft_destroy(lsfft_solver s);
 
 /* ---------------------------------------------------------------- 1D

@@ -640,9 +640,6 @@ lsfft_status run_solve(lsfft_solver s, const double *Eb, double tol, int maxit) 
     if (ps != LSFFT_OK) return ps;
   }
   if (!all_done(s)) return LSFFT_EDEVICE;
-  if (s->disp) {
-    LSFFT_CHECK(strain_from_u<T>(s, Eb));
-  }
   s->last_iters = s->st_host[0].iters;
   if (s->timing_kernel >= 0 && s->ev_used >= 2) {
     double tot = 0.0;
@@ -826,11 +823,6 @@ lsfft_status solve_group(const std::vector<lsfft_solver> &hs, const double *Eb, 
   for (int i = 0; i < n; ++i) {
     lsfft_solver s = hs[i];
     if (!all_done(s)) return done(LSFFT_EDEVICE);
-    if (s->disp) {
-      hipError_t e = (s->prec == LSFFT_F32) ? strain_from_u<float>(s, Eb + 6 * off)
-                                            : strain_from_u<double>(s, Eb + 6 * off);
-      if (e != hipSuccess) return done(LSFFT_EDEVICE);
-    }
     s->last_iters = s->st_host[0].iters;
     off += s->B;
   }
@@ -838,8 +830,11 @@ lsfft_status solve_group(const std::vector<lsfft_solver> &hs, const double *Eb, 
 }
 
 // Outputs of every system: eps_out / sig_out hold [B][6][N] values (host
-// doubles or device T); either may be null.
-template <typename T> lsfft_status finish_outputs(lsfft_solver s, void *eps_out, void *sig_out, bool host) {
+// doubles or device T); either may be null.  In the displacement form the
+// strain is formed from u here, and only when an output needs it.  Eb: [B][6].
+template <typename T>
+lsfft_status finish_outputs(lsfft_solver s, void *eps_out, void *sig_out, bool host, const double *Eb) {
+  if (s->disp && (eps_out || sig_out)) LSFFT_CHECK(strain_from_u<T>(s, Eb));
   const size_t n6 = 6 * (size_t)s->d.N;
   const size_t bytes = n6 * (size_t)s->B * sizeof(T);
   if (eps_out) {
@@ -1496,8 +1491,8 @@ static lsfft_status solve_common(lsfft_solver s, const double *Ebar, double tol,
   lsfft_status rs = (s->prec == LSFFT_F32) ? run_solve<float>(s, Ebar, tol, maxit)
                                            : run_solve<double>(s, Ebar, tol, maxit);
   if (rs < 0) return rs;
-  lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, eps, sig, host)
-                                           : finish_outputs<double>(s, eps, sig, host);
+  lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, eps, sig, host, Ebar)
+                                           : finish_outputs<double>(s, eps, sig, host, Ebar);
   if (os != LSFFT_OK) return os;
   for (int b = 0; b < s->B; ++b) {
     const State &x = s->st_host[b];
@@ -1558,8 +1553,8 @@ lsfft_status lsfft_solve_group(const lsfft_solver *handles, int32_t count, const
   for (int i = 0; i < count; ++i) {
     lsfft_solver s = hs[i];
     void *e = eps_dev ? eps_dev[i] : nullptr;
-    lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, e, nullptr, false)
-                                             : finish_outputs<double>(s, e, nullptr, false);
+    lsfft_status os = (s->prec == LSFFT_F32) ? finish_outputs<float>(s, e, nullptr, false, Ebar + 6 * off)
+                                             : finish_outputs<double>(s, e, nullptr, false, Ebar + 6 * off);
     if (os != LSFFT_OK) return os;
     for (int b = 0; b < s->B; ++b, ++off) {
       const State &x = s->st_host[b];
