@@ -499,6 +499,26 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   if (a.counter) last_block_reduce<WG>(a.red, a.counter, sysb, red);
 }
 
+// Buffer resources over a field of `count` elements (raw: offsets in bytes,
+// bounds-checked against the field's size, which stays below 4 GiB for every
+// supported grid) and loads through them: the load adds a scalar byte offset
+// to the per-thread one, so a plane-invariant per-thread offset needs no
+// vector address arithmetic.
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const E *p, long long count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<E *>(p), 0, (int)(unsigned)(count * (long long)sizeof(E)),
+                                           0x00020000);
+}
+__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <typename T> __device__ __forceinline__ T load_t(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
 // Register-resident variant for n1 = 2^a or 3 * 2^a: every thread owns fixed
 // x columns (XV of them) of one y-group and keeps its own displacement
 // planes, edge differences and sigma planes in registers; LDS only carries
@@ -547,17 +567,15 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   constexpr int NUL = T2 + 2, NSL = T2 + 1;
   constexpr int UX = G * NUL * 3 * N1;           // the exchanged u plane (FP64)
   constexpr int NPEN = G * T2 * 3;
-  constexpr int UE = NPEN * N1;                  // the exchanged divergence parts (T)
-  constexpr int SCR = (NPEN + 1) * line_scratch<L>();  // transform scratch (complex T)
+  constexpr int NF = NPEN * N1;                  // the two divergence parts of a plane (T)
+  constexpr int SCR = NPEN * line_scratch<L>();  // transform scratch (complex T)
   static_assert(G * NX == WG, "the workgroup must split evenly into x columns");
   static_assert(NPEN * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
   static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
-  static_assert(UE <= 2 * SCR, "the divergence exchange must fit in the transform scratch");
   __shared__ double Ux[UX];
-  // the divergence exchange and, once f is in F, the transform scratch
+  __shared__ T Fv[NF];  // f_i's part from the own column, at x
+  __shared__ T Fu[NF];  // f_i's part that column x takes from column x-1, at x
   __shared__ cplx<T> Scr[SCR];
-  T *const Ue = reinterpret_cast<T *>(Scr);
-  __shared__ T F[G * T2 * 3 * N1];
   __shared__ cplx<T> twl[N1];   // the x twiddles, read by every transform below
   __shared__ double red[(WG / 64) * 8];
   const int tid = threadIdx.x;
@@ -591,33 +609,46 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   // load is in bounds; u of the first pass is zero-filled memory): a load
   // whose result had to be merged with an old register value would force a
   // wait right after it.  Groups past n2 compute on wrapped rows and store
-  // nothing.
+  // nothing.  The loads go through buffer resources: the byte offset of the
+  // plane and component is a scalar, the thread's column on a line a fixed
+  // 32-bit register (lo8 for FP64, lo4 for T), so the march spends no vector
+  // instructions on addresses.
+  static_assert((long long)NX * (XV - 1) * 8 < 4096, "column offsets must fit the load's immediate");
+  unsigned lo8[NUL], lo4[NSL];
+#pragma unroll
+  for (int l = 0; l < NUL; ++l) {
+    const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
+    lo8[l] = (unsigned)(yg * N1 + xt) * 8u;
+    if (l < NSL) lo4[l] = (unsigned)(yg * N1 + xt) * (unsigned)sizeof(T);
+  }
+  const unsigned plane = (unsigned)(n2 * N1);
+  const auto u_rs = buffer_of(a.u, 3 * N);
+  const auto lam_rs = buffer_of(a.lam, N), mu_rs = buffer_of(a.mu, N);
+  // the march reads planes z0-1 .. z0+Z+1 with z0+Z <= n3: one wrap at most
+  auto zwrap = [&](int zz) { return zz < 0 ? zz + n3 : (zz >= n3 ? zz - n3 : zz); };
   auto fetch_u = [&](double (&dst)[XV][NUL][3], int zz) {
-    const int zg = ((zz % n3) + n3) % n3;
+    const unsigned zg = (unsigned)zwrap(zz);
 #pragma unroll
-    for (int v = 0; v < XV; ++v)
+    for (int c = 0; c < 3; ++c) {
+      const unsigned so = (zg * plane + (unsigned)c * (unsigned)N) * 8u;
 #pragma unroll
-      for (int l = 0; l < NUL; ++l) {
-        const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
-        const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
+      for (int v = 0; v < XV; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dst[v][l][c] = a.u[c * N + gi];
-      }
+        for (int l = 0; l < NUL; ++l) dst[v][l][c] = load_f64(u_rs, lo8[l] + NX * 8 * v, so);
+    }
   };
   auto fetch_lm = [&](T (&dl)[XV][NSL], T (&dm)[XV][NSL], int zz) {
-    const int zg = ((zz % n3) + n3) % n3;
+    const unsigned so = (unsigned)zwrap(zz) * plane * (unsigned)sizeof(T);
 #pragma unroll
     for (int v = 0; v < XV; ++v)
 #pragma unroll
       for (int l = 0; l < NSL; ++l) {
-        const int yg = ((yg0 - 1 + l) % n2 + n2) % n2;
-        const long long gi = ((long long)zg * n2 + yg) * N1 + xt + NX * v;
-        dl[v][l] = a.lam[gi];
-        dm[v][l] = a.mu[gi];
+        dl[v][l] = load_t<T>(lam_rs, lo4[l] + NX * sizeof(T) * v, so);
+        dm[v][l] = load_t<T>(mu_rs, lo4[l] + NX * sizeof(T) * v, so);
       }
   };
   auto ux_at = [&](int l, int c, int x) -> double & { return Ux[((g * NUL + l) * 3 + c) * N1 + x]; };
-  auto ue_at = [&](int m, int i, int x) -> T & { return Ue[((g * T2 + m) * 3 + i) * N1 + x]; };
+  auto fpart = [&](int m, int i, int x) { return ((g * T2 + m) * 3 + i) * N1 + x; };
   // y differences of plane `src`, publish it, take its x differences
   auto take_plane = [&](const double (&src)[XV][NUL][3], T (&ddx)[XV][NUL][3], T (&ddy)[XV][NSL][3]) {
 #pragma unroll
@@ -657,9 +688,9 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         for (int c = 0; c < 3; ++c) dz[v][l][c] = (T)((u[Q][v][l][c] - u[P][v][l][c]) + hE[c][2]);
     fetch_u(u[P], z + 2);
     fetch_lm(lam[Q], mu[Q], z + 1);
-    // The previous step's last reads of Ux (its exchange) and of the sigma
-    // plane reused below (its transform scratch) precede a barrier of that
-    // step or the one inside this exchange.
+    // The previous step's last reads of Ux (its exchange) precede a barrier
+    // of that step, its transforms' reads of Fv, Fu the one inside this
+    // exchange.
     take_plane(u[Q], dx[Q], dy[Q]);
     // ---- sigma at the cells (x, lines 0..NSL-1, plane z) of this thread
 #pragma unroll
@@ -719,14 +750,15 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
     // ---- f = div sigma at the nodes (x, lines 0..T2-1, plane z).  Node line
     // m gathers cell lines m+1 and m, cell planes z (sg[P]) and z-1 (sg[Q]),
     // columns x and x-1.  Each difference operator is separable, so the part
-    // of f_i that the own column contributes and the part the column x+1
-    // takes from it are formed here (fv, and fu published to LDS), and
-    // f_i(x) = fv_i(x) - fu_i(x-1): three values per node cross the column
-    // boundary instead of the six stress components of two cell planes.
-    T fv[XV][T2][3];
+    // of f_i that the own column contributes (fv, to Fv at x) and the part
+    // the column x+1 takes from it (fu, to Fu at x+1) are formed here, and
+    // the transforms below read f_i(x) = fv_i(x) - fu_i(x-1): three values
+    // per node cross the column boundary instead of the six stress
+    // components of two cell planes.
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
       const int x = xt + NX * v;
+      const int x1 = (x + 1) % N1;
 #pragma unroll
       for (int m = 0; m < T2; ++m) {
         T xp[3], w[3];  // x-derivative part and (y, z)-derivative part of f_i
@@ -752,8 +784,8 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
           w[2] = q[1] * Y[3] + q[2] * Zd[2];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            fv[v][m][i] = q[0] * xp[i] + w[i];
-            ue_at(m, i, x) = q[0] * xp[i] - w[i];
+            Fv[fpart(m, i, x)] = q[0] * xp[i] + w[i];
+            Fu[fpart(m, i, x1)] = q[0] * xp[i] - w[i];
           }
         } else {
           // backward differences: cell (x, m+1, z) minus its neighbour in x, y, z
@@ -768,54 +800,41 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
           w[2] = ih[1] * (o[3] - ym[3]) + ih[2] * (o[2] - zm[2]);
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            fv[v][m][i] = ih[0] * xp[i] + w[i];
-            ue_at(m, i, x) = ih[0] * xp[i];
+            Fv[fpart(m, i, x)] = ih[0] * xp[i] + w[i];
+            Fu[fpart(m, i, x1)] = ih[0] * xp[i];
           }
         }
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int v = 0; v < XV; ++v) {
-      const int x = xt + NX * v;
-      const int xm = (x + N1 - 1) % N1;
-#pragma unroll
-      for (int m = 0; m < T2; ++m) {
-        T f[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) f[i] = fv[v][m][i] - ue_at(m, i, xm);
-        if (a.fstar) {  // eigenstrain: the force of the eigenstress, T = C [E - E_*]
-          const int yg = (yg0 + m) % n2;  // groups past n2 work on wrapped rows
-          const long long gi = ((long long)(z % n3) * n2 + yg) * N1 + x;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) f[i] -= a.fstar[i * N + gi];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) F[((g * T2 + m) * 3 + i) * N1 + x] = f[i];
-        if (gvalid) sums[6] += (double)(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-      }
-    }
-    __syncthreads();
-    // ---- forward x transforms of the G x T2 x 3 f lines (scratch over the
-    // exchange buffer, whose reads precede the barrier above)
-    {
+    // ---- f of the G x T2 x 3 lines and their forward x transforms, in whole
+    // wavefronts (the threads past the last line skip them: a line's
+    // exchanges are ordered within its wavefront)
+    if (tid < NPEN * TPC) {
       const int pid = tid / TPC, t = tid % TPC;
-      const bool act = pid < NPEN;
-      const int pg = act ? pid / (T2 * 3) : 0;
-      const int m = act ? (pid / 3) % T2 : 0, c = act ? pid % 3 : 0;
+      const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
+      const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;  // rows past n2 store nothing
+      const int lo = ((pg * T2 + m) * 3 + c) * N1;
       cplx<T> vv[E];
+      T ff = T(0);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int xx = 2 * (t + TPC * e);
-        const int o = ((pg * T2 + m) * 3 + c) * N1 + xx;
-        vv[e] = act ? cplx<T>{F[o], F[o + 1]} : cplx<T>{T(0), T(0)};
+        T f0 = Fv[lo + xx] - Fu[lo + xx], f1 = Fv[lo + xx + 1] - Fu[lo + xx + 1];
+        if (a.fstar) {  // eigenstrain: the force of the eigenstress, T = C [E - E_*]
+          const long long gi = ((long long)zwrap(z) * n2 + yrow % n2) * N1 + xx;
+          f0 -= a.fstar[c * N + gi];
+          f1 -= a.fstar[c * N + gi + 1];
+        }
+        ff += f0 * f0 + f1 * f1;
+        vv[e] = cplx<T>{f0, f1};
       }
-      cplx<T> *scr = Scr + (act ? pid : NPEN) * line_scratch<L>();
+      cplx<T> *scr = Scr + pid * line_scratch<L>();
       int buf = 0;
       const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, twl, buf);
-      const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;
-      if (act && yrow < n2) {
-        const long long row = (long long)(z % n3) * n2 + yrow;
+      if (yrow < n2) {
+        sums[6] += (double)ff;
+        const long long row = (long long)zwrap(z) * n2 + yrow;
         cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
         for (int e = 0; e < E; ++e) dst[t + TPC * e] = vv[e];

@@ -99,16 +99,16 @@ constexpr int stencil_groups(int n1) {
   return (stencil_reg_kernel(n1) && n1 < lsfft::stencil_wg_of(n1)) ? lsfft::stencil_wg_of(n1) / n1 : 1;
 }
 // LDS of the stencil kernels (n1 values per line): the register-resident one
-// holds one FP64 u plane (T2+2 lines x 3) per y-group, the transform scratch
-// ((3 T2 G + 1) complex lines, which also carries the divergence exchange),
-// the f lines (T2 x 3) and the x twiddles; the other one two u planes, two
-// sigma planes (T2+1 lines x 6) and the f lines.
+// holds one FP64 u plane (T2+2 lines x 3) per y-group, the two parts of the
+// divergence exchange (T2 x 3 lines each), the transform scratch (3 T2 G
+// complex lines) and the x twiddles; the other one two u planes, two sigma
+// planes (T2+1 lines x 6) and the f lines.
 template <typename T> constexpr long long stencil_lds(int n1) {
   const long long G = stencil_groups(n1);
   const long long t2 = st2_of<T>(n1);
   const long long ts = (long long)sizeof(T);
   if (stencil_reg_kernel(n1))
-    return G * n1 * ((t2 + 2) * 3 * 8 + t2 * 3 * ts) + (G * t2 * 3 + 1) * lsfft::line_scratch_of(n1 / 2) * 2 * ts +
+    return G * n1 * ((t2 + 2) * 3 * 8 + 2 * t2 * 3 * ts) + G * t2 * 3 * lsfft::line_scratch_of(n1 / 2) * 2 * ts +
            2LL * n1 * ts + 256;
   return G * n1 * (2 * (t2 + 2) * 3 * 8 + (2 * (t2 + 1) * 6 + t2 * 3) * ts) + 256;
 }
