@@ -41,7 +41,8 @@ def _golden(name):
         return json.load(f)
 
 
-C2 = ["c2_afb_10_sharp", "c2_fb_10_sharp", "c2_afb_10_smooth", "c2_fb_10_smooth", "c2_afb_1000_sharp"]
+C2 = ["c2_afb_10_sharp", "c2_fb_10_sharp", "c2_afb_10_smooth", "c2_fb_10_smooth", "c2_afb_1000_sharp",
+      "c2_fb_1000_sharp", "c2_afb_1000_smooth"]
 
 
 @pytest.mark.parametrize("name", C2)
