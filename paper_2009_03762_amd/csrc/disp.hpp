@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
       // idle threads (pid >= 6) share one dummy scratch area
       cplx<T> *scr = reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : 6) * line_scratch<L>();
       int buf = 0;
-      const cplx<T> xnq = r2c_line<T, L, E>(v, t, tid & 63, scr, a.tw, buf);
+      const cplx<T> xnq = r2c_line<T, L, E, false>(v, t, tid & 63, scr, a.tw, buf);  // twice the spectrum
       if (act) {
         const int zg = z % n3;
         const long long row = (long long)zg * n2 + (y0 + m);
@@ -592,6 +592,14 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   const T q[3] = {T(0.25) * a.ih[0], T(0.25) * a.ih[1], T(0.25) * a.ih[2]};
   const T ih[3] = {a.ih[0], a.ih[1], a.ih[2]};
   double sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  T acc0[6];  // the even step's stress sums of a loop pass
+  static_assert(XV == 1, "one x column per thread");
+  // Wave priorities (FP32, two workgroups per CU): a step's loads, exchange
+  // and FP64 differences first, then its stresses and divergence parts, its
+  // line transforms last, so that a workgroup's latency-bound transforms
+  // fill the other's issue gaps instead of competing with its arithmetic
+  // (the FP64 stencil, one wave per SIMD at 256 columns, measured no gain).
+  constexpr bool PRIO = sizeof(T) == 4;
 
   // Per-plane buffers indexed by plane parity.  u: own columns (FP64), plane
   // p in u[p & 1].  Edge differences of the TOTAL displacement u + Ebar x,
@@ -692,6 +700,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
     // of that step, its transforms' reads of Fv, Fu the one inside this
     // exchange.
     take_plane(u[Q], dx[Q], dy[Q]);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
     // ---- sigma at the cells (x, lines 0..NSL-1, plane z) of this thread
 #pragma unroll
     for (int v = 0; v < XV; ++v) {
@@ -737,10 +746,16 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
           if (l >= 1) acc[c] += s6[c];
         }
       }
-      // mean stress: the T2 owned cell lines, summed in T per step, then in FP64
-      if (gvalid && !FIRST) {
+      // mean stress: the T2 owned cell lines, summed in T over the two steps
+      // of a loop pass, then in FP64
+      if constexpr (!FIRST) {
+        if constexpr (P == 0) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sums[c] += (double)acc[c];
+          for (int c = 0; c < 6; ++c) acc0[c] = acc[c];
+        } else if (gvalid) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) sums[c] += (double)(acc0[c] + acc[c]);
+        }
       }
     }
     if constexpr (FIRST) {
@@ -810,6 +825,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
     // ---- f of the G x T2 x 3 lines and their forward x transforms, in whole
     // wavefronts (the threads past the last line skip them: a line's
     // exchanges are ordered within its wavefront)
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     if (tid < NPEN * TPC) {
       const int pid = tid / TPC, t = tid % TPC;
       const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
@@ -831,7 +847,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
       }
       cplx<T> *scr = Scr + pid * line_scratch<L>();
       int buf = 0;
-      const cplx<T> xnq = r2c_line<T, L, E>(vv, t, tid & 63, scr, twl, buf);
+      const cplx<T> xnq = r2c_line<T, L, E, false>(vv, t, tid & 63, scr, twl, buf);  // twice the spectrum
       if (yrow < n2) {
         sums[6] += (double)ff;
         const long long row = (long long)zwrap(z) * n2 + yrow;
@@ -841,6 +857,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xnq;
       }
     }
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
   };
 
   // prologue: plane z0-1 (odd parity, since Z and hence z0 are even) and its

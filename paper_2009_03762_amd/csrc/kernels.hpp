@@ -153,8 +153,10 @@ __device__ __forceinline__ void c2r_line(cplx<T> (&v)[E], cplx<T> xn, int t, int
 
 // Forward real transform of one x-line.  In: v[e] = (x[2m], x[2m+1]).
 // Out: v[e] = X[k] for k = t + TPC e in [0, L), and the return value X[L]
-// (in thread t = 0).
-template <typename T, int L, int E>
+// (in thread t = 0); with HALF false, 2 X[k] and 2 X[L] (four fewer
+// multiplications per point, for callers that fold the factor into a later
+// scale).
+template <typename T, int L, int E, bool HALF = true>
 __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cplx<T> *lds,
                                             const cplx<T> *__restrict__ tw, int &buf) {
   constexpr int TPC = L / E;
@@ -162,18 +164,19 @@ __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cp
   cplx<T> pv[E];
   partner<T, E, TPC>(v, pv, t, lane);
   cplx<T> xn{T(0), T(0)};
+  constexpr T two = HALF ? T(1) : T(2);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int k = t + TPC * e;
     const cplx<T> z = v[e];
     if (k == 0) {
-      v[e] = cplx<T>{z.x + z.y, T(0)};
-      xn = cplx<T>{z.x - z.y, T(0)};
+      v[e] = cplx<T>{two * (z.x + z.y), T(0)};
+      xn = cplx<T>{two * (z.x - z.y), T(0)};
     } else {
       const cplx<T> zp = conjg(pv[e]);
-      const cplx<T> fe = T(0.5) * (z + zp);
-      const cplx<T> d = T(0.5) * (z - zp);
-      const cplx<T> fo = cplx<T>{d.y, -d.x};  // (z - zp) / (2i)
+      const cplx<T> fe = HALF ? T(0.5) * (z + zp) : z + zp;
+      const cplx<T> d = HALF ? T(0.5) * (z - zp) : z - zp;
+      const cplx<T> fo = cplx<T>{d.y, -d.x};  // (z - zp) / (2i), times 2 unless HALF
       v[e] = fe + tw[k] * fo;
     }
   }

@@ -390,7 +390,10 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
   const lsfft::YArgs<T> ya = yargs<T>(s, true, ncomp);
   const int nyg = ygrid<T>(s, ncomp);
   lsfft::ZArgs<T> za = zargs<T>(s, true, 0);
-  if (disp) za.main_blocks = s->zu_main_blocks;
+  if (disp) {
+    za.main_blocks = s->zu_main_blocks;
+    za.g.scale = (T)(0.5 / (double)s->d.N);  // the stencils' real x transforms return twice the spectrum
+  }
   const lsfft::XArgs<T> xa = xargs<T>(s, dgo ? lsfft::XMODE_DGO : lsfft::XMODE_UPDATE, nullptr, true);
   const lsfft::SArgs<T> sa = with_reduce(sargs<T>(s, 0));
   const lsfft::UArgs<T> ua = uargs<T>(s);
