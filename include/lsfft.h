@@ -173,10 +173,11 @@ typedef struct {
                               final status comes from an FP64 evaluation.
                               Measured (AFB, 256^3, contrast 1e3, tol 1e-6):
                               f64_until = 3e-4 with refine = 8 stops at r <=
-                              tol in the FP64 iteration count, about 10 %
-                              faster than F64; a switch at a residual much
-                              above 300 x tol leaves FP32 rounding in the
-                              slowest modes and costs many more iterations. */
+                              tol in the FP64 iteration count, about 12 %
+                              faster than F64 (tol 1e-8, f64_until 3e-6: 8 %);
+                              a switch at a residual much above 300 x tol
+                              leaves FP32 rounding in the slowest modes and
+                              costs many more iterations at tight tol.       */
 } lsfft_config;
 
 /* Create a solver (Sec. 5.2 "given: n, C(x), Ebar, C_H, G").  Copies lambda

@@ -198,6 +198,8 @@ template <typename T> struct SArgs {
   int Z;               // planes per workgroup
   int xcd;             // 1: XCD-aware order of the tiles
   int zero_u;          // u is identically zero (first pass): the LDS variant skips its loads
+  float *raw;          // FP64 register stencil only: store -f here [system][3][N] instead of transforming
+                       // (the FP64 residual force of a refinement cycle), or null
 };
 
 // Offset the per-system pointers of stencil arguments to system b.
@@ -209,6 +211,7 @@ template <typename T> __device__ __forceinline__ void stencil_member(SArgs<T> &a
   a.nyq += b * a.bs.nyq;
   if (a.partial) a.partial += b * a.bs.part;
   if (a.fstar) a.fstar += b * 3 * a.bs.field;
+  if (a.raw) a.raw += b * 3 * a.bs.field;
 }
 
 template <int SCHEME> struct Stencil;
@@ -546,7 +549,11 @@ constexpr int stencil_wg_of(int n1) {
 template <typename T, int N1> constexpr int stencil_min_waves() {
   return (sizeof(T) == 4 && !pow2_len(N1) && N1 <= 192) ? 2 : LSFFT_STENCIL_WAVES;
 }
-template <typename T, int N1, int E, int SCHEME, int T2>
+//
+// FS: the system subtracts a force at the nodes (a.fstar: the eigenstress's,
+// or a refinement cycle's FP64 residual); a separate instantiation, since
+// its prefetch registers would otherwise size the plain kernel.
+template <typename T, int N1, int E, int SCHEME, int T2, bool FS>
 __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) void k_stencil_reg(SArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
@@ -583,7 +590,8 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   const long long N = a.d.N;
   const int ny_blocks = (n2 + G * T2 - 1) / (G * T2);
   const int tile = stencil_tile(a.xcd);
-  for (int i = tid; i < N1; i += WG) twl[i] = a.tw[i];
+  if (a.tw)
+    for (int i = tid; i < N1; i += WG) twl[i] = a.tw[i];
   const int g = tid / NX, xt = tid % NX;
   const int yg0 = (tile % ny_blocks) * G * T2 + g * T2;
   const bool gvalid = yg0 < n2;
@@ -696,6 +704,20 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         for (int c = 0; c < 3; ++c) dz[v][l][c] = (T)((u[Q][v][l][c] - u[P][v][l][c]) + hE[c][2]);
     fetch_u(u[P], z + 2);
     fetch_lm(lam[Q], mu[Q], z + 1);
+    // the force this plane's transforms subtract (eigenstress, or the FP64
+    // residual of a refinement cycle), fetched now so that its latency
+    // overlaps the step instead of stalling the transforms
+    T fsv[E][2];
+    if constexpr (FS && !FIRST) {
+      if (tid < NPEN * TPC) {
+        const int pid = tid / TPC, t = tid % TPC;
+        const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
+        const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;  // groups past n2 work on wrapped rows
+        const T *fs = a.fstar + c * N + ((long long)zwrap(z) * n2 + yrow % n2) * N1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) ld2(fs + 2 * (t + TPC * e), fsv[e][0], fsv[e][1]);
+      }
+    }
     // The previous step's last reads of Ux (its exchange) precede a barrier
     // of that step, its transforms' reads of Fv, Fu the one inside this
     // exchange.
@@ -837,13 +859,23 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
       for (int e = 0; e < E; ++e) {
         const int xx = 2 * (t + TPC * e);
         T f0 = Fv[lo + xx] - Fu[lo + xx], f1 = Fv[lo + xx + 1] - Fu[lo + xx + 1];
-        if (a.fstar) {  // eigenstrain: the force of the eigenstress, T = C [E - E_*]
-          const long long gi = ((long long)zwrap(z) * n2 + yrow % n2) * N1 + xx;
-          f0 -= a.fstar[c * N + gi];
-          f1 -= a.fstar[c * N + gi + 1];
+        if constexpr (FS) {
+          f0 -= fsv[e][0];
+          f1 -= fsv[e][1];
         }
         ff += f0 * f0 + f1 * f1;
         vv[e] = cplx<T>{f0, f1};
+      }
+      if constexpr (sizeof(T) == 8) {
+        if (a.raw) {  // a refinement cycle's FP64 evaluation: -f in real space, rounded to FP32
+          if (yrow < n2) {
+            float *dst = a.raw + c * N + ((long long)zwrap(z) * n2 + yrow) * N1;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+              *reinterpret_cast<float2 *>(dst + 2 * (t + TPC * e)) = float2{(float)-vv[e].x, (float)-vv[e].y};
+          }
+          return;
+        }
       }
       cplx<T> *scr = Scr + pid * line_scratch<L>();
       int buf = 0;

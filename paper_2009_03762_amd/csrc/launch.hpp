@@ -88,10 +88,12 @@ hipError_t Launch<T>::stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int gr
 #define SCASE(Lv)                                                                                      \
 case 2 * Lv:                                                                                         \
   if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
-    hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv)>),                      \
-                       dim3(grid, s->launch_b),                                                                 \
-                       dim3(lsfft::stencil_wg_of(2 * Lv)),                                                      \
-                       0, s->stream, a);                                                                        \
+    if (a.fstar)                                                                                     \
+      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), true>),               \
+                         dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), 0, s->stream, a);           \
+    else                                                                                             \
+      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), false>),              \
+                         dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), 0, s->stream, a);           \
     return hipGetLastError();                                                                        \
   } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
     hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, st2_of<T>(2 * Lv)>), dim3(grid, s->launch_b), \

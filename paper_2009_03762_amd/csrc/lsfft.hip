@@ -175,6 +175,7 @@ template <typename T> lsfft::ZArgs<T> zargs(lsfft_solver s, bool flag, int forwa
 
 template <typename T> lsfft::SArgs<T> sargs(lsfft_solver s, int zero_u) {
   lsfft::SArgs<T> a;
+  a.raw = nullptr;
   a.d = s->d;
   // refinement: the sweeps iterate on the correction with Ebar = 0 and the
   // FP64 residual force of the folded displacement as their load
@@ -260,6 +261,20 @@ template <typename T> lsfft_status upload_members(lsfft_solver s, const double *
   }
   LSFFT_CHECK(hipMemcpyAsync(s->mem, m.data(), sizeof(lsfft::Member<T>) * s->B, hipMemcpyHostToDevice, s->stream));
   LSFFT_CHECK(hipMemcpyAsync(s->enorm, en.data(), sizeof(double) * s->B, hipMemcpyHostToDevice, s->stream));
+  std::vector<lsfft::Member<double>> m64(s->mem64 ? s->B : 0);
+  for (size_t b = 0; b < m64.size(); ++b) {
+    for (int c = 0; c < 6; ++c) m64[b].Eb[c] = m[b].Eb[c];
+    for (int i = 0; i < 3; ++i)
+      for (int r = 0; r < 3; ++r) m64[b].hE[i][r] = m[b].hE[i][r];
+    m64[b].lam0 = s->lam0v[b];
+    m64[b].mu0 = s->mu0v[b];
+    m64[b].c1 = 1.0 / s->mu0v[b];
+    m64[b].c2 = (s->lam0v[b] + s->mu0v[b]) / (s->mu0v[b] * (s->lam0v[b] + 2.0 * s->mu0v[b]));
+    m64[b].beta = (s->lam0v[b] + s->mu0v[b]) / (s->lam0v[b] + 2.0 * s->mu0v[b]);
+  }
+  if (s->mem64)
+    LSFFT_CHECK(hipMemcpyAsync(s->mem64, m64.data(), sizeof(lsfft::Member<double>) * s->B, hipMemcpyHostToDevice,
+                               s->stream));
   if (s->mem_ref) {
     for (auto &x : m) {
       for (int c = 0; c < 6; ++c) x.Eb[c] = 0.0;
@@ -506,12 +521,48 @@ void drop_graph(lsfft_solver s) {
 
 // Start of a refinement cycle (systems not done): fold delta into u, then
 // the FP64 cell stress of u, its mean and its divergence at the nodes.
+int stencil_yblocks(const lsfft_solver s, bool f64);
+
 template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
   const long long n3 = 3 * s->d.N;
   const unsigned fb = (unsigned)std::min<long long>((n3 + 255) / 256, 4096);
   hipLaunchKernelGGL(lsfft::k_refine_fold, dim3(fb, s->B), dim3(256), 0, s->stream, (double *)s->u, s->du, s->st,
                      n3);
   LSFFT_CHECK(hipGetLastError());
+  if (s->mem64) {
+    // the FP64 register stencil on the folded u: its divergence f (minus the
+    // eigenstress force), stored as -F_b, and its stress block sums
+    lsfft::SArgs<double> a;
+    a.d = s->d;
+    a.u = (const double *)s->u;
+    a.lam = s->lam64;
+    a.mu = s->mu64;
+    a.spec = nullptr;
+    a.nyq = nullptr;
+    a.tw = nullptr;
+    a.mem = (const lsfft::Member<double> *)s->mem64;
+    a.bs = s->bs;
+    a.bs.part = s->spx;
+    for (int r = 0; r < 3; ++r) {
+      a.ihu[r] = 1.0 / s->h[r];
+      a.ih[r] = 1.0 / s->h[r];
+    }
+    a.partial = s->px;
+    a.st = s->st;
+    a.fstar = s->fstar64;
+    a.red = lsfft::ReduceArgs{};
+    a.counter = nullptr;
+    a.Z = s->sZ;
+    a.xcd = s->xcd & 1;
+    a.zero_u = 0;
+    a.raw = (float *)s->fref;
+    const int nsb64 = stencil_yblocks(s, true) * (s->n[2] / s->sZ);  // its own node lines per workgroup
+    LSFFT_CHECK(Launch<double>::stencil(s, a, nsb64));
+    hipLaunchKernelGGL(lsfft::k_refine_mean, dim3(s->B), dim3(64), 0, s->stream, s->px, nsb64, s->spx, s->sref,
+                       s->eig ? s->smean : nullptr, s->st, (double)s->d.N);
+    LSFFT_CHECK(hipGetLastError());
+    return LSFFT_OK;
+  }
   lsfft::RefineArgs<T> a;
   a.d = s->d;
   a.u = (const double *)s->u;
@@ -535,8 +586,8 @@ template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
     hipLaunchKernelGGL((lsfft::k_refine_div<T, lsfft::SCHEME_AFB>), grid, dim3(256), 0, s->stream, a);
   }
   LSFFT_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(lsfft::k_refine_mean, dim3(s->B), dim3(64), 0, s->stream, s->rpart, s->nrb, s->sref, s->st,
-                     (double)s->d.N);
+  hipLaunchKernelGGL(lsfft::k_refine_mean, dim3(s->B), dim3(64), 0, s->stream, s->rpart, s->nrb,
+                     (long long)s->nrb * 8, s->sref, nullptr, s->st, (double)s->d.N);
   LSFFT_CHECK(hipGetLastError());
   return LSFFT_OK;
 }
@@ -901,10 +952,10 @@ template <typename T> lsfft_status upload_moduli(lsfft_solver s, const lsfft_con
 
 // y-blocks of a stencil plane: the register stencil packs several
 // independent y-groups per workgroup when n1 is shorter than the workgroup.
-int stencil_yblocks(const lsfft_solver s) {
+int stencil_yblocks(const lsfft_solver s, bool f64 = false) {
   const int n1 = s->n[0];
   const int G = stencil_groups(n1);
-  const int t2 = (s->prec == LSFFT_F32) ? st2_of<float>(n1) : st2_of<double>(n1);
+  const int t2 = (s->prec == LSFFT_F32 && !f64) ? st2_of<float>(n1) : st2_of<double>(n1);
   return (s->n[1] + G * t2 - 1) / (G * t2);
 }
 
@@ -934,7 +985,9 @@ template <typename T> lsfft_status set_grids(lsfft_solver s) {
 // workgroups (8 values each; two planes per stencil workgroup at least) and
 // z-pass workgroups (one value each).
 template <typename T> void partial_slots(const lsfft_solver s, long long &spx, long long &spz) {
-  const long long nsb_max = s->disp ? (long long)stencil_yblocks(s) * (s->n[2] / 2) : 0;
+  // (a refinement's FP64 evaluation runs the FP64 stencil on these block sums)
+  const long long nsb_max =
+      s->disp ? (long long)std::max(stencil_yblocks(s), s->refine ? stencil_yblocks(s, true) : 0) * (s->n[2] / 2) : 0;
   spx = 8LL * std::max<long long>(s->nxb, nsb_max);
   spz = 1;
   for (int v = 0; v < 2; ++v) {
@@ -996,7 +1049,7 @@ void release(lsfft_solver s) {
   void *ptrs[] = {s->eps,  s->lam,      s->mu,      s->spec, s->nyq, s->tab,    s->twx, s->twy, s->twz, s->u,
                   s->dgo_main, s->dgo_nyq, s->px, s->pz,   s->pg,  s->pstage, s->st,  s->hist, s->mem, s->enorm,
                   s->sstar, s->fstar, s->smean, s->counter, s->du, s->sref, s->lam64, s->mu64, s->sstar64,
-                  s->rpart, s->fref, s->mem_ref, s->rsig};
+                  s->rpart, s->fref, s->mem_ref, s->rsig, s->fstar64, s->mem64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->st_host) (void)hipHostFree(s->st_host);
@@ -1053,6 +1106,7 @@ template <typename T> lsfft_status setup_eigenstrain(lsfft_solver s, const lsfft
   LSFFT_CHECK(hipMalloc(&s->smean, B * 6 * sizeof(double)));
   if (s->disp) LSFFT_CHECK(hipMalloc(&s->fstar, B * 3 * (size_t)N * sizeof(T)));
   if (s->refine) LSFFT_CHECK(hipMalloc(&s->sstar64, B * 6 * (size_t)N * sizeof(double)));
+  if (s->refine && s->mem64) LSFFT_CHECK(hipMalloc(&s->fstar64, B * 3 * (size_t)N * sizeof(double)));
   std::vector<double> sd(6 * (size_t)N), fd(s->disp ? 3 * (size_t)N : 0), mean(6 * B, 0.0);
   std::vector<T> tmp(6 * (size_t)N);
   s->estar_rms.assign(B, 0.0);
@@ -1121,6 +1175,8 @@ template <typename T> lsfft_status setup_eigenstrain(lsfft_solver s, const lsfft
     }
     for (size_t i = 0; i < fd.size(); ++i) tmp[i] = (T)fd[i];
     LSFFT_CHECK(hipMemcpy((T *)s->fstar + m * 3 * N, tmp.data(), 3 * N * sizeof(T), hipMemcpyHostToDevice));
+    if (s->fstar64)
+      LSFFT_CHECK(hipMemcpy(s->fstar64 + m * 3 * N, fd.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice));
   }
   LSFFT_CHECK(hipMemcpy(s->smean, mean.data(), mean.size() * sizeof(double), hipMemcpyHostToDevice));
   return LSFFT_OK;
@@ -1410,13 +1466,21 @@ lsfft_status lsfft_create_batch(const lsfft_config *cfgs, int32_t count, lsfft_s
     s->refine = cfg->refine;
     const size_t n3 = B * 3 * (size_t)N;
     s->nrb = (int)std::min<long long>((N + 255) / 256, 2048);
+    // the FP64 residual evaluation: the FP64 register stencil where it runs
+    // at this n1, else the cell-stress and divergence kernels
+    const bool reg64 = stencil_reg_kernel(s->n[0]) && stencil_fits<double>(s->n[0]);
     if (hipMalloc(&s->du, n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
-    if (hipMalloc(&s->rsig, 2 * n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (reg64) {
+      if (hipMalloc(&s->mem64, B * sizeof(lsfft::Member<double>)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    } else if (hipMalloc(&s->rsig, 2 * n3 * sizeof(double)) != hipSuccess) {
+      return fail(LSFFT_ENOMEM);
+    }
     if (hipMalloc(&s->fref, n3 * sizeof(float)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->sref, B * 6 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->lam64, B * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->mu64, B * (size_t)N * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
-    if (hipMalloc(&s->rpart, B * (size_t)s->nrb * 8 * sizeof(double)) != hipSuccess) return fail(LSFFT_ENOMEM);
+    if (!reg64 && hipMalloc(&s->rpart, B * (size_t)s->nrb * 8 * sizeof(double)) != hipSuccess)
+      return fail(LSFFT_ENOMEM);
     if (hipMalloc(&s->mem_ref, B * sizeof(lsfft::Member<float>)) != hipSuccess) return fail(LSFFT_ENOMEM);
     // defined contents for the schedule tuner, which times the sweeps alone
     if (hipMemset(s->du, 0, n3 * sizeof(double)) != hipSuccess) return fail(LSFFT_EDEVICE);

@@ -53,19 +53,21 @@ __global__ __launch_bounds__(256) void k_refine_fold(double *u, double *du, cons
 }
 
 // smean of the refined sweeps: minus the mean of sigma_b (the stopping test
-// subtracts smean from the mean stress of delta).  Fixed summation order.
-__global__ __launch_bounds__(64) void k_refine_mean(const double *part, int rows, double *smean, const State *st,
-                                                    double N) {
+// subtracts smean from the mean stress of delta), from `rows` rows of 8 block
+// sums per system (`stride` doubles apart) and, when the block sums leave the
+// eigenstress out, its mean emean.  Fixed summation order.
+__global__ __launch_bounds__(64) void k_refine_mean(const double *part, int rows, long long stride, double *smean,
+                                                    const double *emean, const State *st, double N) {
   const int sysb = blockIdx.x;
   if (st[sysb].done) return;
-  part += (long long)sysb * rows * 8;
+  part += (long long)sysb * stride;
   __shared__ double red[8];
   double vals[6] = {0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < rows; i += 64)
     for (int c = 0; c < 6; ++c) vals[c] += part[i * 8 + c];
   block_sum<64>(vals, 6, red);
   if (threadIdx.x == 0)
-    for (int c = 0; c < 6; ++c) smean[6 * sysb + c] = -vals[c] / N;
+    for (int c = 0; c < 6; ++c) smean[6 * sysb + c] = -(vals[c] / N - (emean ? emean[6 * sysb + c] : 0.0));
 }
 
 __global__ void k_state_init(State *st, int count) {

@@ -200,10 +200,13 @@ struct lsfft_solver_s {
   // sstar64 with an eigenstrain) the FP64 data of the residual evaluation,
   // rsig its cell stress [B][6][N]; mem_ref the per-system constants with
   // Ebar = 0; rpart the block sums of k_refine_stress (nrb rows per system).
+  // Where the FP64 register stencil runs the evaluation instead (mem64 set:
+  // Member<double>[B] of the loading, fstar64 the FP64 eigenstress force),
+  // rsig and rpart are not allocated.
   int refine = 0;
   double *du = nullptr, *sref = nullptr, *lam64 = nullptr, *mu64 = nullptr, *sstar64 = nullptr, *rpart = nullptr;
-  double *rsig = nullptr;
-  void *fref = nullptr, *mem_ref = nullptr;
+  double *rsig = nullptr, *fstar64 = nullptr;
+  void *fref = nullptr, *mem_ref = nullptr, *mem64 = nullptr;
   int nrb = 0;
 };
 
