@@ -123,6 +123,50 @@ def test_fixed_iterations_every_cycle_length(L, cycle, scheme):
         assert abs(hist[-1] - h_ref[-1]) <= 1e-3 * h_ref[-1]
 
 
+@pytest.mark.parametrize("shape,scheme,eig", [((4, 8, 8), "afb", False), ((6, 12, 8), "fb", False),
+                                              ((6, 8, 12), "afb", True)])
+def test_cell_kernel_evaluation(L, shape, scheme, eig):
+    """x-lines of 4 and 6 points, where the FP64 register stencil does not run
+    and each cycle's FP64 residual comes from the cell-stress and divergence
+    kernels instead: converged refined solves against the oracle."""
+    print(f"\n[refine cell kernels] {shape} {scheme} eig={eig}", flush=True)
+    side = tuple(n // 2 if (n - n // 2) % 2 == 0 else n // 2 - 1 for n in shape)  # centred cubes
+    lam, mu, l0, m0 = _inclusion(shape, side, 10.0)
+    es = 1e-3 * np.random.default_rng(5).standard_normal((6,) + lam.shape) if eig else None
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec="f32", form="displacement", refine=8, eigenstrain=es)
+    assert s.describe().split()[0].startswith("k_stencil<float")
+    out = s.solve(EB, tol=1e-10, maxit=2000)
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=scheme.upper(), tol=1e-10, maxit=2000, eigenstrain=es)
+    assert out["status"] == L.OK and abs(out["iters"] - ref.iters) <= 1
+    assert rel(out["eps"], ref.eps) < 1e-6
+    assert rel(out["sig_mean"], ref.sig_mean) < 1e-6
+
+
+def test_fp32_floor_status(L):
+    """The F32 displacement form's residual floor (about (n/2)^2 x 2^-24, 6e-5
+    at 64^3, contrast 1e3): a tolerance below it ends ENOTCONV after maxit
+    with the fields at FP64 accuracy, one above it stops OK, and f64_until
+    with refinement certifies the tolerance below it."""
+    print("\n[floor status]", flush=True)
+    lam, mu, l0, m0 = _inclusion((64, 64, 64), (32, 32, 32), 1e3)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", f64_warmup=5)
+    lo = s.solve(EB, tol=1e-7, maxit=400)
+    hi = s.solve(EB, tol=1e-3, maxit=400)
+    s.close()
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f64")
+    ref = s.solve(EB, tol=1e-10, maxit=3000)
+    s.close()
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", f64_until=3e-5, refine=8)
+    cert = s.solve(EB, tol=1e-7, maxit=3000)
+    s.close()
+    assert lo["status"] == L.ENOTCONV and lo["iters"] == 400 and lo["residual"] > 1e-7
+    assert rel(lo["eps"], ref["eps"]) < 1e-5
+    assert hi["status"] == L.OK and hi["residual"] <= 1e-3
+    assert cert["status"] == L.OK and cert["residual"] <= 1e-7
+    assert rel(cert["eps"], ref["eps"]) < 1e-5
+
+
 def test_anisotropic_spacing(L):
     print("\n[refine spacing]", flush=True)
     h = (0.5, 1.0, 2.0)
