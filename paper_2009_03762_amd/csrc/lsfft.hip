@@ -470,12 +470,36 @@ lsfft_status run_phase(lsfft_solver s, double tol, int maxit, int k_begin, int k
     LSFFT_CHECK(hipEventRecord(s->gevent, s->stream));
     LSFFT_CHECK(hipStreamWaitEvent(s->gstream, s->gevent, 0));
     int per_sync = (tol == 0.0 || s->tuning) ? (k_end - k + GRAPH_CHUNK - 1) / GRAPH_CHUNK : 1;
+    // residual and tested iterate of every system at the previous read
+    std::vector<double> r_prev(s->B, -1.0);
+    std::vector<int> k_prev(s->B, 0);
     for (;;) {
       for (int j = 0; j < per_sync && k < k_end; ++j, k += GRAPH_CHUNK) LSFFT_CHECK(hipGraphLaunch(s->gexec, s->gstream));
       lsfft_status rs = read_state(s->gstream);
       if (rs != LSFFT_OK) return rs;
       if (all_done(s) || k >= k_end) break;
+      // Chunks between reads: doubling up to 8, but no more than the slowest
+      // running system still needs at its contraction since the last read
+      // (chunks enqueued past a stop return at once, yet each costs its
+      // launches).
+      int need = 0;
+      bool known = true;
+      for (int b = 0; b < s->B; ++b) {
+        const State &x = s->st_host[b];
+        if (x.done) continue;
+        const int dk = x.k - k_prev[b];
+        const double rho = (r_prev[b] > 0.0 && x.r > 0.0 && dk > 0) ? std::pow(x.r / r_prev[b], 1.0 / dk) : 1.0;
+        if (!(rho < 1.0) || !(tol > 0.0)) {
+          known = false;
+        } else {
+          const double left = std::log(tol / x.r) / std::log(rho);
+          need = std::max(need, (int)std::ceil(std::max(left, 1.0) / GRAPH_CHUNK));
+        }
+        r_prev[b] = x.r;
+        k_prev[b] = x.k;
+      }
       per_sync = std::min(per_sync * 2, 8);
+      if (known && need > 0) per_sync = std::min(per_sync, need);
     }
     return LSFFT_OK;
   }
