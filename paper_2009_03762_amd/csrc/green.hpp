@@ -278,6 +278,25 @@ __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, i
   return green_real(g, k, s);
 }
 
+// A scheme fixed at compile time (SCH >= 0: only AFB is specialised) or
+// taken from g (SCH < 0): the table values and the Green step of that scheme.
+template <int SCH, typename T> __device__ __forceinline__ AxisVal<T> axis_val_s(const GreenParams<T> &g, int axis, int i) {
+  if constexpr (SCH == SCHEME_AFB)
+    return AxisVal<T>{tabv(g, TAB_SH, axis, i), tabv(g, TAB_C, axis, i)};
+  else
+    return axis_val(g, axis, i);
+}
+template <int SCH, typename T>
+__device__ __forceinline__ double green_point_s(const GreenParams<T> &g, int i1, int i2, int i3,
+                                                const AxisVal<T> (&ax)[3], cplx<T> (&s)[6]) {
+  if constexpr (SCH == SCHEME_AFB) {
+    const T k[3] = {ax[0].p * ax[1].q * ax[2].q, ax[1].p * ax[2].q * ax[0].q, ax[2].p * ax[0].q * ax[1].q};
+    return green_real(g, k, s);
+  } else {
+    return green_point(g, i1, i2, i3, ax, s);
+  }
+}
+
 // The same, loading the table values itself.
 template <typename T>
 __device__ __forceinline__ double green_point(const GreenParams<T> &g, int i1, int i2, int i3, cplx<T> (&s)[6]) {

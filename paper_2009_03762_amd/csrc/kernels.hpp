@@ -476,8 +476,16 @@ template <typename T> __device__ __forceinline__ void member_green(GreenParams<T
   g.beta = m.beta;
 }
 
-template <typename T, int NZ, int E, int P>
-__global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
+// SCH: the scheme, fixed at compile time for AFB (its Green step and tables
+// only, sizing the kernel for that path), or -1: any scheme, from a.g.
+#ifndef LSFFT_Z_WAVES
+#define LSFFT_Z_WAVES 3
+#endif
+template <typename T, int SCH> constexpr int z_min_waves() {
+  return (sizeof(T) == 4 && SCH == SCHEME_AFB) ? LSFFT_Z_WAVES : 1;
+}
+template <typename T, int NZ, int E, int P, int SCH>
+__global__ __launch_bounds__(P *(NZ / E), (z_min_waves<T, SCH>())) void k_zpass(ZArgs<T> a) {
   const int sysb = blockIdx.y;
   if (a.st && a.st[sysb].done) return;
   a.spec += sysb * a.bs.spec;
@@ -520,14 +528,14 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
       v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
-  const AxisVal<T> axx = axis_val(a.g, 0, i1), axy = axis_val(a.g, 1, valid ? i2 : 0);
+  const AxisVal<T> axx = axis_val_s<SCH>(a.g, 0, i1), axy = axis_val_s<SCH>(a.g, 1, valid ? i2 : 0);
 #if LSFFT_LDS_AXIS
   __shared__ AxisVal<T> axl[NZ];
-  stage_axis(axl, a.g, 2);
+  for (int i = threadIdx.x; i < NZ; i += blockDim.x) axl[i] = axis_val_s<SCH>(a.g, 2, i);
 #else
   AxisVal<T> axz[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) axz[e] = axis_val(a.g, 2, t + TPC * e);
+  for (int e = 0; e < E; ++e) axz[e] = axis_val_s<SCH>(a.g, 2, t + TPC * e);
 #endif
   int buf = 0;
   const cplx<T> *twl = stage_twiddles(twl_, a.tw);  // its barrier publishes axl too
@@ -554,7 +562,7 @@ __global__ __launch_bounds__(P *(NZ / E)) void k_zpass(ZArgs<T> a) {
 #else
     const AxisVal<T> ax[3] = {axx, axy, axz[e]};
 #endif
-    const double r = green_point(a.g, i1, valid ? i2 : 0, t + TPC * e, ax, s);
+    const double r = green_point_s<SCH>(a.g, i1, valid ? i2 : 0, t + TPC * e, ax, s);
     if (valid) res += wgt * r;
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][e] = s[c];

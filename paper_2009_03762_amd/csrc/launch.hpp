@@ -53,11 +53,17 @@ hipError_t Launch<T>::zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) 
 #define ZCASE(Nv)                                                                                      \
 case Nv: {                                                                                           \
   constexpr int E = ez_of(Nv), P0 = pcols_z<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                      \
-  if (s->zv)                                                                                         \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, s->stream, \
+  if (s->scheme == LSFFT_AFB && s->zv)                                                               \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),           \
+                       dim3(P1 * (Nv / E)), 0, s->stream, a);                                        \
+  else if (s->scheme == LSFFT_AFB)                                                                   \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),           \
+                       dim3(P0 * (Nv / E)), 0, s->stream, a);                                        \
+  else if (s->zv)                                                                                    \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1, -1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, s->stream, \
                        a);                                                                           \
   else                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, s->stream, \
+    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0, -1>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, s->stream, \
                        a);                                                                           \
   return hipGetLastError();                                                                          \
 }
