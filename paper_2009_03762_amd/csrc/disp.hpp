@@ -522,18 +522,18 @@ template <typename T> __device__ __forceinline__ T load_t(__amdgpu_buffer_rsrc_t
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
-// Register-resident variant for n1 = 2^a or 3 * 2^a: every thread owns fixed
-// x columns (XV of them) of one y-group and keeps its own displacement
-// planes, edge differences and sigma planes in registers; LDS only carries
-// the column exchange with the x +- 1 neighbours, the f lines and the
-// transform scratch.  The workgroup has WG = 256 threads for a power-of-two
-// n1 up to 256 and 192 for 3 * 2^a up to 192, n1 threads beyond: it splits
-// evenly into x columns, one per thread from 192 columns on, and holds
-// G = WG / n1 independent y-groups when n1 < WG.  The FP64 u exchange is
-// single-buffered: each plane is published once and the x differences it
-// yields are kept for the next step.  The z-march is unrolled by two so that
-// the per-plane buffers alternate by name (index P = z & 1) instead of being
-// copied.
+// Register-resident variant for n1 = 2^a or 3 * 2^a: every thread owns one
+// x column of one y-group and keeps its own displacement planes, edge
+// differences and sigma planes in registers; LDS only carries the column
+// exchange with the x +- 1 neighbours, the two parts of the divergence and
+// the transform scratch.  The workgroup has WG = 256 threads for a
+// power-of-two n1 up to 256 and 192 for 3 * 2^a up to 192, n1 threads
+// beyond, and holds G = WG / n1 independent y-groups when n1 < WG.  The FP64
+// u exchange is single-buffered: each plane is published once and the x
+// differences it yields are kept for the next step.  Two workgroup barriers
+// per plane (the u exchange, the divergence parts).  The z-march is unrolled
+// by two so that the per-plane buffers alternate by name (index P = z & 1)
+// instead of being copied.
 #ifndef LSFFT_STENCIL_WAVES
 #define LSFFT_STENCIL_WAVES 1
 #endif
