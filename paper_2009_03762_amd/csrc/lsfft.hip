@@ -543,10 +543,12 @@ void drop_graph(lsfft_solver s) {
   s->g_maxit = -1;
 }
 
-// Start of a refinement cycle (systems not done): fold delta into u, then
-// the FP64 cell stress of u, its mean and its divergence at the nodes.
 int stencil_yblocks(const lsfft_solver s, bool f64);
 
+// Start of a refinement cycle (systems not done): fold delta into u, then in
+// FP64 the divergence of the cell stress of u at the nodes, stored as the
+// sweeps' load -F_b, and the mean stress: by the FP64 register stencil where
+// it runs at this n1, else by the cell-stress and divergence kernels.
 template <typename T> lsfft_status refine_rebase(lsfft_solver s) {
   const long long n3 = 3 * s->d.N;
   const unsigned fb = (unsigned)std::min<long long>((n3 + 255) / 256, 4096);
