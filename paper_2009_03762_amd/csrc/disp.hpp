@@ -145,7 +145,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   for (int c = 0; c < 3; ++c) {
     const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
-    for (int e = 0; e < E; ++e) w[c][e] = valid ? src[t + TPC * e] : zero;
+    for (int e = 0; e < E; ++e) w[c][e] = valid ? ldc_nt(src + t + TPC * e) : zero;
     xn[c] = (valid && t == 0) ? a.nyq[(long long)c * a.d.rows + row] : zero;
   }
 #pragma unroll
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const long long idx = row * n1 + 2 * (t + TPC * e);
-      if (valid) ld2(a.u + c * N + idx, uo[c][e][0], uo[c][e][1]);
+      if (valid) ld2_nt(a.u + c * N + idx, uo[c][e][0], uo[c][e][1]);
       else uo[c][e][0] = uo[c][e][1] = 0.0;
     }
   const cplx<T> *twl = stage_twiddles(twl_, a.tw);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const long long idx = row * n1 + 2 * (t + TPC * e);
-        st2(a.u + c * N + idx, uo[c][e][0] + (double)w[c][e].x, uo[c][e][1] + (double)w[c][e].y);
+        st2_nt(a.u + c * N + idx, uo[c][e][0] + (double)w[c][e].x, uo[c][e][1] + (double)w[c][e].y);
       }
   }
 }
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         const long long row = (long long)zwrap(z) * n2 + yrow;
         cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
-        for (int e = 0; e < E; ++e) dst[t + TPC * e] = vv[e];
+        for (int e = 0; e < E; ++e) stc_nt(dst + t + TPC * e, vv[e]);
         if (t == 0) a.nyq[(long long)c * a.d.rows + row] = xnq;
       }
     }

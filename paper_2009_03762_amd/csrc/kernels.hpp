@@ -98,6 +98,31 @@ template <> __device__ __forceinline__ void st2<double>(double *p, double a, dou
   *reinterpret_cast<double2 *>(p) = make_double2(a, b);
 }
 
+// Streaming (non-temporal) loads and stores of two-element values, for the
+// contiguous row accesses of the x-direction kernels, which touch each value
+// of u and of the spectrum once per iteration.  The y- and z-passes keep
+// cached accesses: their column accesses share cache lines between
+// workgroups.
+template <typename T> __device__ __forceinline__ void ld2_nt(const T *p, T &a, T &b) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  a = v.x;
+  b = v.y;
+}
+template <typename T> __device__ __forceinline__ void st2_nt(T *p, T a, T b) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = a;
+  v.y = b;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+template <typename T> __device__ __forceinline__ cplx<T> ldc_nt(const cplx<T> *p) {
+  cplx<T> v;
+  ld2_nt(&p->x, v.x, v.y);
+  return v;
+}
+template <typename T> __device__ __forceinline__ void stc_nt(cplx<T> *p, cplx<T> v) { st2_nt(&p->x, v.x, v.y); }
+
 template <typename T> __device__ __forceinline__ T shfl(T v, int lane) { return __shfl(v, lane, 64); }
 
 // Partner value X[(L - k) mod L] for every point k = t + TPC e held by this
@@ -278,7 +303,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
     for (int c = 0; c < 6; ++c) {
       const cplx<T> *src = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
-      for (int e = 0; e < E; ++e) w[c][e] = src[t + TPC * e];
+      for (int e = 0; e < E; ++e) w[c][e] = ldc_nt(src + t + TPC * e);
       xn[c] = (t == 0) ? a.nyq[(long long)c * a.d.rows + row] : zero;
     }
   } else {
@@ -293,8 +318,8 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
   for (int e = 0; e < E; ++e) {
     const long long idx = row * n1 + 2 * (t + TPC * e);
     if (valid) {
-      ld2(a.lam + idx, lam[e][0], lam[e][1]);
-      ld2(a.mu + idx, mu[e][0], mu[e][1]);
+      ld2_nt(a.lam + idx, lam[e][0], lam[e][1]);
+      ld2_nt(a.mu + idx, mu[e][0], mu[e][1]);
     } else {
       lam[e][0] = lam[e][1] = mu[e][0] = mu[e][1] = T(0);
     }
@@ -305,7 +330,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const long long idx = row * n1 + 2 * (t + TPC * e);
-        if (valid && need_old) ld2(eps_src + c * N + idx, eo[c][e][0], eo[c][e][1]);
+        if (valid && need_old) ld2_nt(eps_src + c * N + idx, eo[c][e][0], eo[c][e][1]);
         else eo[c][e][0] = eo[c][e][1] = T(0);
       }
   }
@@ -328,7 +353,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
         o1 = eo[c][e][1];
       } else {
         o0 = o1 = T(0);
-        if (valid && need_old) ld2(eps_src + c * N + idx, o0, o1);
+        if (valid && need_old) ld2_nt(eps_src + c * N + idx, o0, o1);
       }
       T n0, n1v;
       if (a.mode == XMODE_UPDATE) {
@@ -348,7 +373,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
         const double d0 = (double)n0 - (double)o0, d1 = (double)n1v - (double)o1;
         sums[6] += (c < 3 ? 1.0 : 2.0) * (d0 * d0 + d1 * d1);
       }
-      if (valid && write_eps) st2(a.eps + c * N + idx, n0, n1v);
+      if (valid && write_eps) st2_nt(a.eps + c * N + idx, n0, n1v);
       ev[c][0] = n0;
       ev[c][1] = n1v;
     }
@@ -357,7 +382,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       ss[c][0] = ss[c][1] = T(0);
-      if (EIG && valid) ld2(a.sstar + c * N + idx, ss[c][0], ss[c][1]);
+      if (EIG && valid) ld2_nt(a.sstar + c * N + idx, ss[c][0], ss[c][1]);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -379,7 +404,7 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
     if (valid) {
       cplx<T> *dst = a.spec + ((long long)c * a.d.rows + row) * L;
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[t + TPC * e] = w[c][e];
+      for (int e = 0; e < E; ++e) stc_nt(dst + t + TPC * e, w[c][e]);
       if (t == 0) a.nyq[(long long)c * a.d.rows + row] = x_nyq;
     }
   }
