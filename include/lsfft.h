@@ -93,7 +93,8 @@ typedef enum {
 } lsfft_status;
 
 typedef struct {
-  int32_t n[3];            /* n1 (fastest), n2, n3: each 2^a or 3*2^a, 4..512  */
+  int32_t n[3];            /* n1 (fastest), n2, n3: each even 2^a*3^b, 4..512
+                              (odd lengths, e.g. 9 or 27, are EINVAL)       */
   double h[3];             /* grid spacing per axis; 0 means 1.0               */
   const double *lambda;    /* N Lame lambda values, HOST memory, field layout  */
   const double *mu;        /* N shear moduli mu, HOST memory, field layout     */

@@ -1,7 +1,8 @@
 """Build the HIP library liblsfft.so in-tree for gfx950.
 
-The host side, the FP32 and FP64 pass kernels and the 1D solver are four
-translation units, compiled in parallel and linked into one shared library.
+The host side, the FP32 and FP64 pass kernels (x side; y, z and strain x)
+and the 1D solver are six translation units, compiled in parallel and linked
+into one shared library.
 
 Usage: python -m paper_2009_03762_amd.build [--quick] [--verbose]
 """
@@ -17,7 +18,8 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblsfft.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("lsfft.hip", "launch_f32.hip", "launch_f64.hip", "solve1d.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("lsfft.hip", "launch_f32.hip", "launch_f32_yz.hip", "launch_f64.hip",
+                                                  "launch_f64_yz.hip", "solve1d.hip")]
 HEADERS = [os.path.join(PKG, "csrc", f) for f in ("fft.hpp", "green.hpp", "kernels.hpp", "disp.hpp", "reduce.hpp",
                                                   "solver.hpp", "launch.hpp")]
 ARCH = os.environ.get("LSFFT_ARCH", "gfx950")

@@ -125,14 +125,15 @@ __global__ __launch_bounds__(WG) void k_uxpass(UArgs<T> a) {
   a.nyq += sysb * a.bs.nyq;
   __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
-  constexpr int P = WG / TPC;
-  static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
-  __shared__ cplx<T> lds[P * line_scratch<L>()];
+  constexpr int P = lines_per_wg(TPC, WG);
+  __shared__ cplx<T> lds[line_slots<TPC, WG>() * line_scratch<L>()];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int p = tid / TPC, t = tid % TPC;
+  int p, t;
+  bool live;
+  line_of<TPC, P>(tid, p, t, live);
   const long long row = (long long)blockIdx.x * P + p;
-  const bool valid = row < a.d.rows;
+  const bool valid = live && row < a.d.rows;
   const int n1 = 2 * L;
   const long long N = a.d.N;
   cplx<T> *sl = lds + p * line_scratch<L>();
@@ -312,9 +313,9 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   constexpr int NSL = T2 + 1;   // cell lines of sigma
   constexpr int UPL = NUL * 3 * N1;
   constexpr int SPL = NSL * 6 * N1;
-  static_assert(6 * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
-  static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
-  static_assert(7 * line_scratch<L>() * 2 <= SPL, "transform scratch must fit in one sigma plane");
+  constexpr int NLW = lines_per_wg(TPC, WG);
+  static_assert(T2 * 3 <= NLW, "x transforms of the workgroup's f lines do not fit");
+  static_assert((T2 * 3 + 1) * line_scratch<L>() * 2 <= SPL, "transform scratch must fit in one sigma plane");
   __shared__ double U[2 * UPL];
   __shared__ T S[2 * SPL];
   __shared__ T F[T2 * 3 * N1];
@@ -465,8 +466,10 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
     __syncthreads();
     // ---- forward x transforms of the T2 x 3 f lines; scratch in the free sigma plane
     {
-      const int pid = tid / TPC, t = tid % TPC;
-      const bool act = pid < T2 * 3;
+      int pid, t;
+      bool live;
+      line_of<TPC, NLW>(tid, pid, t, live);
+      const bool act = live && pid < T2 * 3;
       const int m = act ? pid / 3 : 0, c = act ? pid % 3 : 0;
       cplx<T> v[E];
 #pragma unroll
@@ -474,8 +477,9 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
         const int xx = 2 * (t + TPC * e);
         v[e] = act ? cplx<T>{F[(m * 3 + c) * N1 + xx], F[(m * 3 + c) * N1 + xx + 1]} : cplx<T>{T(0), T(0)};
       }
-      // idle threads (pid >= 6) share one dummy scratch area
-      cplx<T> *scr = reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : 6) * line_scratch<L>();
+      // idle threads share one dummy scratch area past the T2 x 3 lines
+      cplx<T> *scr =
+          reinterpret_cast<cplx<T> *>(S + ((z - 1) & 1) * SPL) + (act ? pid : T2 * 3) * line_scratch<L>();
       int buf = 0;
       const cplx<T> xnq = r2c_line<T, L, E, false>(v, t, tid & 63, scr, a.tw, buf);  // twice the spectrum
       if (act) {

@@ -229,6 +229,36 @@ __device__ __forceinline__ const cplx<T> *stage_twiddles(cplx<T> (&dst)[NT], con
   return dst;
 }
 
+// Lines of TPC threads packed into wavefronts: 64 / TPC whole lines per
+// wavefront, so that no line straddles two (the line transforms exchange at
+// wavefront scope).  When TPC divides 64 every lane works and line p of a
+// workgroup is threads [p TPC, (p + 1) TPC); otherwise the lanes past the
+// last whole line of a wavefront idle.
+constexpr int lines_per_wg(int tpc, int wg) { return (wg / 64) * (64 / tpc); }
+// Line p (of NL per workgroup) and point index t of thread tid; `live` is
+// false on idle lanes, which are given the dummy line NL + wavefront (their
+// own scratch, nothing loaded or stored) and t < TPC.
+template <int TPC, int NL>
+__device__ __forceinline__ void line_of(int tid, int &p, int &t, bool &live) {
+  static_assert(TPC >= 1 && TPC <= 64, "a line must fit in one wavefront");
+  if constexpr (64 % TPC == 0) {
+    p = tid / TPC;
+    t = tid % TPC;
+    live = true;
+  } else {
+    constexpr int LPW = 64 / TPC;
+    const int w = tid >> 6, l = tid & 63, q = l / TPC;
+    live = q < LPW;
+    t = l - q * TPC;
+    p = live ? w * LPW + q : NL + w;
+  }
+}
+// Scratch lines a workgroup of WG threads needs for lines of TPC threads
+// (one dummy line per wavefront when lanes idle).
+template <int TPC, int WG> constexpr int line_slots() {
+  return lines_per_wg(TPC, WG) + (64 % TPC == 0 ? 0 : WG / 64);
+}
+
 // Number of LDS exchanges the transform performs (passes - 1).
 template <int L, int E> constexpr int fft_exchanges() { return Plan<L, E>::npass() - 1; }
 

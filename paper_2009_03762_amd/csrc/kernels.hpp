@@ -274,16 +274,17 @@ __global__ __launch_bounds__(WG, (x_min_waves<T, L, E, EIG>())) void k_xpass(XAr
   const T lam0 = a.mem[sysb].lam0, mu0 = a.mem[sysb].mu0;
   __shared__ cplx<T> twl_[2 * L];
   constexpr int TPC = L / E;
-  constexpr int P = WG / TPC;
+  constexpr int P = lines_per_wg(TPC, WG);
   constexpr bool PRELOAD_EPS = (sizeof(T) == 4) && LSFFT_X_PRELOAD;
-  static_assert(64 % TPC == 0 || TPC == 1, "a line must not straddle wavefronts");
-  __shared__ cplx<T> lds[P * line_scratch<L>()];
+  __shared__ cplx<T> lds[line_slots<TPC, WG>() * line_scratch<L>()];
   __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int p = tid / TPC, t = tid % TPC;
+  int p, t;
+  bool live;
+  line_of<TPC, P>(tid, p, t, live);
   const long long row = (long long)blockIdx.x * P + p;
-  const bool valid = row < a.d.rows;
+  const bool valid = live && row < a.d.rows;
   const int n1 = 2 * L;
   const long long N = a.d.N;
   cplx<T> *sl = lds + p * line_scratch<L>();

@@ -1,12 +1,13 @@
-// Pass-kernel launches of the float solvers: every instantiation of the x, y,
-// z, displacement-update and stencil kernels in this precision lives in this
-// translation unit.
+// Pass-kernel launches of the float solvers, x side: the stencils, the
+// displacement update and the kernel description.  The y and z passes and the
+// strain-form x-pass of this precision live in launch_f32_yz.hip (two
+// translation units, so the library's kernels compile in parallel).
 #include "launch.hpp"
 
 namespace lsfft_host {
 
-template struct Launch<float>;
-template hipError_t Launch<float>::ypass<true>(lsfft_solver, const lsfft::YArgs<float> &, int);
-template hipError_t Launch<float>::ypass<false>(lsfft_solver, const lsfft::YArgs<float> &, int);
+template hipError_t Launch<float>::stencil(lsfft_solver, const lsfft::SArgs<float> &, int);
+template hipError_t Launch<float>::uxpass(lsfft_solver, const lsfft::UArgs<float> &, int);
+template std::string Launch<float>::describe(lsfft_solver);
 
 }  // namespace lsfft_host

@@ -321,7 +321,7 @@ hipError_t launch_bars(int n, int count, const lsfft::Bar1dArgs<T> &a, hipStream
   case Nv:                                                                                           \
     hipLaunchKernelGGL((lsfft::k_bar_1d<T, Nv, bar_e(Nv)>), dim3(count), dim3(Nv / bar_e(Nv)), 0, st, a); \
     return hipGetLastError();
-    LSFFT_YZ_LENGTHS(BCASE)
+    LSFFT_BAR_LENGTHS(BCASE)
 #undef BCASE
     default:
       return hipErrorInvalidValue;
@@ -555,7 +555,7 @@ extern "C" lsfft_status lsfft_solve_1d_noalloc(const lsfft_config_1d *cfg, int32
             lsfft::NOALLOC_MAX_N);
     return LSFFT_EINVAL;
   }
-  if (!lsfft_host::supported_len(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
+  if (!lsfft_host::supported_len_1d(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
   if (cfg->scheme < LSFFT_1D_F || cfg->scheme > LSFFT_1D_DGO) return LSFFT_EINVAL;
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F32 && cfg->prec != LSFFT_F64) return LSFFT_EINVAL;
@@ -574,7 +574,7 @@ extern "C" lsfft_status lsfft_solve_1d(const lsfft_config_1d *cfg, int32_t count
                                        const double *Ebar, double tol, int32_t maxit, double *E_out, double *S_out,
                                        int32_t *iters, double *residual, int32_t *status) {
   if (!cfg || !C || !CH || !Ebar || count < 1 || count > 65535) return LSFFT_EINVAL;
-  if (!lsfft_host::supported_len(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
+  if (!lsfft_host::supported_len_1d(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
   if (cfg->scheme < LSFFT_1D_F || cfg->scheme > LSFFT_1D_DGO) return LSFFT_EINVAL;
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F32 && cfg->prec != LSFFT_F64) return LSFFT_EINVAL;

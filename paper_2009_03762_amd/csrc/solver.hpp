@@ -21,7 +21,9 @@ namespace lsfft_host {
 // ------------------------------------------------------------------ sizes
 // Points per thread for each transform: y and z use radix-8/4/2 passes with 8
 // points per thread, x uses 4 (its six strain and six spectrum components are
-// all held in registers); lengths with a factor 3 use 6 (x, z) or 12 (y).
+// all held in registers); lengths with a factor 3 use 6 (x, z) or 12 (y),
+// or the smallest multiple of 3 (of 6 on even lengths) that divides the
+// length and keeps a line within the given number of threads.
 #ifndef LSFFT_XE
 #define LSFFT_XE 4
 #endif
@@ -32,9 +34,17 @@ namespace lsfft_host {
 #define LSFFT_ZSEG 64
 #endif
 constexpr int e_pow2(int L) { return L < 8 ? L : 8; }
-constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : 6) : (L < LSFFT_XE ? L : LSFFT_XE); }
-constexpr int ey_of(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : e_pow2(n); }
-constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < LSFFT_ZE ? n : LSFFT_ZE); }
+constexpr int e_mult3(int L, int maxtpc) {
+  const int base = (L % 2 == 0) ? 6 : 3;
+  for (int e = base; e < L; e += base)
+    if (L % e == 0 && L / e <= maxtpc) return e;
+  return L;
+}
+constexpr int ex_of(int L) { return (L % 3 == 0) ? (L < 6 ? L : e_mult3(L, 64)) : (L < LSFFT_XE ? L : LSFFT_XE); }
+constexpr int ey_of(int n) {
+  return (n % 3 == 0) ? (n < 12 ? n : (n % 12 == 0 ? 12 : e_mult3(n, 64))) : e_pow2(n);
+}
+constexpr int ez_of(int n) { return (n % 3 == 0) ? (n < 6 ? n : e_mult3(n, 64)) : (n < LSFFT_ZE ? n : LSFFT_ZE); }
 // Columns per workgroup: at least `seg` bytes of each row (coalescing), at
 // least 256 threads per workgroup.
 template <typename T> constexpr int pcols_seg(int n, int E, int seg) {
@@ -57,7 +67,7 @@ template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(
 #endif
 template <typename T> constexpr int ezu_of(int n) {
   const int e = sizeof(T) == 8 ? LSFFT_ZUE64 : LSFFT_ZUE;
-  return (n % 3 == 0) ? (n < 6 ? n : 6) : (n < e ? n : e);
+  return (n % 3 == 0) ? (n < 6 ? n : e_mult3(n, 64)) : (n < e ? n : e);
 }
 template <typename T> constexpr int pcols_zu(int n, int E) {
   return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
@@ -76,7 +86,7 @@ template <typename T> constexpr int palt(int n, int E, int P) {
 constexpr int XWG = 256;
 // Stencil kernel: its 2 x 3 x-transforms must fit in 256 threads (<= 32 threads each).
 constexpr int es_of(int L) {
-  return (L % 3 == 0) ? (L < 6 ? L : (L > 192 ? L / 32 : 6)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
+  return (L % 3 == 0) ? (L < 6 ? L : e_mult3(L, 32)) : (L < 4 ? L : (L > 128 ? L / 32 : 4));
 }
 // Points per thread of the register stencil's x-transforms: four on
 // power-of-two lines (at most 64 threads per line, inside one wavefront),
@@ -90,7 +100,8 @@ constexpr int ST2 = LSFFT_ST2;
 // beyond 256 columns, where two would not fit in LDS.
 template <typename T> constexpr int st2_of(int n1) { return (sizeof(T) == 8 && n1 > 256) ? 1 : ST2; }
 // The register-resident stencil takes n1 = 2^a >= 8 and 3 * 2^a in [12, 384]
-// (256- and 192-thread workgroups); other lengths use the LDS stencil.
+// (256- and 192-thread workgroups); other lengths (4, 6, and those with a
+// factor 9) use the LDS stencil.
 constexpr bool stencil_reg_kernel(int n1) {
   return lsfft::pow2_len(n1) ? n1 >= 8 : (n1 % 3 == 0 && lsfft::pow2_len(n1 / 3) && n1 >= 12 && n1 <= 384);
 }
@@ -114,14 +125,21 @@ template <typename T> constexpr long long stencil_lds(int n1) {
 }
 template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T>(n1) <= 150000; }
 
-// Lengths handled by the dispatch switches.  Every supported n_r = 2^a 3^b in
-// [4, 512] appears for y / z; x uses n1/2.
+// Lengths handled by the dispatch switches.  Every supported n_r (even,
+// 2^a 3^b, in [4, 512]) appears for y / z; x uses n1/2.
 #ifdef LSFFT_QUICK_BUILD
 #define LSFFT_YZ_LENGTHS(X) X(8) X(16) X(64) X(256)
 #define LSFFT_X_LENGTHS(X) X(4) X(8) X(32) X(128)
+#define LSFFT_BAR_LENGTHS(X) X(8) X(16) X(64) X(256)
 #else
-#define LSFFT_YZ_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
-#define LSFFT_X_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+// bar lengths of the 1D solver: 2^a and 3 * 2^a
+#define LSFFT_BAR_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define LSFFT_YZ_LENGTHS(X)                                                                                  \
+  X(4) X(6) X(8) X(12) X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) \
+  X(192) X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
+#define LSFFT_X_LENGTHS(X)                                                                                   \
+  X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) X(64) X(72) X(81) X(96)  \
+  X(108) X(128) X(144) X(162) X(192) X(216) X(243) X(256)
 #endif
 
 }  // namespace lsfft_host
@@ -213,7 +231,16 @@ struct lsfft_solver_s {
 namespace lsfft_host {
 
 // The transform lengths the kernels are instantiated for: 2^a or 3 * 2^a.
+// Grid lengths of the 3D solver: even 2^a 3^b in [4, 512].
 inline bool supported_len(int n) {
+  if (n < 4 || n > 512 || (n & 1)) return false;
+  int m = n;
+  while (m % 2 == 0) m /= 2;
+  while (m % 3 == 0) m /= 3;
+  return m == 1;
+}
+// Bar lengths of the 1D solver: 2^a or 3 * 2^a in [4, 512].
+inline bool supported_len_1d(int n) {
   if (n < 4 || n > 512 || (n & 1)) return false;
   int m = n;
   while (m % 2 == 0) m /= 2;
@@ -263,7 +290,7 @@ template <typename T> struct Tiles {
       default:
         return 0;
     }
-    const int P = XWG / tpc;
+    const int P = lsfft::lines_per_wg(tpc, XWG);
     return (int)((rows + P - 1) / P);
   }
   // columns per y-pass workgroup of tile variant v

@@ -1,0 +1,178 @@
+"""Grid lengths with a factor 9 (the even 2^a 3^b that are not 2^a or 3 * 2^a)
+in every axis position, against the oracle at fixed iteration counts
+(Sec. 5.2, Alg. T3; the displacement form's stencils of Sec. 5.3, eq. (43);
+the strain form's Green operators of Sec. 5.1 and the DGO of Sec. 5.4).
+
+Shapes are written (n1, n2, n3), n1 the fastest axis.  On these x lengths a
+line of the real x transform takes L / E threads (L = n1 / 2), a count that
+need not divide a wavefront: the kernels pack whole lines into each
+wavefront and leave the remaining lanes idle, so these cases check that
+packing (and the ragged last workgroup of lines) as much as the radix-3
+passes.  Where the displacement stencil's LDS does not hold n1 columns
+(n1 >= 432) the default form is the strain form, which the kernel names
+confirm."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import green, solve3d  # noqa: E402
+from paper_2009_03762_amd import inputs  # noqa: E402
+
+from oracle_ref import plane_errors, rel  # noqa: E402
+
+NAMES = {"basic": "basic", "fb": "FB", "afb": "AFB", "cd": "CD", "acd": "ACD"}
+EB = np.array([1e-3, -2e-4, 3e-4, 1e-4, -1e-4, 5e-4])
+LENGTHS = [18, 36, 54, 108, 144, 162, 216, 288, 324, 432, 486]
+K = 10
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2009_03762_amd import lsfft
+    return lsfft
+
+
+def _cell(shape, seed):
+    n1, n2, n3 = shape
+    lam, mu = inputs.random_moduli(shape, seed=seed, E_range=(1.0, 100.0))
+    assert lam.shape == (n3, n2, n1)
+    return lam, mu, 0.5 * (lam.min() + lam.max()), 0.5 * (mu.min() + mu.max())
+
+
+def _check(out, hist, ref, prec):
+    f64 = prec == "f64"
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < (1e-12 if f64 else 1e-5)
+    assert rel(out["sig"], ref.sig) < (1e-12 if f64 else 1e-5)
+    assert rel(out["sig_mean"], ref.sig_mean) < (1e-12 if f64 else 1e-6)
+    assert rel(hist, np.array(ref.history)) < (1e-9 if f64 else 1e-3)
+    for name, err in plane_errors(out["eps"], ref.eps).items():
+        assert err < (1e-10 if f64 else 1e-4), name
+
+
+def _disp_fits(n1, prec):
+    """The LDS stencil's shared memory for n1 columns (two FP64 u planes of
+    T2 + 2 lines, two sigma planes of T2 + 1 lines, the f lines; T2 = 1 in
+    FP64 beyond 256 columns) within its 150000-byte budget."""
+    ts = 4 if prec == "f32" else 8
+    t2 = 1 if (prec == "f64" and n1 > 256) else 2
+    return n1 * (2 * (t2 + 2) * 3 * 8 + (2 * (t2 + 1) * 6 + t2 * 3) * ts) + 256 <= 150000
+
+
+@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("scheme,prec", [("afb", "f64"), ("afb", "f32"), ("fb", "f64")])
+def test_length9_in_each_axis(L, n, axis, scheme, prec):
+    shape = [8, 6, 4]
+    shape[axis] = n
+    shape = tuple(shape)
+    lam, mu, l0, m0 = _cell(shape, seed=3 * n + axis)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec)
+    kern = s.describe()
+    print(f"\n[lengths9] (n1,n2,n3)={shape} {scheme} {prec}: {kern}", flush=True)
+    tn = "float" if prec == "f32" else "double"
+    names = kern.split()
+    if _disp_fits(shape[0], prec):
+        assert names[0].split("<")[0] in ("k_stencil", "k_stencil_reg")
+        assert names[0].startswith(f"{names[0].split('<')[0]}<{tn},{shape[0]},")
+        assert names[2].startswith(f"k_zpass_u<{tn},{shape[2]},")
+    else:
+        assert names[0].startswith(f"k_xpass<{tn},{shape[0] // 2},")
+        assert names[2].startswith(f"k_zpass<{tn},{shape[2]},")
+    assert names[1].startswith(f"k_ypass<{tn},{shape[1]},")
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K)
+    _check(out, hist, ref, prec)
+
+
+@pytest.mark.parametrize("n1", [36, 486])
+def test_displacement_form_where_it_fits(L, n1):
+    """Forcing the displacement form: accepted where its stencil fits (36
+    columns), EINVAL where it does not (486 columns in FP32)."""
+    shape = (n1, 6, 4)
+    lam, mu, l0, m0 = _cell(shape, seed=n1)
+    if _disp_fits(n1, "f32"):
+        s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement")
+        assert s.describe().split()[0].startswith(f"k_stencil<float,{n1},")
+        s.close()
+    else:
+        with pytest.raises(L.LsfftError) as e:
+            L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement")
+        assert e.value.status == L.EINVAL
+
+
+@pytest.mark.parametrize("scheme", ["basic", "cd", "acd", "afb"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_strain_form_schemes(L, scheme, prec):
+    """The strain form of every Green operator on a cell with a factor 9 or
+    27 in each axis (x-pass lines of 3 threads, 21 to a wavefront)."""
+    shape = (36, 18, 54)
+    lam, mu, l0, m0 = _cell(shape, seed=11)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec, form="strain")
+    print(f"\n[lengths9 strain] {shape} {scheme} {prec}: {s.describe()}", flush=True)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K)
+    _check(out, hist, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dgo_length9(L, prec):
+    shape = (18, 12, 36)
+    M = 2
+    lam, mu, l0, m0 = _cell(shape, seed=5)
+    s = L.Solver(lam, mu, l0, m0, scheme="dgo", disc="pcd", prec=prec, dgo_images=M, dgo_weight_power=1)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    s.close()
+    Gc = green.dgo_voigt(shape, l0, m0, M, 1)
+    ref = solve3d.solve_dgo(lam, mu, EB, l0, m0, Gc, tol=0.0, maxit=K)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < tol
+    assert rel(out["sig"], ref.sig) < tol
+
+
+def test_converged_fp64_length9(L):
+    """Converged AFB solve on a 36 x 18 x 72 cubic inclusion: the oracle's
+    iteration count and solution."""
+    shape = (36, 18, 72)
+    lam, mu = inputs.cubic_inclusion(shape, (18, 8, 36), 1.0, 10.0)
+    assert lam.shape == (72, 18, 36)
+    l0, m0 = inputs.reference_medium_mean(1.0, 10.0)
+    Eb = inputs.macro_strain("12", 1e-3)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f64")
+    out = s.solve(Eb, tol=1e-8, maxit=2000)
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, Eb, l0, m0, scheme="AFB", tol=1e-8, maxit=2000)
+    assert out["status"] == L.OK and ref.status == solve3d.OK
+    assert out["iters"] == ref.iters
+    assert rel(out["eps"], ref.eps) < 1e-11
+    assert rel(out["sig_mean"], ref.sig_mean) < 1e-11
+
+
+@pytest.mark.parametrize("opt", ["warm", "refine"])
+def test_f32_options_length9(L, opt):
+    """FP64 warm start and FP64 refinement on an x length with a factor 9."""
+    shape = (72, 12, 18)
+    lam, mu, l0, m0 = _cell(shape, seed=72)
+    kw = {"f64_warmup": 3} if opt == "warm" else {"refine": 4}
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", **kw)
+    print(f"\n[lengths9 {opt}] {shape}: {s.describe()}", flush=True)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K)
+    assert out["iters"] == K
+    assert rel(out["eps"], ref.eps) < (1e-5 if opt == "warm" else 1e-6)
+    if opt == "warm":
+        assert rel(hist[:3], np.array(ref.history[:3])) < 1e-9
+    else:
+        assert rel(hist, np.array(ref.history)) < 1e-3

@@ -44,8 +44,10 @@ def _mat(shape, lam=1.0, mu=1.0):
     return np.full((n3, n2, n1), lam), np.full((n3, n2, n1), mu)
 
 
-@pytest.mark.parametrize("shape", [(10, 8, 8), (8, 7, 8), (8, 8, 1024), (2, 8, 8), (8, 8, 27), (18, 8, 8),
-                                   (8, 36, 8), (8, 8, 768)])
+# Supported: even 2^a 3^b in [4, 512] on every axis.  Rejected: a factor 5 or
+# 7, odd lengths (27 = 3^3, 9), lengths past 512 (768, 1024) or below 4.
+@pytest.mark.parametrize("shape", [(10, 8, 8), (8, 7, 8), (8, 8, 1024), (2, 8, 8), (8, 8, 27), (9, 8, 8),
+                                   (8, 40, 8), (8, 8, 768), (8, 8, 972)])
 def test_unsupported_sizes_rejected(L, shape):
     lam, mu = _mat(shape)
     with pytest.raises(L.LsfftError) as e:
