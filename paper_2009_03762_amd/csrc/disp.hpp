@@ -97,7 +97,7 @@ __device__ __forceinline__ void green_disp_point(const GreenParams<T> &g, const 
     return;
   }
   // K^{-1} = (1 / (mu0 |k|^2)) [I - beta k (x) k / |k|^2],  beta = (lam0+mu0)/(lam0+2mu0)
-  const T inv = T(1) / kk;
+  const T inv = recip(kk);
   const T a1 = g.c1 * inv * g.scale;
   const cplx<T> kf = k[0] * f[0] + k[1] * f[1] + k[2] * f[2];
   const cplx<T> a2 = (g.beta * inv) * kf;
@@ -504,26 +504,6 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
     }
   }
   if (a.counter) last_block_reduce<WG>(a.red, a.counter, sysb, red);
-}
-
-// Buffer resources over a field of `count` elements (raw: offsets in bytes,
-// bounds-checked against the field's size, which stays below 4 GiB for every
-// supported grid) and loads through them: the load adds a scalar byte offset
-// to the per-thread one, so a plane-invariant per-thread offset needs no
-// vector address arithmetic.
-template <typename E>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const E *p, long long count) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<E *>(p), 0, (int)(unsigned)(count * (long long)sizeof(E)),
-                                           0x00020000);
-}
-__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-template <typename T> __device__ __forceinline__ T load_t(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
 // Register-resident variant for n1 = 2^a or 3 * 2^a: every thread owns one
@@ -970,6 +950,8 @@ __global__ __launch_bounds__(P *(NZ / E), (zu_min_waves<T, SCH>())) void k_zpass
     zstride = a.d.n2;
     cstride = a.d.comp_nyq;
   }
+  // global addressing: buffer loads with scalar z offsets (as in the strain
+  // form's z-pass) issue fewer instructions here but measured 3 % slower
   cplx<T> v[3][E];
 #pragma unroll
   for (int c = 0; c < 3; ++c)

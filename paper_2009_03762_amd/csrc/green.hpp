@@ -29,6 +29,11 @@
 
 namespace lsfft {
 
+// 1 / x: the hardware reciprocal in FP32 (1 ulp; the Green steps' 1 / |k|^2
+// and complex divisions, far from the denormal range), a division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 enum { SCHEME_BASIC = 0, SCHEME_FB = 1, SCHEME_AFB = 2, SCHEME_DGO = 3, SCHEME_CD = 4, SCHEME_ACD = 5 };
 
 // Table kinds, laid out tab[kind * (n1 + n2 + n3) + off[axis] + i]:
@@ -93,7 +98,7 @@ __device__ __forceinline__ double green_real(const GreenParams<T> &g, const T (&
     v[i] = k[0] * s[voigt(i, 0)] + k[1] * s[voigt(i, 1)] + k[2] * s[voigt(i, 2)];
   }
   const double res = (double)norm2(v[0]) + (double)norm2(v[1]) + (double)norm2(v[2]);
-  const T inv = T(1) / kk;
+  const T inv = recip(kk);
   const cplx<T> kv = k[0] * v[0] + k[1] * v[1] + k[2] * v[2];
   const T a1 = -g.c1 * inv * g.scale;                  // -(1/mu0)/|k|^2
   const cplx<T> a2 = (g.c2 * inv * inv * g.scale) * kv;  // +c2 (k.v)/|k|^4
@@ -107,8 +112,8 @@ __device__ __forceinline__ double green_real(const GreenParams<T> &g, const T (&
 }
 
 template <typename T> __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) {
-  const T d = b.x * b.x + b.y * b.y;
-  return cplx<T>{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+  const T r = recip(b.x * b.x + b.y * b.y);
+  return cplx<T>{(a.x * b.x + a.y * b.y) * r, (a.y * b.x - a.x * b.y) * r};
 }
 
 // FB Green step with complex a = q^a, q^b = conj(a).

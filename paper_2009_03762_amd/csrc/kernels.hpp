@@ -123,6 +123,44 @@ template <typename T> __device__ __forceinline__ cplx<T> ldc_nt(const cplx<T> *p
 }
 template <typename T> __device__ __forceinline__ void stc_nt(cplx<T> *p, cplx<T> v) { st2_nt(&p->x, v.x, v.y); }
 
+// Buffer resources over a field of `count` elements (raw: offsets in bytes,
+// bounds-checked against the field's size, which stays below 4 GiB for every
+// supported grid) and loads through them: the load adds a scalar byte offset
+// to the per-thread one, so a plane-invariant per-thread offset needs no
+// vector address arithmetic.
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const E *p, long long count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<E *>(p), 0, (int)(unsigned)(count * (long long)sizeof(E)),
+                                           0x00020000);
+}
+__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <typename T> __device__ __forceinline__ T load_t(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+// Complex values through a buffer resource (8 bytes in FP32, 16 in FP64).
+template <typename T> __device__ __forceinline__ cplx<T> load_c(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, cplx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+  } else {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, (int)voff, (int)soff, 0);
+  }
+}
+
 template <typename T> __device__ __forceinline__ T shfl(T v, int lane) { return __shfl(v, lane, 64); }
 
 // Partner value X[(L - k) mod L] for every point k = t + TPC e held by this
@@ -526,34 +564,43 @@ __global__ __launch_bounds__(P *(NZ / E), (z_min_waves<T, SCH>())) void k_zpass(
   const int tid = threadIdx.x;
   const int p = tid % P, t = tid / P;
   const int L = a.d.L;
-  cplx<T> *base;
-  long long zstride, cstride;
+  // one buffer resource per component (each below 4 GiB): the thread's
+  // column and z point a fixed 32-bit byte offset, each z step a scalar one;
+  // a column past the last one lies past the resource (its loads return 0)
+  unsigned zstride, voff;
   int i1, i2;
   bool valid;
+  const cplx<T> *cbase;
+  long long cstride;
   if ((long long)blockIdx.x < a.main_blocks) {
-    const long long col = tile_of(blockIdx.x, a.main_blocks, a.xcd) * P + p;
-    valid = col < (long long)a.d.n2 * L;
-    i2 = (int)(col / L);
-    i1 = (int)(col % L);
-    base = a.spec + col;
-    zstride = (long long)a.d.n2 * L;
+    const unsigned col = (unsigned)(tile_of(blockIdx.x, a.main_blocks, a.xcd) * P + p);
+    valid = col < (unsigned)(a.d.n2 * L);
+    i2 = (int)(col / (unsigned)L);
+    i1 = (int)(col % (unsigned)L);
+    zstride = (unsigned)(a.d.n2 * L);
+    cbase = a.spec;
     cstride = a.d.comp_main;
+    voff = (col + (unsigned)t * zstride) * (unsigned)sizeof(cplx<T>);
   } else {
-    const long long col = ((long long)blockIdx.x - a.main_blocks) * P + p;
-    valid = col < a.d.n2;
+    const unsigned col = (unsigned)(((long long)blockIdx.x - a.main_blocks) * P + p);
+    valid = col < (unsigned)a.d.n2;
     i2 = (int)col;
     i1 = L;
-    base = a.nyq + col;
-    zstride = a.d.n2;
+    zstride = (unsigned)a.d.n2;
+    cbase = a.nyq;
     cstride = a.d.comp_nyq;
+    voff = (col + (unsigned)t * zstride) * (unsigned)sizeof(cplx<T>);
   }
+  __amdgpu_buffer_rsrc_t rs[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) rs[c] = buffer_of(cbase + c * cstride, cstride);
+  auto soff = [&](int e) { return (unsigned)(TPC * e) * zstride * (unsigned)sizeof(cplx<T>); };
   cplx<T> v[6][E];
   // every load of the tile first, then the transforms
 #pragma unroll
   for (int c = 0; c < 6; ++c)
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      v[c][e] = valid ? base[c * cstride + (t + TPC * e) * zstride] : cplx<T>{T(0), T(0)};
+    for (int e = 0; e < E; ++e) v[c][e] = load_c<T>(rs[c], voff, soff(e));
   const AxisVal<T> axx = axis_val_s<SCH>(a.g, 0, i1), axy = axis_val_s<SCH>(a.g, 1, valid ? i2 : 0);
 #if LSFFT_LDS_AXIS
   __shared__ AxisVal<T> axl[NZ];
@@ -572,7 +619,7 @@ __global__ __launch_bounds__(P *(NZ / E), (z_min_waves<T, SCH>())) void k_zpass(
 #pragma unroll
       for (int c = 0; c < 6; ++c)
 #pragma unroll
-        for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
+        for (int e = 0; e < E; ++e) store_c<T>(rs[c], voff, soff(e), v[c][e]);
     }
     return;
   }
@@ -598,7 +645,7 @@ __global__ __launch_bounds__(P *(NZ / E), (z_min_waves<T, SCH>())) void k_zpass(
     fft_pencil<T, NZ, E, false>(v[c], t, lds + p, P, twl, 1, buf);
     if (valid) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) base[c * cstride + (t + TPC * e) * zstride] = v[c][e];
+      for (int e = 0; e < E; ++e) store_c<T>(rs[c], voff, soff(e), v[c][e]);
     }
   }
   if (a.partial) {
