@@ -564,7 +564,7 @@ def refine_study(n=256, tols=(1e-6, 1e-8), maxit=1500):
     return out
 
 
-def size_sweep(sizes=(32, 64, 128, 192, 256, 384, 512)):
+def size_sweep(sizes=(32, 64, 128, 144, 192, 256, 288, 384, 512)):
     """Throughput of the benchmark workload (AFB, contrast 1e3, tol 0) across
     grid sizes, both precisions, automatic form, tuned schedule, replayed
     iteration graphs: where the path is launch-bound and where it streams."""
