@@ -247,13 +247,25 @@ __device__ __forceinline__ cplx<T> r2c_line(cplx<T> (&v)[E], int t, int lane, cp
 }
 
 template <int WG> __device__ __forceinline__ void block_sum(double *vals, int nv, double *red) {
-  // fixed-order reduction: per-wavefront butterfly, then wavefronts in order
+  // fixed-order reduction: per-wavefront butterfly, then wavefronts in order.
+  // A workgroup that is not whole wavefronts (some y and z tiles of lengths
+  // with a factor 9) has lanes past its last thread that were never
+  // launched: their values are discarded.  Lane 0 reads each lane m once, at
+  // the step of m's highest set bit, when m holds the sum over lanes above
+  // it only, so for a partial wavefront every value it discards is empty.
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = (WG + 63) / 64;
+  const int live = (WG % 64 != 0 && wave == NW - 1) ? WG - 64 * (NW - 1) : 64;
   for (int i = 0; i < nv; ++i) {
     double x = vals[i];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(x, o, 64);
+      if constexpr (WG % 64 == 0)
+        x += y;
+      else
+        x += ((lane ^ o) < live) ? y : 0.0;
+    }
     if (lane == 0) red[wave * 8 + i] = x;
   }
   __syncthreads();
