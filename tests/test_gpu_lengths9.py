@@ -176,3 +176,79 @@ def test_f32_options_length9(L, opt):
         assert rel(hist[:3], np.array(ref.history[:3])) < 1e-9
     else:
         assert rel(hist, np.array(ref.history)) < 1e-3
+
+
+def _probe(L, h, n3):
+    """Each knob's values the handle accepts (the default and its doubled or
+    halved tiles, the even plane counts dividing n3)."""
+    d = L.get_schedule(h)
+    out = {}
+    for key in ("y_cols", "z_cols"):
+        vals = [d[key]]
+        for c in (d[key] // 2, d[key] * 2):
+            try:
+                L.set_schedule(h, dict(d, **{key: c}))
+                vals.append(c)
+            except L.LsfftError as e:
+                assert e.status == L.EINVAL
+        out[key] = vals
+    out["stencil_planes"] = [z for z in (2, 6, 18) if n3 % z == 0] if d["stencil_planes"] else [0]
+    L.set_schedule(h, d)
+    return d, out
+
+
+@pytest.mark.parametrize("form,prec", [("displacement", "f32"), ("displacement", "f64"), ("strain", "f64")])
+def test_offered_schedules_length9(L, form, prec):
+    """Every offered tile of the y and z passes (many of them workgroups that
+    are not whole wavefronts on these lengths, whose block sums feed the
+    residual) and plane count gives the iterates of the default schedule."""
+    shape = (36, 18, 54)
+    lam, mu, l0, m0 = _cell(shape, seed=36)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec=prec, form=form)
+    d, offered = _probe(L, s.handle, shape[2])
+    print(f"\n[lengths9 schedule] {form} {prec} default {d} offered {offered}", flush=True)
+    assert len(offered["z_cols"]) == 2  # 28 and 56 (FP32) or 14 (FP64) columns of 9 threads
+    ref = s.solve(EB, tol=0.0, maxit=K)
+    hist_ref = s.residual_history()
+    tol = 1e-13 if prec == "f64" else 2e-6
+    for z in offered["stencil_planes"]:
+        for y in offered["y_cols"]:
+            for zc in offered["z_cols"]:
+                for x in (0, 7):
+                    sch = {"stencil_planes": z, "y_cols": y, "z_cols": zc, "xcd_order": x}
+                    L.set_schedule(s.handle, sch)
+                    out = s.solve(EB, tol=0.0, maxit=K)
+                    assert rel(out["eps"], ref["eps"]) < tol, sch
+                    assert rel(s.residual_history(), hist_ref) < (1e-9 if prec == "f64" else 1e-5), sch
+    s.close()
+    oref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K)
+    assert rel(ref["eps"], oref.eps) < (1e-12 if prec == "f64" else 1e-5)
+
+
+def test_batch_and_group_length9(L):
+    """Two cells of different sizes with factor-9 lengths, two loads each:
+    one group graph gives each batch's own iterates bit for bit, and both
+    match the oracle."""
+    loads = np.array([[1e-3, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 1e-3]])
+    cells = [_cell((18, 18, 18), seed=18), _cell((36, 18, 54), seed=54)]
+    shapes = [(18, 18, 18), (36, 18, 54)]
+    hs = [L.create_batch([c, c], scheme="afb", prec="f64") for c in cells]
+    try:
+        devs = [torch.zeros((2, 6) + sh[::-1], dtype=torch.float64, device="cuda") for sh in shapes]
+        st, res = L.solve_group(hs, [loads, loads], 0.0, K, eps_devs=devs)
+        torch.cuda.synchronize()
+        eps = [d.cpu().numpy() for d in devs]
+        each = []
+        for h, sh in zip(hs, shapes):
+            d1 = torch.zeros((2, 6) + sh[::-1], dtype=torch.float64, device="cuda")
+            L.solve_batch(h, loads, 0.0, K, eps_dev=d1)
+            torch.cuda.synchronize()
+            each.append(d1.cpu().numpy())
+    finally:
+        for h in hs:
+            L.destroy(h)
+    for (lam, mu, l0, m0), e, e1 in zip(cells, eps, each):
+        assert np.array_equal(e, e1)
+        for b in range(2):
+            ref = solve3d.solve_gfp(lam, mu, loads[b], l0, m0, scheme="AFB", tol=0.0, maxit=K)
+            assert rel(e[b], ref.eps) < 1e-12
