@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
   __shared__ double U[2 * UPL];
   __shared__ T S[2 * SPL];
   __shared__ T F[T2 * 3 * N1];
-  __shared__ double red[(WG / 64) * 8];
+  __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
@@ -511,8 +511,10 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 // differences and sigma planes in registers; LDS only carries the column
 // exchange with the x +- 1 neighbours, the two parts of the divergence and
 // the transform scratch.  The workgroup has WG = 256 threads for a
-// power-of-two n1 up to 256 and 192 for 3 * 2^a up to 192, n1 threads
-// beyond, and holds G = WG / n1 independent y-groups when n1 < WG.  The FP64
+// power-of-two n1 up to 256, 192 for 3 * 2^a up to 192, the most whole
+// y-groups that fit in 256 threads for lengths with a factor 9 (e.g. 252 at
+// 36 columns, 144 at 144: not always whole wavefronts), n1 threads beyond,
+// and holds G = WG / n1 independent y-groups when n1 < WG.  The FP64
 // u exchange is single-buffered: each plane is published once and the x
 // differences it yields are kept for the next step.  Two workgroup barriers
 // per plane (the u exchange, the divergence parts).  The z-march is unrolled
@@ -523,6 +525,7 @@ __global__ __launch_bounds__(256) void k_stencil(SArgs<T> a) {
 #endif
 constexpr bool pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
 constexpr int stencil_wg_of(int n1) {
+  if (n1 % 9 == 0) return n1 >= 256 ? n1 : (256 / n1) * n1;
   const int base = pow2_len(n1) ? 256 : 192;
   return n1 > base ? n1 : base;
 }
@@ -561,14 +564,18 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
   constexpr int NF = NPEN * N1;                  // the two divergence parts of a plane (T)
   constexpr int SCR = NPEN * line_scratch<L>();  // transform scratch (complex T)
   static_assert(G * NX == WG, "the workgroup must split evenly into x columns");
-  static_assert(NPEN * TPC <= WG, "x transforms of the workgroup's f lines do not fit");
-  static_assert(64 % TPC == 0, "a line must not straddle wavefronts");
+  static_assert(TPC <= 64, "a line must fit in one wavefront");
+  // Whole x-lines the workgroup's wavefronts hold (64 / TPC per wavefront, a
+  // partial last wavefront included) and the rounds of line transforms a
+  // plane takes: one, except on some lengths with a factor 9.
+  constexpr int NLW = (WG / 64) * (64 / TPC) + (WG % 64) / TPC;
+  constexpr int ROUNDS = (NPEN + NLW - 1) / NLW;
   __shared__ double Ux[UX];
   __shared__ T Fv[NF];  // f_i's part from the own column, at x
   __shared__ T Fu[NF];  // f_i's part that column x takes from column x-1, at x
   __shared__ cplx<T> Scr[SCR];
   __shared__ cplx<T> twl[N1];   // the x twiddles, read by every transform below
-  __shared__ double red[(WG / 64) * 8];
+  __shared__ double red[(WG + 63) / 64 * 8];
   const int tid = threadIdx.x;
   const int n2 = a.d.n2, n3 = a.d.n3;
   const long long N = a.d.N;
@@ -691,15 +698,21 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
     // the force this plane's transforms subtract (eigenstress, or the FP64
     // residual of a refinement cycle), fetched now so that its latency
     // overlaps the step instead of stalling the transforms
-    T fsv[E][2];
+    T fsv[ROUNDS][E][2];
     if constexpr (FS && !FIRST) {
-      if (tid < NPEN * TPC) {
-        const int pid = tid / TPC, t = tid % TPC;
-        const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
-        const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;  // groups past n2 work on wrapped rows
-        const T *fs = a.fstar + c * N + ((long long)zwrap(z) * n2 + yrow % n2) * N1;
+      int lp, t;
+      bool live;
+      line_of<TPC, NLW>(tid, lp, t, live);
 #pragma unroll
-        for (int e = 0; e < E; ++e) ld2(fs + 2 * (t + TPC * e), fsv[e][0], fsv[e][1]);
+      for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int pid = rd * NLW + lp;
+        if (live && lp < NLW && pid < NPEN) {
+          const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
+          const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;  // groups past n2 work on wrapped rows
+          const T *fs = a.fstar + c * N + ((long long)zwrap(z) * n2 + yrow % n2) * N1;
+#pragma unroll
+          for (int e = 0; e < E; ++e) ld2(fs + 2 * (t + TPC * e), fsv[rd][e][0], fsv[rd][e][1]);
+        }
       }
     }
     // The previous step's last reads of Ux (its exchange) precede a barrier
@@ -828,12 +841,18 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
       }
     }
     __syncthreads();
-    // ---- f of the G x T2 x 3 lines and their forward x transforms, in whole
-    // wavefronts (the threads past the last line skip them: a line's
-    // exchanges are ordered within its wavefront)
+    // ---- f of the G x T2 x 3 lines and their forward x transforms, each
+    // line inside one wavefront (the lanes past the last whole line skip
+    // them: a line's exchanges are ordered within its wavefront), in ROUNDS
+    // rounds of at most NLW lines
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
-    if (tid < NPEN * TPC) {
-      const int pid = tid / TPC, t = tid % TPC;
+    int lp, t;
+    bool live;
+    line_of<TPC, NLW>(tid, lp, t, live);
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int pid = rd * NLW + lp;
+      if (!(live && lp < NLW && pid < NPEN)) continue;
       const int pg = pid / (T2 * 3), m = (pid / 3) % T2, c = pid % 3;
       const int yrow = (tile % ny_blocks) * G * T2 + pg * T2 + m;  // rows past n2 store nothing
       const int lo = ((pg * T2 + m) * 3 + c) * N1;
@@ -844,8 +863,8 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
         const int xx = 2 * (t + TPC * e);
         T f0 = Fv[lo + xx] - Fu[lo + xx], f1 = Fv[lo + xx + 1] - Fu[lo + xx + 1];
         if constexpr (FS) {
-          f0 -= fsv[e][0];
-          f1 -= fsv[e][1];
+          f0 -= fsv[rd][e][0];
+          f1 -= fsv[rd][e][1];
         }
         ff += f0 * f0 + f1 * f1;
         vv[e] = cplx<T>{f0, f1};
@@ -858,7 +877,7 @@ __global__ __launch_bounds__(stencil_wg_of(N1), (stencil_min_waves<T, N1>())) vo
             for (int e = 0; e < E; ++e)
               *reinterpret_cast<float2 *>(dst + 2 * (t + TPC * e)) = float2{(float)-vv[e].x, (float)-vv[e].y};
           }
-          return;
+          continue;
         }
       }
       cplx<T> *scr = Scr + pid * line_scratch<L>();

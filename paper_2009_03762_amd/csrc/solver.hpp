@@ -90,8 +90,12 @@ constexpr int es_of(int L) {
 }
 // Points per thread of the register stencil's x-transforms: four on
 // power-of-two lines (at most 64 threads per line, inside one wavefront),
-// es_of on 3 * 2^a.
-constexpr int esr_of(int L) { return (L % 3 == 0) ? es_of(L) : (L < 4 ? L : 4); }
+// es_of on 3 * 2^a; lengths with a factor 9 pack their lines into
+// wavefronts and may take two rounds of line transforms, so they allow up
+// to 64 threads per line.
+constexpr int esr_of(int L) {
+  return (L % 9 == 0) ? e_mult3(L, 64) : ((L % 3 == 0) ? es_of(L) : (L < 4 ? L : 4));
+}
 #ifndef LSFFT_ST2
 #define LSFFT_ST2 2
 #endif
@@ -99,11 +103,13 @@ constexpr int ST2 = LSFFT_ST2;
 // Node lines owned per y-group of a stencil workgroup: ST2, and one for FP64
 // beyond 256 columns, where two would not fit in LDS.
 template <typename T> constexpr int st2_of(int n1) { return (sizeof(T) == 8 && n1 > 256) ? 1 : ST2; }
-// The register-resident stencil takes n1 = 2^a >= 8 and 3 * 2^a in [12, 384]
-// (256- and 192-thread workgroups); other lengths (4, 6, and those with a
-// factor 9) use the LDS stencil.
+// The register-resident stencil takes n1 = 2^a >= 8, 3 * 2^a in [12, 384]
+// and the lengths with a factor 9 from 18 (see stencil_wg_of for their
+// workgroups); 4 and 6 use the LDS stencil.
 constexpr bool stencil_reg_kernel(int n1) {
-  return lsfft::pow2_len(n1) ? n1 >= 8 : (n1 % 3 == 0 && lsfft::pow2_len(n1 / 3) && n1 >= 12 && n1 <= 384);
+  if (lsfft::pow2_len(n1)) return n1 >= 8;
+  if (n1 % 3 == 0 && lsfft::pow2_len(n1 / 3)) return n1 >= 12 && n1 <= 384;
+  return n1 % 9 == 0 && n1 >= 18;
 }
 // y-groups per register-stencil workgroup
 constexpr int stencil_groups(int n1) {

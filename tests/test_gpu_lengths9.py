@@ -8,9 +8,8 @@ line of the real x transform takes L / E threads (L = n1 / 2), a count that
 need not divide a wavefront: the kernels pack whole lines into each
 wavefront and leave the remaining lanes idle, so these cases check that
 packing (and the ragged last workgroup of lines) as much as the radix-3
-passes.  Where the displacement stencil's LDS does not hold n1 columns
-(n1 >= 432) the default form is the strain form, which the kernel names
-confirm."""
+passes.  The displacement form runs the register stencil on every one of
+these x lengths; the kernel names confirm it."""
 import numpy as np
 import pytest
 
@@ -55,15 +54,6 @@ def _check(out, hist, ref, prec):
         assert err < (1e-10 if f64 else 1e-4), name
 
 
-def _disp_fits(n1, prec):
-    """The LDS stencil's shared memory for n1 columns (two FP64 u planes of
-    T2 + 2 lines, two sigma planes of T2 + 1 lines, the f lines; T2 = 1 in
-    FP64 beyond 256 columns) within its 150000-byte budget."""
-    ts = 4 if prec == "f32" else 8
-    t2 = 1 if (prec == "f64" and n1 > 256) else 2
-    return n1 * (2 * (t2 + 2) * 3 * 8 + (2 * (t2 + 1) * 6 + t2 * 3) * ts) + 256 <= 150000
-
-
 @pytest.mark.parametrize("n", LENGTHS)
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("scheme,prec", [("afb", "f64"), ("afb", "f32"), ("fb", "f64")])
@@ -77,14 +67,10 @@ def test_length9_in_each_axis(L, n, axis, scheme, prec):
     print(f"\n[lengths9] (n1,n2,n3)={shape} {scheme} {prec}: {kern}", flush=True)
     tn = "float" if prec == "f32" else "double"
     names = kern.split()
-    if _disp_fits(shape[0], prec):
-        assert names[0].split("<")[0] in ("k_stencil", "k_stencil_reg")
-        assert names[0].startswith(f"{names[0].split('<')[0]}<{tn},{shape[0]},")
-        assert names[2].startswith(f"k_zpass_u<{tn},{shape[2]},")
-    else:
-        assert names[0].startswith(f"k_xpass<{tn},{shape[0] // 2},")
-        assert names[2].startswith(f"k_zpass<{tn},{shape[2]},")
+    stencil = "k_stencil" if shape[0] < 8 else "k_stencil_reg"
+    assert names[0].startswith(f"{stencil}<{tn},{shape[0]},")
     assert names[1].startswith(f"k_ypass<{tn},{shape[1]},")
+    assert names[2].startswith(f"k_zpass_u<{tn},{shape[2]},")
     out = s.solve(EB, tol=0.0, maxit=K)
     hist = s.residual_history()
     s.close()
@@ -92,20 +78,23 @@ def test_length9_in_each_axis(L, n, axis, scheme, prec):
     _check(out, hist, ref, prec)
 
 
-@pytest.mark.parametrize("n1", [36, 486])
-def test_displacement_form_where_it_fits(L, n1):
-    """Forcing the displacement form: accepted where its stencil fits (36
-    columns), EINVAL where it does not (486 columns in FP32)."""
+@pytest.mark.parametrize("n1,prec", [(18, "f32"), (162, "f32"), (486, "f32"), (486, "f64")])
+def test_register_stencil_rounds(L, n1, prec):
+    """Workgroups that are not whole wavefronts (162 threads), two rounds of
+    line transforms per plane (18 columns: 14 y-groups, 84 lines of 3
+    threads; 162 columns: lines of 27 threads, two to a wavefront) and the
+    widest rows (486): the register stencil against the oracle."""
     shape = (n1, 6, 4)
-    lam, mu, l0, m0 = _cell(shape, seed=n1)
-    if _disp_fits(n1, "f32"):
-        s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement")
-        assert s.describe().split()[0].startswith(f"k_stencil<float,{n1},")
-        s.close()
-    else:
-        with pytest.raises(L.LsfftError) as e:
-            L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement")
-        assert e.value.status == L.EINVAL
+    lam, mu, l0, m0 = _cell(shape, seed=n1 + 1)
+    s = L.Solver(lam, mu, l0, m0, scheme="afb", prec=prec, form="displacement")
+    tn = "float" if prec == "f32" else "double"
+    print(f"\n[lengths9 rounds] {shape} {prec}: {s.describe()}", flush=True)
+    assert s.describe().split()[0].startswith(f"k_stencil_reg<{tn},{n1},")
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme="AFB", tol=0.0, maxit=K)
+    _check(out, hist, ref, prec)
 
 
 @pytest.mark.parametrize("scheme", ["basic", "cd", "acd", "afb"])
