@@ -147,11 +147,15 @@ def test_converged_fp64_length9(L):
     assert rel(out["sig_mean"], ref.sig_mean) < 1e-11
 
 
+@pytest.mark.parametrize("n1", [72, 18, 162])
 @pytest.mark.parametrize("opt", ["warm", "refine"])
-def test_f32_options_length9(L, opt):
-    """FP64 warm start and FP64 refinement on an x length with a factor 9."""
-    shape = (72, 12, 18)
-    lam, mu, l0, m0 = _cell(shape, seed=72)
+def test_f32_options_length9(L, opt, n1):
+    """FP64 warm start and FP64 refinement on x lengths with a factor 9 (at
+    18 and 162 columns the register stencils, the refinement's prescribed-
+    force instantiation and its FP64 real-space evaluation included, run
+    their line transforms in two rounds)."""
+    shape = (n1, 12, 18)
+    lam, mu, l0, m0 = _cell(shape, seed=n1)
     kw = {"f64_warmup": 3} if opt == "warm" else {"refine": 4}
     s = L.Solver(lam, mu, l0, m0, scheme="afb", prec="f32", form="displacement", **kw)
     print(f"\n[lengths9 {opt}] {shape}: {s.describe()}", flush=True)
@@ -241,3 +245,19 @@ def test_batch_and_group_length9(L):
         for b in range(2):
             ref = solve3d.solve_gfp(lam, mu, loads[b], l0, m0, scheme="AFB", tol=0.0, maxit=K)
             assert rel(e[b], ref.eps) < 1e-12
+
+
+@pytest.mark.parametrize("n1,scheme,prec", [(18, "afb", "f32"), (54, "afb", "f64"), (162, "fb", "f64")])
+def test_eigenstrain_length9(L, n1, scheme, prec):
+    """An eigenstrain (Sec. 7) through the register stencil's prescribed-force
+    instantiation where its line transforms take two rounds per plane."""
+    shape = (n1, 6, 4)
+    lam, mu, l0, m0 = _cell(shape, seed=n1 + 2)
+    es = 1e-3 * np.random.default_rng(n1).standard_normal((6,) + lam.shape)
+    s = L.Solver(lam, mu, l0, m0, scheme=scheme, prec=prec, form="displacement", eigenstrain=es)
+    print(f"\n[lengths9 eig] {shape} {scheme} {prec}: {s.describe()}", flush=True)
+    out = s.solve(EB, tol=0.0, maxit=K)
+    hist = s.residual_history()
+    s.close()
+    ref = solve3d.solve_gfp(lam, mu, EB, l0, m0, scheme=NAMES[scheme], tol=0.0, maxit=K, eigenstrain=es)
+    _check(out, hist, ref, prec)
