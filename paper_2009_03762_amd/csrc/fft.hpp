@@ -233,11 +233,15 @@ __device__ __forceinline__ const cplx<T> *stage_twiddles(cplx<T> (&dst)[NT], con
 // wavefront, so that no line straddles two (the line transforms exchange at
 // wavefront scope).  When TPC divides 64 every lane works and line p of a
 // workgroup is threads [p TPC, (p + 1) TPC); otherwise the lanes past the
-// last whole line of a wavefront idle.
+// last whole line of a wavefront idle.  lines_per_wg and line_slots count
+// whole wavefronts (wg a multiple of 64); a workgroup with a partial last
+// wavefront counts its lines itself.
 constexpr int lines_per_wg(int tpc, int wg) { return (wg / 64) * (64 / tpc); }
 // Line p (of NL per workgroup) and point index t of thread tid; `live` is
 // false on idle lanes, which are given the dummy line NL + wavefront (their
-// own scratch, nothing loaded or stored) and t < TPC.
+// own scratch, nothing loaded or stored) and t < TPC.  In a partial last
+// wavefront a line whose lanes were not all launched gets p >= NL too, when
+// NL counts only the whole lines.
 template <int TPC, int NL>
 __device__ __forceinline__ void line_of(int tid, int &p, int &t, bool &live) {
   static_assert(TPC >= 1 && TPC <= 64, "a line must fit in one wavefront");
