@@ -409,7 +409,7 @@ typedef enum {
 } lsfft_scheme_1d;
 
 typedef struct {
-  int32_t n;                /* samples per bar: 2^a or 3*2^a, 4..512         */
+  int32_t n;                /* samples per bar: even 2^a*3^b, 4..512         */
   double h;                 /* spacing; 0 means 1.0                          */
   int32_t scheme;           /* lsfft_scheme_1d                               */
   int32_t disc;             /* lsfft_disc (DGO: PCD)                          */

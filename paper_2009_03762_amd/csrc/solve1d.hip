@@ -310,9 +310,12 @@ using lsfft_host::cis_exact;
     }                                                                                     \
   } while (0)
 
-// Points per thread: the y-pass choice (radix-8 passes, 12 for lengths with
-// a factor 3).
-constexpr int bar_e(int n) { return (n % 3 == 0) ? (n < 12 ? n : 12) : (n < 8 ? n : 8); }
+// Points per thread: the y-pass choice (radix-8 passes; 12 for lengths with
+// a factor 3 where it divides, else the smallest multiple of 6 that does
+// and keeps a bar within 64 threads).
+constexpr int bar_e(int n) {
+  return (n % 3 == 0) ? (n < 12 ? n : (n % 12 == 0 ? 12 : lsfft_host::e_mult3(n, 64))) : (n < 8 ? n : 8);
+}
 
 template <typename T>
 hipError_t launch_bars(int n, int count, const lsfft::Bar1dArgs<T> &a, hipStream_t st) {
@@ -321,7 +324,7 @@ hipError_t launch_bars(int n, int count, const lsfft::Bar1dArgs<T> &a, hipStream
   case Nv:                                                                                           \
     hipLaunchKernelGGL((lsfft::k_bar_1d<T, Nv, bar_e(Nv)>), dim3(count), dim3(Nv / bar_e(Nv)), 0, st, a); \
     return hipGetLastError();
-    LSFFT_BAR_LENGTHS(BCASE)
+    LSFFT_YZ_LENGTHS(BCASE)
 #undef BCASE
     default:
       return hipErrorInvalidValue;
@@ -555,7 +558,7 @@ extern "C" lsfft_status lsfft_solve_1d_noalloc(const lsfft_config_1d *cfg, int32
             lsfft::NOALLOC_MAX_N);
     return LSFFT_EINVAL;
   }
-  if (!lsfft_host::supported_len_1d(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
+  if (!lsfft_host::supported_len(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
   if (cfg->scheme < LSFFT_1D_F || cfg->scheme > LSFFT_1D_DGO) return LSFFT_EINVAL;
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F32 && cfg->prec != LSFFT_F64) return LSFFT_EINVAL;
@@ -574,7 +577,7 @@ extern "C" lsfft_status lsfft_solve_1d(const lsfft_config_1d *cfg, int32_t count
                                        const double *Ebar, double tol, int32_t maxit, double *E_out, double *S_out,
                                        int32_t *iters, double *residual, int32_t *status) {
   if (!cfg || !C || !CH || !Ebar || count < 1 || count > 65535) return LSFFT_EINVAL;
-  if (!lsfft_host::supported_len_1d(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
+  if (!lsfft_host::supported_len(cfg->n) || !(cfg->h >= 0.0) || !std::isfinite(cfg->h)) return LSFFT_EINVAL;
   if (cfg->scheme < LSFFT_1D_F || cfg->scheme > LSFFT_1D_DGO) return LSFFT_EINVAL;
   if (cfg->disc != LSFFT_TD && cfg->disc != LSFFT_PCD) return LSFFT_EINVAL;
   if (cfg->prec != LSFFT_F32 && cfg->prec != LSFFT_F64) return LSFFT_EINVAL;

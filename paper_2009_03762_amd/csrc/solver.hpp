@@ -136,10 +136,7 @@ template <typename T> constexpr bool stencil_fits(int n1) { return stencil_lds<T
 #ifdef LSFFT_QUICK_BUILD
 #define LSFFT_YZ_LENGTHS(X) X(8) X(16) X(64) X(256)
 #define LSFFT_X_LENGTHS(X) X(4) X(8) X(32) X(128)
-#define LSFFT_BAR_LENGTHS(X) X(8) X(16) X(64) X(256)
 #else
-// bar lengths of the 1D solver: 2^a and 3 * 2^a
-#define LSFFT_BAR_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 #define LSFFT_YZ_LENGTHS(X)                                                                                  \
   X(4) X(6) X(8) X(12) X(16) X(18) X(24) X(32) X(36) X(48) X(54) X(64) X(72) X(96) X(108) X(128) X(144) X(162) \
   X(192) X(216) X(256) X(288) X(324) X(384) X(432) X(486) X(512)
@@ -237,20 +234,14 @@ struct lsfft_solver_s {
 namespace lsfft_host {
 
 // The transform lengths the kernels are instantiated for: 2^a or 3 * 2^a.
-// Grid lengths of the 3D solver: even 2^a 3^b in [4, 512].
+// Grid lengths of the 3D solver and bar lengths of the 1D solver: even
+// 2^a 3^b in [4, 512].
 inline bool supported_len(int n) {
   if (n < 4 || n > 512 || (n & 1)) return false;
   int m = n;
   while (m % 2 == 0) m /= 2;
   while (m % 3 == 0) m /= 3;
   return m == 1;
-}
-// Bar lengths of the 1D solver: 2^a or 3 * 2^a in [4, 512].
-inline bool supported_len_1d(int n) {
-  if (n < 4 || n > 512 || (n & 1)) return false;
-  int m = n;
-  while (m % 2 == 0) m /= 2;
-  return m == 1 || m == 3;
 }
 
 // ------------------------------------------------------------------ tables

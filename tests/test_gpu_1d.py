@@ -47,7 +47,7 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("scheme", ["f", "fd", "cd", "fd_hc"])
 @pytest.mark.parametrize("disc", ["td", "pcd"])
-@pytest.mark.parametrize("n", [4, 12, 64, 96, 512])
+@pytest.mark.parametrize("n", [4, 12, 18, 64, 96, 162, 486, 512])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_gfp_fixed_iterations_match_oracle(L, scheme, disc, n, prec):
     print(f"\n[1d gfp] {scheme} {disc} n={n} {prec}", flush=True)
@@ -92,7 +92,7 @@ def test_gfp_converged_matches_oracle_and_analytic(L, scheme, disc):
 
 
 @pytest.mark.parametrize("p", [1, 2])
-@pytest.mark.parametrize("n", [8, 24, 256])
+@pytest.mark.parametrize("n", [8, 24, 54, 256])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_dgo_matches_oracle(L, p, n, prec):
     print(f"\n[1d dgo] p={p} n={n} {prec}", flush=True)
