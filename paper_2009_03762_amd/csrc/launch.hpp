@@ -1,9 +1,21 @@
 // Definitions of the pass-kernel launches, instantiated once per precision
 // by launch_f32.hip and launch_f64.hip.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include <cstdio>
 
 #include "solver.hpp"
+
+// A pass launch on the solver's stream; while the solver times this pass
+// (s->tstart set), the launch itself records the start and stop events.
+#define LSFFT_LAUNCH(kernel, grid, block, s, a)                                                          \
+  do {                                                                                                   \
+    if ((s)->tstart)                                                                                     \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, (s)->stream, (s)->tstart, (s)->tstop, 0, a);         \
+    else                                                                                                 \
+      hipLaunchKernelGGL(kernel, grid, block, 0, (s)->stream, a);                                        \
+  } while (0)
 
 namespace lsfft_host {
 
@@ -13,11 +25,9 @@ hipError_t Launch<T>::xpass(lsfft_solver s, const lsfft::XArgs<T> &a, int grid) 
 #define XCASE(Lv)                                                                                        \
 case Lv:                                                                                               \
   if (a.sstar)                                                                                           \
-    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, true>), dim3(grid, s->launch_b), dim3(XWG), 0,    \
-                       s->stream, a);                                                                    \
+    LSFFT_LAUNCH((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, true>), dim3(grid, s->launch_b), dim3(XWG), s, a);                                                                    \
   else                                                                                                   \
-    hipLaunchKernelGGL((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, false>), dim3(grid, s->launch_b), dim3(XWG), 0,   \
-                       s->stream, a);                                                                    \
+    LSFFT_LAUNCH((lsfft::k_xpass<T, Lv, ex_of(Lv), XWG, false>), dim3(grid, s->launch_b), dim3(XWG), s, a);                                                                    \
   return hipGetLastError();
     LSFFT_X_LENGTHS(XCASE)
 #undef XCASE
@@ -33,11 +43,9 @@ hipError_t Launch<T>::ypass(lsfft_solver s, const lsfft::YArgs<T> &a, int grid) 
 case Nv: {                                                                                           \
   constexpr int E = ey_of(Nv), P0 = pcols<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                        \
   if (s->yv)                                                                                         \
-    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P1, FWD>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, \
-                       s->stream, a);                                                                \
+    LSFFT_LAUNCH((lsfft::k_ypass<T, Nv, E, P1, FWD>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), s, a);                                                                \
   else                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_ypass<T, Nv, E, P0, FWD>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, \
-                       s->stream, a);                                                                \
+    LSFFT_LAUNCH((lsfft::k_ypass<T, Nv, E, P0, FWD>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), s, a);                                                                \
   return hipGetLastError();                                                                          \
 }
     LSFFT_YZ_LENGTHS(YCASE)
@@ -54,17 +62,15 @@ hipError_t Launch<T>::zpass(lsfft_solver s, const lsfft::ZArgs<T> &a, int grid) 
 case Nv: {                                                                                           \
   constexpr int E = ez_of(Nv), P0 = pcols_z<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                      \
   if (s->scheme == LSFFT_AFB && s->zv)                                                               \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),           \
-                       dim3(P1 * (Nv / E)), 0, s->stream, a);                                        \
+    LSFFT_LAUNCH((lsfft::k_zpass<T, Nv, E, P1, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),                 \
+                 dim3(P1 * (Nv / E)), s, a);                                                         \
   else if (s->scheme == LSFFT_AFB)                                                                   \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),           \
-                       dim3(P0 * (Nv / E)), 0, s->stream, a);                                        \
+    LSFFT_LAUNCH((lsfft::k_zpass<T, Nv, E, P0, lsfft::SCHEME_AFB>), dim3(grid, s->launch_b),                 \
+                 dim3(P0 * (Nv / E)), s, a);                                                         \
   else if (s->zv)                                                                                    \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P1, -1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, s->stream, \
-                       a);                                                                           \
+    LSFFT_LAUNCH((lsfft::k_zpass<T, Nv, E, P1, -1>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), s, a);                                                                           \
   else                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_zpass<T, Nv, E, P0, -1>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, s->stream, \
-                       a);                                                                           \
+    LSFFT_LAUNCH((lsfft::k_zpass<T, Nv, E, P0, -1>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), s, a);                                                                           \
   return hipGetLastError();                                                                          \
 }
     LSFFT_YZ_LENGTHS(ZCASE)
@@ -79,7 +85,7 @@ hipError_t Launch<T>::uxpass(lsfft_solver s, const lsfft::UArgs<T> &a, int grid)
   switch (s->d.L) {
 #define UCASE(Lv)                                                                                         \
 case Lv:                                                                                                \
-  hipLaunchKernelGGL((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), 0, s->stream, a); \
+  LSFFT_LAUNCH((lsfft::k_uxpass<T, Lv, ex_of(Lv), XWG>), dim3(grid, s->launch_b), dim3(XWG), s, a); \
   return hipGetLastError();
     LSFFT_X_LENGTHS(UCASE)
 #undef UCASE
@@ -95,16 +101,15 @@ hipError_t Launch<T>::stencil_s(lsfft_solver s, const lsfft::SArgs<T> &a, int gr
 case 2 * Lv:                                                                                         \
   if constexpr (stencil_fits<T>(2 * Lv) && stencil_reg_kernel(2 * Lv)) {                            \
     if (a.fstar)                                                                                     \
-      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), true>),               \
-                         dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), 0, s->stream, a);           \
+      LSFFT_LAUNCH((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), true>),                     \
+                   dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), s, a);                                \
     else                                                                                             \
-      hipLaunchKernelGGL((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), false>),              \
-                         dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), 0, s->stream, a);           \
+      LSFFT_LAUNCH((lsfft::k_stencil_reg<T, 2 * Lv, esr_of(Lv), SCH, st2_of<T>(2 * Lv), false>),                    \
+                   dim3(grid, s->launch_b), dim3(lsfft::stencil_wg_of(2 * Lv)), s, a);                                \
     return hipGetLastError();                                                                        \
   } else if constexpr (stencil_fits<T>(2 * Lv)) {                                                    \
-    hipLaunchKernelGGL((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, st2_of<T>(2 * Lv)>), dim3(grid, s->launch_b), \
-                       dim3(256), 0,                                                                            \
-                       s->stream, a);                                                                \
+    LSFFT_LAUNCH((lsfft::k_stencil<T, 2 * Lv, es_of(Lv), SCH, st2_of<T>(2 * Lv)>), dim3(grid, s->launch_b),       \
+                 dim3(256), s, a);                                                                                    \
     return hipGetLastError();                                                                        \
   } else {                                                                                           \
     return hipErrorInvalidValue;                                                                     \
@@ -128,11 +133,9 @@ hipError_t Launch<T>::zpass_u_s(lsfft_solver s, const lsfft::ZArgs<T> &a, int gr
 case Nv: {                                                                                           \
   constexpr int E = ezu_of<T>(Nv), P0 = pcols_zu<T>(Nv, E), P1 = palt<T>(Nv, E, P0);                    \
   if (s->zv)                                                                                         \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P1, SCH>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), 0, \
-                       s->stream, a);                                                                \
+    LSFFT_LAUNCH((lsfft::k_zpass_u<T, Nv, E, P1, SCH>), dim3(grid, s->launch_b), dim3(P1 * (Nv / E)), s, a);                                                                \
   else                                                                                               \
-    hipLaunchKernelGGL((lsfft::k_zpass_u<T, Nv, E, P0, SCH>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), 0, \
-                       s->stream, a);                                                                \
+    LSFFT_LAUNCH((lsfft::k_zpass_u<T, Nv, E, P0, SCH>), dim3(grid, s->launch_b), dim3(P0 * (Nv / E)), s, a);                                                                \
   return hipGetLastError();                                                                          \
 }
     LSFFT_YZ_LENGTHS(ZUCASE)

@@ -96,20 +96,34 @@ hipEvent_t next_event(lsfft_solver s) {
   return s->ev[s->ev_used++];
 }
 
+// Times the launches of pass `id` in its scope.  The single-kernel passes
+// (ids 0-4, launched through LSFFT_LAUNCH) record the start and stop events
+// in the launch itself; the strain form's two-kernel reduction (id 5)
+// records them around its launches.
 struct Timed {
   lsfft_solver s;
-  bool on;
-  Timed(lsfft_solver s_, int id) : s(s_), on(s_->timing_kernel == id) {
-    if (on) {
-      hipEvent_t e = next_event(s);
-      if (e) (void)hipEventRecord(e, s->stream);
-      else on = false;
+  bool on, in_launch;
+  Timed(lsfft_solver s_, int id) : s(s_), on(s_->timing_kernel == id), in_launch(id <= 4) {
+    if (!on) return;
+    hipEvent_t a = next_event(s);
+    hipEvent_t b = a ? next_event(s) : nullptr;
+    if (!b) {
+      on = false;
+      return;
+    }
+    if (in_launch) {
+      s->tstart = a;
+      s->tstop = b;
+    } else {
+      (void)hipEventRecord(a, s->stream);
     }
   }
   ~Timed() {
-    if (on) {
-      hipEvent_t e = next_event(s);
-      if (e) (void)hipEventRecord(e, s->stream);
+    if (!on) return;
+    if (in_launch) {
+      s->tstart = s->tstop = nullptr;
+    } else {
+      (void)hipEventRecord(s->ev[s->ev_used - 1], s->stream);
     }
   }
 };

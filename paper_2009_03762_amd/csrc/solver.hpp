@@ -180,6 +180,10 @@ struct lsfft_solver_s {
   int tabS = 0, off[3] = {0, 0, 0};
   int timing_kernel = -1;
   std::vector<hipEvent_t> ev;
+  // start / stop events of the timed kernel's next launch (null: untimed);
+  // the launch records them itself, so timing adds no packets between
+  // kernels
+  hipEvent_t tstart = nullptr, tstop = nullptr;
   size_t ev_used = 0;
   double timing_mean = 0.0;
   int timing_count = 0;
