@@ -359,7 +359,9 @@ lsfft_status lsfft_stiffness_gradient(lsfft_solver s, const void *eps_a_dev, con
                                       void *dj_dlambda_dev, void *dj_dmu_dev, void *dj_dyoung_dev);
 
 /* Per-kernel event timing for benchmarking.  lsfft_set_timing(s, id) makes
- * every later solve record HIP events around each launch of kernel `id`
+ * every later solve record a pair of HIP events with each launch of kernel `id`
+ * (the launch records them itself; the strain form's two-kernel reduction
+ * records them around its launches)
  * (0 = x-pass, 1 = forward y-pass, 2 = z-pass + Green, 3 = inverse y-pass,
  * 4 = displacement update, 5 = reduction; -1 = off).
  * lsfft_get_timing returns the mean duration in ms and the launch count
