@@ -76,6 +76,20 @@ def test_noalloc_matches_allocating_entry_point(L, scheme, disc, prec):
                            atol=1e-14 if f64 else 1e-6)
 
 
+@pytest.mark.parametrize("n,scheme,disc", [(54, "fd", "pcd"), (162, "cd", "td"), (486, "dgo", "pcd")])
+def test_noalloc_lengths_with_a_factor_9(L, n, scheme, disc):
+    """Bar lengths with a factor 9: the tables the kernel builds into the
+    scratch array against the allocating entry point's (FP64, fixed
+    iterations)."""
+    print(f"\n[noalloc 1d] n={n} {scheme} {disc}", flush=True)
+    kw = dict(scheme=scheme, disc=disc, prec="f64", dgo_images=3, dgo_weight_power=2)
+    C, CH, Eb = _bars(5, n, n)
+    ref = L.solve_1d(C, CH, Eb, tol=0.0, maxit=20, **kw)
+    got = _noalloc(L, C, CH, Eb, tol=0.0, maxit=20, **kw)
+    assert np.array_equal(got["iters"], ref["iters"])
+    assert _rel(got["E"], ref["E"]) < 1e-12 and _rel(got["T"], ref["T"]) < 1e-12
+
+
 def test_noalloc_rejects_bad_bars_and_sizes(L):
     print("\n[noalloc 1d] rejections", flush=True)
     C, CH, Eb = _bars(4, 16, 3)
