@@ -1320,8 +1320,11 @@ lsfft_status autotune(lsfft_solver s, int iterations, lsfft_schedule *best, doub
     return LSFFT_OK;
   };
   if (st == LSFFT_OK && s->disp) {
+    // every even divisor of n3 up to 128: on 3 x 2^a and factor-9 grids the
+    // best march is often one that is not a power of two (the number of
+    // workgroups fills whole rounds of the CUs)
     const int z0 = cur.stencil_planes;
-    for (int z = 2; z <= 128 && st == LSFFT_OK; z *= 2) {
+    for (int z = 2; z <= 128 && st == LSFFT_OK; z += 2) {
       if (z == z0 || s->n[2] % z) continue;
       lsfft_schedule c = cur;
       c.stencil_planes = z;
