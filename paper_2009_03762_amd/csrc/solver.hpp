@@ -65,9 +65,13 @@ template <typename T> constexpr int pcols_z(int n, int E) { return pcols_seg<T>(
 #ifndef LSFFT_ZUE64
 #define LSFFT_ZUE64 LSFFT_ZUE
 #endif
+// Lengths with a factor 3 from 288 take twelve points per thread where
+// twelve divides them (five radix passes instead of seven at 288 and 384:
+// FP64 z-pass at 384^3 966 us against 1143, FP32 288^3 225 against 241);
+// below, six measured as fast or faster.
 template <typename T> constexpr int ezu_of(int n) {
   const int e = sizeof(T) == 8 ? LSFFT_ZUE64 : LSFFT_ZUE;
-  return (n % 3 == 0) ? (n < 6 ? n : e_mult3(n, 64)) : (n < e ? n : e);
+  return (n % 3 == 0) ? (n < 6 ? n : ((n >= 288 && n % 12 == 0) ? 12 : e_mult3(n, 64))) : (n < e ? n : e);
 }
 template <typename T> constexpr int pcols_zu(int n, int E) {
   return pcols_seg<T>(n, E, LSFFT_ZUSEG * (int)sizeof(T) / 4);
