@@ -330,11 +330,16 @@ template <typename F> lsfft_status ensure_graph(lsfft_solver s, double tol, int 
   }
   hipStream_t user = s->stream;
   s->stream = s->gstream;
+  // captured chunks are never timed (a group solve may capture a handle
+  // whose kernel timing is on)
+  const int timing = s->timing_kernel;
+  s->timing_kernel = -1;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal);
   for (int j = 0; j < GRAPH_CHUNK && e == hipSuccess; ++j) e = iteration(false);
   hipError_t e2 = hipStreamEndCapture(s->gstream, &g);
   s->stream = user;
+  s->timing_kernel = timing;
   if (e != hipSuccess || e2 != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     fprintf(stderr, "lsfft: graph capture failed: %s\n", hipGetErrorString(e != hipSuccess ? e : e2));

@@ -129,3 +129,27 @@ def test_group_rejects_refined_and_repeated_handles(L):
     finally:
         L.destroy(a)
         L.destroy(b)
+
+
+def test_group_with_a_timed_handle(L):
+    """A handle whose kernel timing is on still joins a group solve (its
+    captured chunks are untimed) and gives the same iterates as without."""
+    print("\n[group timed]", flush=True)
+    lam, mu, l0, m0 = _cell(16, 11, log10_E=(0.0, 1.0))
+    loads = [np.array([[1e-3, 0, 0, 0, 0, 0]])] * 2
+    out = []
+    for timed in (False, True):
+        hs = [L.create_batch([(lam, mu, l0, m0)], scheme="afb", prec="f64") for _ in range(2)]
+        try:
+            if timed:
+                L.set_timing(hs[0], 0)
+            devs = [torch.zeros((1, 6, 16, 16, 16), dtype=torch.float64, device="cuda") for _ in range(2)]
+            st, res = L.solve_group(hs, loads, 0.0, 24, eps_devs=devs)
+            torch.cuda.synchronize()
+            assert st == L.ENOTCONV
+            out.append([d.cpu().numpy() for d in devs])
+        finally:
+            for h in hs:
+                L.destroy(h)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
